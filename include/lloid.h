@@ -1,0 +1,187 @@
+/*
+ * lloid.h -- C ABI of the MI355X (gfx950) LLOID filtering library.
+ *
+ * The library runs the filtering stage of the paper's pipeline on one GPU
+ * (Sec. II.A and II.B): whitened strain is down-sampled to the rate of every
+ * time slice, correlated with that slice's orthogonal basis filters,
+ * multiplied by the slice's SVD coefficients (mixing matrix), up-sampled
+ * and summed into one complex SNR series per template, and reduced on the
+ * device to per-window SNR peaks; peaks with |SNR| >= threshold (4 by
+ * default, Fig. 1 caption) are the triggers, and only they (not the SNR
+ * series) come back to the host (Sec. II.B, last paragraph).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns lloid_status: LLOID_OK (0) or a negative error code.
+ *    No C++ exception crosses this boundary.  lloid_last_error() returns a
+ *    description of the last error raised on the calling thread.
+ *  - Ownership: the caller owns every buffer passed in or out.  Inputs are
+ *    copied (or fully consumed) before the call returns; the library owns
+ *    its device state until the matching *_destroy call.
+ *  - Pointers documented as "host or device" may point to host memory or to
+ *    device memory of the context's GPU; the library finds out which.
+ *  - Sample indices are full-rate samples; sample 0 is the first strain
+ *    sample of an lloid_filter call or of a stream.
+ *  - Strain is whitened data (unit variance per full-rate sample in the
+ *    noise, as the filtering stage of Sec. II.A consumes it).  In the FP16
+ *    and BF16 modes it is rounded to the operand type after multiplication
+ *    by lloid_trigger_opts.strain_scale (exact power of two, default 1).
+ *
+ * Definitions (notation of the paper's method, Sec. II.A):
+ *  f0 = full rate.  Template i has two real filters, row 2i (cos, Re z_i)
+ *  and row 2i+1 (sin, Im z_i).  Slice s runs at rate r_s = f0 / D_s (D_s a
+ *  power of two), starts J_s full-rate taps before coalescence (J_s a
+ *  multiple of D_s), has N_s taps at rate r_s and L_s basis filters:
+ *      o_s[l, k] = sum_{m < N_s} basis_s[l, m] x_s[k - J_s / D_s - m]
+ *      y_s       = mixing_s o_s
+ *  where x_s is the strain down-sampled to r_s by the zero-phase half-band
+ *  stage d[k] = sum_{|n| <= 32} g[n] u[2k - n] applied log2(D_s) times,
+ *      g[n] = 1/2 sinc(n/2) I0(10 sqrt(1 - (n/32)^2)) / I0(10),
+ *  and the physical SNR is the up-sample-and-add cascade from the lowest
+ *  rate up, w_k = (slices at rate f0/2^k) + up(w_{k+1}) with
+ *      up(w)[n] = sum_j w[j] 2 g[n - 2j],
+ *  Y = w_0, z_i[n] = Y_{2i}[n] + i Y_{2i+1}[n].  Strain is zero outside the
+ *  data, so outputs near the ends see zero padding on both sides.
+ *  Trigger window w covers samples [floor(w f0 a / b), floor((w+1) f0 a / b))
+ *  for window length a/b seconds; its peak is the lowest sample attaining
+ *  the maximum |z_i| in the window.
+ */
+#ifndef LLOID_H
+#define LLOID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LLOID_OK = 0,
+  LLOID_EINVAL = -1,  /* invalid argument (shape, rate, pointer, option) */
+  LLOID_ENOMEM = -2,  /* device or host allocation failed */
+  LLOID_EAGAIN = -3,  /* stream admission: not enough HBM budget now; the bank is queued */
+  LLOID_ETRUNC = -4,  /* output buffer too small; the required count is returned */
+  LLOID_EDEVICE = -5, /* a HIP runtime call failed */
+  LLOID_EORDER = -6,  /* stream stride does not continue the previous one */
+  LLOID_EDATA = -7    /* non-finite strain sample */
+} lloid_status;
+
+typedef enum { LLOID_F64 = 0, LLOID_F32 = 1, LLOID_F16 = 2, LLOID_BF16 = 3 } lloid_dtype;
+
+typedef struct lloid_ctx lloid_ctx;
+typedef struct lloid_bank lloid_bank;
+typedef struct lloid_stream lloid_stream;
+
+/* One time slice of one SVD bank (Sec. II.A: the templates are split into
+ * time slices, each with its own sample rate, and each slice is decomposed
+ * by an SVD into orthogonal basis filters and SVD coefficients). */
+typedef struct {
+  int32_t rate_hz;       /* r_s; f0 / r_s is a power of two */
+  int32_t n_taps;        /* N_s >= 1, taps at rate r_s */
+  int64_t start_tap;     /* J_s >= 0, full-rate taps before coalescence, multiple of f0 / r_s */
+  int32_t n_basis;       /* L_s, 1 <= L_s <= N_s */
+  int32_t reserved;
+  const double *basis;   /* host, [L_s][N_s] row-major; tap m sits J_s + m f0/r_s samples before coalescence */
+  const double *mixing;  /* host, [2 n_templates][L_s] row-major; row 2i = cos (Re z_i), 2i+1 = sin (Im z_i) */
+} lloid_slice;
+
+typedef struct {
+  int32_t full_rate_hz;  /* f0 */
+  int32_t n_templates;   /* F >= 1 */
+  int32_t n_slices;      /* S >= 1; every slice rate distinct from the others is not required */
+  lloid_dtype compute;   /* operand type of both GEMMs: LLOID_F32, LLOID_F16 or LLOID_BF16;
+                            accumulation is always FP32 */
+  const lloid_slice *slices;
+} lloid_bank_desc;
+
+/* A trigger: the SNR peak of one template in one window with |z| >= threshold. */
+typedef struct {
+  int32_t bank;          /* bank index in a batched call / stream slot; 0 for lloid_filter */
+  int32_t detector;      /* as passed by the caller */
+  int32_t template_id;   /* i */
+  int32_t reserved;
+  int64_t window;        /* w */
+  int64_t sample;        /* peak sample n* */
+  float snr;             /* |z_i[n*]| */
+  float phase;           /* atan2(Im z_i[n*], Re z_i[n*]) in (-pi, pi] */
+} lloid_trigger;
+
+typedef struct {
+  int64_t window_num;    /* window length = window_num / window_den seconds, e.g. 1/10 */
+  int64_t window_den;
+  float threshold;       /* inclusive; 4.0 when the options pointer is NULL */
+  float strain_scale;    /* power of two applied before rounding strain to FP16/BF16; 0 means 1 */
+} lloid_trigger_opts;
+
+/* Optional dense outputs of lloid_filter: the peak of every (template, window). */
+typedef struct {
+  float *snr;            /* [n_templates][n_windows], host or device, or NULL */
+  int64_t *sample;       /* [n_templates][n_windows], host or device, or NULL */
+  float *phase;          /* [n_templates][n_windows], host or device, or NULL */
+  int64_t n_windows;     /* in: capacity per template; out: windows covering [0, n) */
+} lloid_peaks;
+
+/* Human-readable description of the last error on the calling thread. */
+const char *lloid_last_error(void);
+
+/* Library version string. */
+const char *lloid_version(void);
+
+/* Create a context on HIP device `device`.  `hip_stream` is the hipStream_t
+ * every call of this context enqueues on (for example the caller's current
+ * stream); NULL creates a private stream.  EDEVICE if the device is absent. */
+lloid_status lloid_ctx_create(int device, void *hip_stream, lloid_ctx **out);
+lloid_status lloid_ctx_destroy(lloid_ctx *ctx);
+
+/* Upload one SVD bank (Sec. II.A "SVD bank").  Validates every slice (EINVAL
+ * on a rate that is not f0 / 2^k, a start tap that is not a multiple of
+ * f0 / r_s, L_s > N_s, a NULL array), scales each slice's basis and the
+ * mixing matrices by exact powers of two, converts them to the compute
+ * type, lays them out for the kernels and computes sigma^2 in FP64.  The
+ * descriptor and its arrays are not referenced after the call returns. */
+lloid_status lloid_bank_create(lloid_ctx *ctx, const lloid_bank_desc *desc, lloid_bank **out);
+
+/* sigma2[i] = sum_s (1/D_s) sum_l (mixing_s[2i][l]^2 + mixing_s[2i+1][l]^2), the
+ * squared full-rate norm of template i as the bank reconstructs it (cos plus
+ * sin; equal to the expected |z_i|^2 in unit white noise), computed in FP64
+ * on the device.  out: host, [n_templates]. */
+lloid_status lloid_bank_sigma2(const lloid_bank *bank, double *out);
+
+/* Shape of an uploaded bank. */
+typedef struct {
+  int32_t full_rate_hz;
+  int32_t n_templates;
+  int32_t n_slices;
+  int32_t n_levels;      /* 1 + log2(f0 / lowest slice rate) */
+  lloid_dtype compute;
+  int32_t concat_k;      /* columns of the concatenated basis operand (sum of padded L_s) */
+  int64_t device_bytes;  /* device memory held by the bank's arrays (not the workspace) */
+} lloid_bank_info;
+
+lloid_status lloid_bank_query(const lloid_bank *bank, lloid_bank_info *out);
+lloid_status lloid_bank_destroy(lloid_bank *bank);
+
+/* Filter one block of strain (offline mode: zero strain before sample 0 and
+ * after sample n-1) and reduce it to triggers.
+ *   strain: host or device, n samples of `strain_dtype` (F64 or F32).
+ *   opts:   window and threshold; NULL means 1 s windows and threshold 4.
+ *   trig:   host, capacity trig_cap; *n_trig receives the number of
+ *           triggers.  If it exceeds trig_cap the first trig_cap (in
+ *           template-major, window-minor order) are written and ETRUNC is
+ *           returned with *n_trig = the required count.
+ *   snr:    NULL, or host or device [n_templates][n][2] float receiving the
+ *           complex SNR (Re, Im) of every template at every sample.
+ *   peaks:  NULL, or dense per-(template, window) peak outputs.
+ * Triggers are ordered by template, then window.  EDATA if a strain sample is
+ * not finite.  Blocks until the results are in the caller's buffers. */
+lloid_status lloid_filter(lloid_bank *bank, int32_t detector,
+                          const void *strain, lloid_dtype strain_dtype, int64_t n,
+                          const lloid_trigger_opts *opts,
+                          lloid_trigger *trig, int64_t trig_cap, int64_t *n_trig,
+                          float *snr, lloid_peaks *peaks);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LLOID_H */

@@ -1,0 +1,241 @@
+"""Python binding of the C ABI in include/lloid.h (argument marshalling only).
+
+Every function here has the name of the C entry point it wraps; all
+filtering work runs in the HIP library liblloid.so built for gfx950.  The
+library must be built first (``python -m paper_2410_16416_amd.build``);
+importing this module without it raises, there is no fallback path.
+Device buffers may be given as torch tensors (their data_ptr is passed).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblloid.so")
+
+LLOID_OK, LLOID_EINVAL, LLOID_ENOMEM, LLOID_EAGAIN = 0, -1, -2, -3
+LLOID_ETRUNC, LLOID_EDEVICE, LLOID_EORDER, LLOID_EDATA = -4, -5, -6, -7
+LLOID_F64, LLOID_F32, LLOID_F16, LLOID_BF16 = 0, 1, 2, 3
+DTYPES = {"f64": LLOID_F64, "f32": LLOID_F32, "f16": LLOID_F16, "bf16": LLOID_BF16}
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EAGAIN", -4: "ETRUNC",
+                -5: "EDEVICE", -6: "EORDER", -7: "EDATA"}
+
+
+class LloidError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class lloid_slice(ctypes.Structure):
+    _fields_ = [("rate_hz", ctypes.c_int32), ("n_taps", ctypes.c_int32),
+                ("start_tap", ctypes.c_int64), ("n_basis", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("basis", ctypes.POINTER(ctypes.c_double)),
+                ("mixing", ctypes.POINTER(ctypes.c_double))]
+
+
+class lloid_bank_desc(ctypes.Structure):
+    _fields_ = [("full_rate_hz", ctypes.c_int32), ("n_templates", ctypes.c_int32),
+                ("n_slices", ctypes.c_int32), ("compute", ctypes.c_int32),
+                ("slices", ctypes.POINTER(lloid_slice))]
+
+
+class lloid_bank_info(ctypes.Structure):
+    _fields_ = [("full_rate_hz", ctypes.c_int32), ("n_templates", ctypes.c_int32),
+                ("n_slices", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("compute", ctypes.c_int32), ("concat_k", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class lloid_trigger_opts(ctypes.Structure):
+    _fields_ = [("window_num", ctypes.c_int64), ("window_den", ctypes.c_int64),
+                ("threshold", ctypes.c_float), ("strain_scale", ctypes.c_float)]
+
+
+class lloid_peaks(ctypes.Structure):
+    _fields_ = [("snr", ctypes.c_void_p), ("sample", ctypes.c_void_p),
+                ("phase", ctypes.c_void_p), ("n_windows", ctypes.c_int64)]
+
+
+TRIGGER_DTYPE = np.dtype([("bank", np.int32), ("detector", np.int32), ("template_id", np.int32),
+                          ("reserved", np.int32), ("window", np.int64), ("sample", np.int64),
+                          ("snr", np.float32), ("phase", np.float32)])
+assert TRIGGER_DTYPE.itemsize == 40
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_16416_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "lloid_last_error": ([], ctypes.c_char_p),
+        "lloid_version": ([], ctypes.c_char_p),
+        "lloid_ctx_create": ([ctypes.c_int, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "lloid_ctx_destroy": ([vp], ctypes.c_int),
+        "lloid_bank_create": ([vp, ctypes.POINTER(lloid_bank_desc), ctypes.POINTER(vp)], ctypes.c_int),
+        "lloid_bank_sigma2": ([vp, vp], ctypes.c_int),
+        "lloid_bank_query": ([vp, ctypes.POINTER(lloid_bank_info)], ctypes.c_int),
+        "lloid_bank_destroy": ([vp], ctypes.c_int),
+        "lloid_filter": ([vp, i32, vp, ctypes.c_int, i64, ctypes.POINTER(lloid_trigger_opts), vp, i64,
+                          ctypes.POINTER(i64), vp, ctypes.POINTER(lloid_peaks)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status: int):
+    if status != LLOID_OK:
+        raise LloidError(status, _lib.lloid_last_error().decode())
+
+
+def _ptr(a):
+    """Address of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return int(a.data_ptr())
+
+
+def exported_symbols():
+    return ["lloid_last_error", "lloid_version", "lloid_ctx_create", "lloid_ctx_destroy",
+            "lloid_bank_create", "lloid_bank_sigma2", "lloid_bank_query", "lloid_bank_destroy",
+            "lloid_filter"]
+
+
+def lloid_version() -> str:
+    return _lib.lloid_version().decode()
+
+
+def lloid_ctx_create(device: int = 0, stream=None):
+    """stream: a hipStream_t as int (e.g. torch.cuda.current_stream().cuda_stream) or None."""
+    out = ctypes.c_void_p()
+    _check(_lib.lloid_ctx_create(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(out)))
+    return out
+
+
+def lloid_ctx_destroy(ctx):
+    _check(_lib.lloid_ctx_destroy(ctx))
+
+
+def lloid_bank_create(ctx, full_rate_hz: int, n_templates: int, slices, compute: str = "f16"):
+    """slices: objects with rate, start_tap, n_taps, basis [L, N], mixing [2F, L] (float64)."""
+    keep = []
+    arr = (lloid_slice * len(slices))()
+    for k, s in enumerate(slices):
+        b = np.ascontiguousarray(s.basis, dtype=np.float64)
+        m = np.ascontiguousarray(s.mixing, dtype=np.float64)
+        keep += [b, m]
+        arr[k].rate_hz = int(s.rate)
+        arr[k].n_taps = int(s.n_taps)
+        arr[k].start_tap = int(s.start_tap)
+        arr[k].n_basis = int(b.shape[0])
+        arr[k].basis = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        arr[k].mixing = m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    desc = lloid_bank_desc(int(full_rate_hz), int(n_templates), len(slices), DTYPES[compute], arr)
+    out = ctypes.c_void_p()
+    _check(_lib.lloid_bank_create(ctx, ctypes.byref(desc), ctypes.byref(out)))
+    return out
+
+
+def lloid_bank_query(bank) -> lloid_bank_info:
+    info = lloid_bank_info()
+    _check(_lib.lloid_bank_query(bank, ctypes.byref(info)))
+    return info
+
+
+def lloid_bank_sigma2(bank) -> np.ndarray:
+    out = np.empty(lloid_bank_query(bank).n_templates, dtype=np.float64)
+    _check(_lib.lloid_bank_sigma2(bank, out.ctypes.data))
+    return out
+
+
+def lloid_bank_destroy(bank):
+    _check(_lib.lloid_bank_destroy(bank))
+
+
+@dataclass
+class FilterResult:
+    triggers: np.ndarray          # TRIGGER_DTYPE records
+    n_triggers: int
+    peak_snr: np.ndarray | None = None
+    peak_sample: np.ndarray | None = None
+    peak_phase: np.ndarray | None = None
+    snr: object = None
+
+
+def lloid_filter(bank, detector: int, strain, window=(1, 1), threshold: float = 4.0,
+                 strain_scale: float = 0.0, trig_cap: int | None = None, triggers_out=None,
+                 snr_out=None, peaks: bool = False, n_windows: int | None = None) -> FilterResult:
+    """strain: float64/float32 numpy array (host) or torch tensor (host or device).
+
+    triggers_out: optional preallocated host buffer (numpy TRIGGER_DTYPE array or a
+    pinned torch uint8 tensor of 40*cap bytes).  snr_out: optional [F, n, 2] float32
+    numpy array or torch tensor receiving the complex SNR.
+    """
+    if isinstance(strain, np.ndarray):
+        strain = np.ascontiguousarray(strain)
+        dt = LLOID_F64 if strain.dtype == np.float64 else LLOID_F32 if strain.dtype == np.float32 else None
+        n = strain.shape[0]
+    else:
+        import torch
+        dt = {torch.float64: LLOID_F64, torch.float32: LLOID_F32}.get(strain.dtype)
+        n = strain.shape[0]
+    if dt is None:
+        raise LloidError(LLOID_EINVAL, "strain must be float64 or float32")
+    info = lloid_bank_query(bank)
+    n_templates = info.n_templates
+    num, den = window
+    opts = lloid_trigger_opts(int(num), int(den), float(threshold), float(strain_scale))
+    if n_windows is None:
+        n_windows = -(-n * int(den) // (info.full_rate_hz * int(num)))
+    pk = None
+    res = FilterResult(triggers=None, n_triggers=0)
+    if peaks:
+        res.peak_snr = np.empty((n_templates, n_windows), dtype=np.float32)
+        res.peak_sample = np.empty((n_templates, n_windows), dtype=np.int64)
+        res.peak_phase = np.empty((n_templates, n_windows), dtype=np.float32)
+        pk = lloid_peaks(res.peak_snr.ctypes.data, res.peak_sample.ctypes.data, res.peak_phase.ctypes.data,
+                         n_windows)
+    if triggers_out is None:
+        cap = trig_cap if trig_cap is not None else n_templates * max(1, n_windows or 1)
+        triggers_out = np.empty(cap, dtype=TRIGGER_DTYPE)
+    cap = (triggers_out.shape[0] if isinstance(triggers_out, np.ndarray)
+           else triggers_out.numel() // TRIGGER_DTYPE.itemsize)
+    n_trig = ctypes.c_int64()
+    st = _lib.lloid_filter(bank, int(detector), ctypes.c_void_p(_ptr(strain)), dt, int(n), ctypes.byref(opts),
+                           ctypes.c_void_p(_ptr(triggers_out)), int(cap), ctypes.byref(n_trig),
+                           ctypes.c_void_p(_ptr(snr_out)) if snr_out is not None else None,
+                           ctypes.byref(pk) if pk is not None else None)
+    if st == LLOID_ETRUNC and pk is not None and pk.n_windows > n_windows:
+        return lloid_filter(bank, detector, strain, window, threshold, strain_scale, trig_cap,
+                            None, snr_out, peaks, int(pk.n_windows))
+    if st == LLOID_ETRUNC and triggers_out is not None and trig_cap is None and n_trig.value > cap:
+        return lloid_filter(bank, detector, strain, window, threshold, strain_scale,
+                            int(n_trig.value), None, snr_out, peaks, n_windows)
+    _check(st)
+    res.n_triggers = int(n_trig.value)
+    if isinstance(triggers_out, np.ndarray):
+        res.triggers = triggers_out[: res.n_triggers]
+    else:
+        res.triggers = triggers_out
+    res.snr = snr_out
+    return res
+
+
+def bank_from_svd(ctx, svd_bank, compute: str = "f16"):
+    """Upload an SVD bank object (attributes f0, n_templates, slices)."""
+    return lloid_bank_create(ctx, svd_bank.f0, svd_bank.n_templates, svd_bank.slices, compute)

@@ -1,0 +1,247 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Small cases (seconds of oracle time) compare every complex-SNR sample and
+every window peak; the full multi-rate workload (1024 templates, 3 slices,
+2 detectors x 1024 s) runs on the GPU in the benchmark's launch
+configuration and is compared on sampled windows the oracle computes one
+by one.
+"""
+
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import configs
+from workloads.strain import Injection, inject
+
+from gpu_util import EPS_ABS, compare_peaks, compare_series, gpu_complex, log, run_filter, ctx
+
+pytestmark = pytest.mark.gpu
+PRECISIONS = ["f32", "f16", "bf16"]
+
+
+@functools.lru_cache(maxsize=None)
+def c0_case():
+    wl = configs.plain_c0()
+    x = wl.strains[0]
+    z = oracle.lloid_snr(wl.bank, x)
+    wins, pa, ps, ph = oracle.peak_table(z, 0, 1024, 1, 10)
+    return wl, x, z, pa, ps, ph
+
+
+@functools.lru_cache(maxsize=None)
+def mini_case():
+    wl = configs.mini_multirate(seconds=12, n_injections=2)
+    x = wl.strains[0][: 12 * 1024 - 333]          # ragged tail: not a multiple of any tile
+    z = oracle.lloid_snr(wl.bank, x)
+    wins, pa, ps, ph = oracle.peak_table(z, 0, 1024, 1, 4)
+    return wl, x, z, pa, ps, ph
+
+
+@pytest.mark.parametrize("compute", PRECISIONS)
+def test_c0_series_and_peaks(compute):
+    log(f"[c0] compute={compute}")
+    wl, x, z, pa, ps, ph = c0_case()
+    res = run_filter(wl.bank, x, compute, (1, 10), snr=True)
+    zg = gpu_complex(res)
+    s = compare_series(zg, z, compute, f"c0/{compute}")
+    p = compare_peaks(res, np.abs(z), pa, ps, compute, label=f"c0/{compute}")
+    log(f"  series {s} peaks {p}")
+    inj = wl.injections[0]
+    assert res.peak_sample[inj.template, 40] == 4146
+    assert abs(res.peak_snr[inj.template, 40] - pa[inj.template, 40]) <= EPS_ABS[compute]
+    # phase at the peak: compare where the peak sample agrees and |z| is well above the noise
+    ok = (res.peak_sample == ps) & (pa >= 4.0)
+    dphi = np.angle(np.exp(1j * (res.peak_phase[ok] - ph[ok])))
+    assert np.max(np.abs(dphi)) <= 3 * EPS_ABS[compute] / 4.0
+
+
+@pytest.mark.parametrize("compute", PRECISIONS)
+def test_mini_multirate_ragged(compute):
+    """Three slices at 1024/256/64 Hz (levels 0, 2, 4 with empty levels between),
+    a ragged length and 0.25 s windows."""
+    log(f"[mini] compute={compute}")
+    wl, x, z, pa, ps, ph = mini_case()
+    res = run_filter(wl.bank, x, compute, (1, 4), snr=True)
+    s = compare_series(gpu_complex(res), z, compute, f"mini/{compute}")
+    p = compare_peaks(res, np.abs(z), pa, ps, compute, label=f"mini/{compute}")
+    log(f"  series {s} peaks {p}")
+
+
+def test_sigma2_fp64():
+    from paper_2410_16416_amd import lloid
+    for bank in (configs.plain_c0_bank(), configs.mini_multirate_bank()):
+        b = lloid.bank_from_svd(ctx(), bank, "f16")
+        try:
+            s2 = lloid.lloid_bank_sigma2(b)
+        finally:
+            lloid.lloid_bank_destroy(b)
+        assert np.allclose(s2, oracle.sigma2(bank), rtol=1e-13, atol=0)
+
+
+def test_triggers_are_thresholded_peaks_and_truncate():
+    from paper_2410_16416_amd import lloid
+    wl, x, z, pa, ps, ph = c0_case()
+    b = lloid.bank_from_svd(ctx(), wl.bank, "f16")
+    try:
+        res = lloid.lloid_filter(b, 3, x, window=(1, 10), threshold=4.0, peaks=True)
+        want = [(i, w) for i in range(res.peak_snr.shape[0]) for w in range(res.peak_snr.shape[1])
+                if res.peak_snr[i, w] >= 4.0]
+        got = list(zip(res.triggers["template_id"].tolist(), res.triggers["window"].tolist()))
+        assert got == want and res.n_triggers == len(want)
+        t = res.triggers
+        assert np.all(t["detector"] == 3)
+        assert np.array_equal(t["sample"], res.peak_sample[t["template_id"], t["window"]])
+        assert np.array_equal(t["snr"], res.peak_snr[t["template_id"], t["window"]])
+        small = np.empty(5, dtype=lloid.TRIGGER_DTYPE)
+        with pytest.raises(lloid.LloidError) as ei:
+            lloid.lloid_filter(b, 3, x, window=(1, 10), trig_cap=5, triggers_out=small)
+        assert ei.value.status == lloid.LLOID_ETRUNC
+        assert np.array_equal(small, res.triggers[:5])
+        # a higher threshold keeps exactly the peaks above it
+        hi = lloid.lloid_filter(b, 3, x, window=(1, 10), threshold=9.0)
+        assert hi.n_triggers == int((res.peak_snr >= 9.0).sum())
+    finally:
+        lloid.lloid_bank_destroy(b)
+
+
+def test_deterministic_and_device_strain():
+    import torch
+    from paper_2410_16416_amd import lloid
+    wl, x, z, pa, ps, ph = mini_case()
+    b = lloid.bank_from_svd(ctx(), wl.bank, "f16")
+    try:
+        r1 = lloid.lloid_filter(b, 0, x, window=(1, 4), peaks=True)
+        r2 = lloid.lloid_filter(b, 0, x, window=(1, 4), peaks=True)
+        xd = torch.from_numpy(x).to("cuda")
+        torch.cuda.synchronize()
+        r3 = lloid.lloid_filter(b, 0, xd, window=(1, 4), peaks=True)
+        r4 = lloid.lloid_filter(b, 0, x.astype(np.float32), window=(1, 4), peaks=True)
+    finally:
+        lloid.lloid_bank_destroy(b)
+    for r in (r2, r3):
+        assert np.array_equal(r1.peak_snr, r.peak_snr) and np.array_equal(r1.peak_sample, r.peak_sample)
+        assert np.array_equal(r1.triggers, r.triggers)
+    # FP32 strain input rounds x before conversion: equal within FP16 tolerance
+    assert np.max(np.abs(r4.peak_snr - r1.peak_snr)) < EPS_ABS["f16"]
+
+
+def test_edge_cases_short_inputs_and_errors():
+    from paper_2410_16416_amd import lloid
+    wl, x, z, pa, ps, ph = c0_case()
+    b = lloid.bank_from_svd(ctx(), wl.bank, "f32")
+    try:
+        for n in (1, 31, 102, 103, 1000):       # shorter than a tile, a window, the filter
+            xs = x[:n]
+            zo = oracle.lloid_snr(wl.bank, xs)
+            _, pao, pso, _ = oracle.peak_table(zo, 0, 1024, 1, 10)
+            res = lloid.lloid_filter(b, 0, xs, window=(1, 10), peaks=True)
+            assert res.peak_snr.shape == pao.shape
+            compare_peaks(res, np.abs(zo), pao, pso, "f32", label=f"n={n}")
+        bad = x[:500].copy()
+        bad[17] = np.nan
+        with pytest.raises(lloid.LloidError) as ei:
+            lloid.lloid_filter(b, 0, bad, window=(1, 10))
+        assert ei.value.status == lloid.LLOID_EDATA
+        with pytest.raises(lloid.LloidError) as ei:
+            lloid.lloid_filter(b, 0, x[:0], window=(1, 10))
+        assert ei.value.status == lloid.LLOID_EINVAL
+        with pytest.raises(lloid.LloidError) as ei:
+            lloid.lloid_filter(b, 0, x[:100], window=(1, 10), strain_scale=3.0)
+        assert ei.value.status == lloid.LLOID_EINVAL
+    finally:
+        lloid.lloid_bank_destroy(b)
+    sl = wl.bank.slices[0]
+
+    class S:
+        pass
+    for rate, start, nb in ((1000, 0, 8), (512, 1, 8), (1024, 0, 2000)):
+        s = S()
+        s.rate, s.start_tap, s.n_taps = rate, start, sl.n_taps
+        s.basis = np.zeros((nb, sl.n_taps)) if nb <= sl.n_taps else np.zeros((nb, sl.n_taps))
+        s.mixing = np.zeros((128, nb))
+        with pytest.raises(lloid.LloidError) as ei:
+            lloid.lloid_bank_create(ctx(), 1024, 64, [s], "f16")
+        assert ei.value.status == lloid.LLOID_EINVAL
+
+
+# ---------------------------------------------------------------- C1 scale
+
+def c1_small_workload(seconds=36):
+    bank = configs.multirate_c1_bank()
+    wl = configs.multirate_c1(seconds=seconds, detectors=1, n_injections=0, bank=bank)
+    injs = [Injection(template=17, t0=33 * 2048 + 611, snr=12.0, phase=0.7),
+            Injection(template=900, t0=34 * 2048 + 1500, snr=25.0, phase=-2.0)]
+    x = inject(wl.strains[0], bank.family, injs)[: seconds * 2048 - 777]
+    return bank, x, injs
+
+
+@functools.lru_cache(maxsize=None)
+def c1_small_case():
+    bank, x, injs = c1_small_workload()
+    tsel = np.array(sorted({17, 900} | set(range(0, 1024, 37))))
+    z = oracle.lloid_snr(bank, x, templates=tsel)
+    wins, pa, ps, ph = oracle.peak_table(z, 0, 2048, 1, 1)
+    return bank, x, injs, tsel, z, pa, ps
+
+
+@pytest.mark.parametrize("compute", PRECISIONS)
+def test_c1_bank_short_block(compute):
+    """The full 1024-template, three-slice bank on 36 s (every slice's history
+    filled, ragged end), 1 s windows; series and peaks on a template subset."""
+    log(f"[c1-short] compute={compute}")
+    bank, x, injs, tsel, z, pa, ps = c1_small_case()
+    res = run_filter(bank, x, compute, (1, 1), snr=True)
+    zg = gpu_complex(res)[tsel]
+    s = compare_series(zg, z, compute, f"c1short/{compute}")
+    res.peak_snr, res.peak_sample = res.peak_snr[tsel], res.peak_sample[tsel]
+    p = compare_peaks(res, np.abs(z), pa, ps, compute, label=f"c1short/{compute}")
+    log(f"  series {s} peaks {p}")
+    for inj in injs:
+        r = int(np.nonzero(tsel == inj.template)[0][0])
+        w = inj.t0 // 2048
+        assert abs(res.peak_sample[r, w] - inj.t0) <= 2
+        assert res.peak_snr[r, w] > 0.9 * inj.snr
+
+
+@functools.lru_cache(maxsize=None)
+def c1_full_inputs():
+    wl = configs.multirate_c1()
+    return wl
+
+
+@pytest.mark.parametrize("compute", ["f16", "f32"])
+def test_c1_full_size_sampled_windows(compute):
+    """2 detectors x 1024 s at the benchmark's launch configuration; the oracle
+    recomputes all 1024 templates on sampled 1 s windows (injection windows,
+    the first, the last, and random ones)."""
+    from paper_2410_16416_amd import lloid
+    log(f"[c1-full] compute={compute}")
+    wl = c1_full_inputs()
+    bank = wl.bank
+    b = lloid.bank_from_svd(ctx(), bank, compute)
+    rng = np.random.default_rng(11)
+    try:
+        for det, x in enumerate(wl.strains):
+            res = lloid.lloid_filter(b, det, x, window=(1, 1), peaks=True)
+            assert res.peak_snr.shape == (1024, 1024)
+            inj_w = sorted({inj.t0 // 2048 for inj in wl.injections})
+            sample = sorted(set(inj_w[:3]) | {0, 1023} | set(rng.integers(0, 1024, 3).tolist()))
+            for w in sample:
+                z = oracle.lloid_snr(bank, x, w * 2048, (w + 1) * 2048)
+                _, pa, ps, _ = oracle.peak_table(z, w * 2048, 2048, 1, 1)
+
+                class R:
+                    pass
+                r = R()
+                r.peak_snr, r.peak_sample = res.peak_snr[:, [w]], res.peak_sample[:, [w]]
+                compare_peaks(r, np.abs(z), pa, ps, compute, n_lo=w * 2048, label=f"c1full/{compute}/d{det}/w{w}")
+            for inj in wl.injections:
+                w = inj.t0 // 2048
+                assert res.peak_snr[inj.template, w] > 0.85 * inj.snr
+                assert abs(res.peak_sample[inj.template, w] - inj.t0) <= 2
+            log(f"  det {det}: {res.n_triggers} triggers, windows checked {sample}")
+    finally:
+        lloid.lloid_bank_destroy(b)
