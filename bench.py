@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of the LLOID filtering path on one MI355X.
+
+Workload (the multi-rate configuration the metric is quoted on): one SVD
+bank of 1024 synthetic chirp templates (durations 0.5-32 s) in three time
+slices at 2048/512/128 Hz with 200/150/100 basis filters, two detectors of
+1024 s of white Gaussian noise with 20 injections (SNR 6-30), 1 s trigger
+windows, threshold 4.  One step filters both detectors from strain already
+resident in HBM to triggers in pinned host memory, through the C ABI.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--compute f16|bf16|f32]
+
+Prints one JSON line: whole-job template-samples of SNR per second, the
+roofline of the dominant kernel (device time from HIP events on the
+library's stream over the timed steps), the plain FP32 path beside it, and
+the FP64 oracle timed on the host cores on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "template-samples of SNR/sec (1 GPU) at stated SNR error; p99 stride latency"
+PEAK_TFLOPS = {"f16": 2516.6, "bf16": 2516.6, "f32": 157.3}   # dense MFMA, MI355X
+PEAK_HBM_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SRC = os.path.join(ROOT, "paper_2410_16416_amd", "csrc", "lloid_kernels.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stage_work(bank, seconds: float, compute: str):
+    """Algorithmic work per lloid_filter call (one detector), per stage.
+
+    FIR: 2 L_s N_s r_s flops per second of data; mixing: 2 (2F) L_s r_s
+    (the method's order: mix at the slice rate).  Interpolation moves the
+    low-rate orthogonal SNR (FP32 read) to the full-rate operand (write in
+    the operand type)."""
+    esz = 4 if compute == "f32" else 2
+    fir = sum(2.0 * s.n_basis * s.n_taps * s.rate for s in bank.slices) * seconds
+    mix = sum(2.0 * 2 * bank.n_templates * s.n_basis * s.rate for s in bank.slices) * seconds
+    interp = sum((s.n_basis * s.rate * 4 + s.n_basis * bank.f0 * esz)
+                 for s in bank.slices if s.rate != bank.f0) * seconds
+    decim = sum(4.0 * bank.f0 / 2 ** k * 1.5 for k in range(1, 5)) * seconds
+    return {"fir": ("mfma", fir), "mix": ("mfma", mix), "interp": ("hbm", interp), "decimate": ("hbm", decim)}
+
+
+def roofline_entry(kind, work, ms_per_launch, compute, traffic=None):
+    if kind == "mfma":
+        achieved = work / (ms_per_launch / 1e3) / 1e12
+        peak = PEAK_TFLOPS[compute]
+        return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": traffic}
+    achieved = work / (ms_per_launch / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
+
+
+def load_traffic(stage: str, compute: str):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(PROFILES, f"traffic_{stage}_multirate_c1_{compute}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_sha") != kernel_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, sample_s: float):
+    """The FP64 oracle on a bounded sample: detector 0, outputs on
+    [32 s, 32 s + sample_s) with the 32 s of history the longest slice needs."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    f0 = wl.bank.f0
+    lo, hi = 32 * f0, int((32 + sample_s) * f0)
+    x = wl.strains[0][: hi + 4 * f0]
+    t0 = time.perf_counter()
+    z = oracle.lloid_snr(wl.bank, x, lo, hi)
+    _ = oracle.triggers(z, lo, f0, 1, 1, 4.0)
+    wall = time.perf_counter() - t0
+    value = wl.bank.n_templates * (hi - lo) / wall
+    return {"value": round(value, 1), "unit": "template-samples/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"detector 0, outputs on [32 s, {32 + sample_s:g} s) of the same workload (all "
+                      f"{wl.bank.n_templates} templates, 32 s history), FP64 NumPy/SciPy multi-rate form "
+                      f"plus window peaks and triggers; wall {wall:.2f} s on {threads} BLAS threads "
+                      f"({os.cpu_count()} host cores visible)"}
+
+
+def run_path(lloid, ctx, wl, xs, compute, steps, warmup, tbufs):
+    import torch
+    bank = lloid.bank_from_svd(ctx, wl.bank, compute)
+    try:
+        def step():
+            n = 0
+            for det, x in enumerate(xs):
+                r = lloid.lloid_filter(bank, det, x, window=(1, 1), threshold=4.0, triggers_out=tbufs[det])
+                n += r.n_triggers
+            return n
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        lloid.lloid_ctx_profile(ctx, True)
+        lloid.lloid_ctx_stage_times(ctx, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_trig = 0
+        for _ in range(steps):
+            n_trig = step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        stages = lloid.lloid_ctx_stage_times(ctx, reset=True)
+        lloid.lloid_ctx_profile(ctx, False)
+    finally:
+        lloid.lloid_bank_destroy(bank)
+    return wall, n_trig, stages
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--compute", default="f16", choices=["f16", "bf16", "f32"])
+    ap.add_argument("--seconds", type=int, default=1024, help="seconds of strain per detector")
+    ap.add_argument("--f32-steps", type=int, default=3, help="timed steps of the plain FP32 path (0: skip)")
+    ap.add_argument("--cpu-sample-s", type=float, default=24.0, help="oracle sample length (0: skip)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the filtering path runs on a single MI355X "
+              "(multi-GPU sharding by bank is described in DESIGN.md, not run here)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from workloads import configs
+    from paper_2410_16416_amd import lloid
+
+    log(f"[bench] generating workload ({args.seconds} s x 2 detectors)")
+    t0 = time.perf_counter()
+    wl = configs.multirate_c1(seconds=args.seconds)
+    log(f"[bench] workload ready in {time.perf_counter() - t0:.1f} s: {wl.bank.describe()}")
+    torch.cuda.init()
+    ctx = lloid.lloid_ctx_create(0)
+    xs = [torch.from_numpy(x).to("cuda") for x in wl.strains]
+    n_win = -(-wl.n_samples // wl.bank.f0)
+    cap = wl.bank.n_templates * n_win
+    tbufs = [torch.empty(cap * lloid.TRIGGER_DTYPE.itemsize, dtype=torch.uint8, pin_memory=True) for _ in xs]
+    torch.cuda.synchronize()
+
+    F, f0 = wl.bank.n_templates, wl.bank.f0
+    samples_per_step = F * wl.n_samples * len(xs)
+    log(f"[bench] {args.compute}: warmup {args.warmup}, steps {args.steps}")
+    wall, n_trig, stages = run_path(lloid, ctx, wl, xs, args.compute, args.steps, args.warmup, tbufs)
+    ms_step = wall / args.steps * 1e3
+    value = samples_per_step / (wall / args.steps)
+    log(f"[bench] {args.compute}: {ms_step:.2f} ms/step, {value:.4g} template-samples/s, stages {stages}")
+
+    work = stage_work(wl.bank, wl.n_samples / f0, args.compute)
+    roofs = {}
+    for st, (kind, w) in work.items():
+        ms, calls = stages[st]
+        if calls:
+            roofs[st] = roofline_entry(kind, w, ms / calls, args.compute, load_traffic(st, args.compute))
+            roofs[st]["ms_per_launch"] = round(ms / calls, 4)
+    dominant = max(roofs, key=lambda k: roofs[k]["ms_per_launch"])
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "template-samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.compute,
+        "data": "synthetic (seeded white Gaussian noise + chirp injections; closed-form chirp bank)",
+        "config": {"workload": "multirate_c1: 1024 chirp templates (0.5-32 s), slices 2048/512/128 Hz "
+                               "with 200/150/100 basis filters, 2 detectors x 1024 s, 20 injections, "
+                               "1 s windows, threshold 4",
+                   "templates": F, "detectors": len(xs), "seconds": wl.n_samples // f0, "f0": f0,
+                   "compute": args.compute, "accumulate": "f32"},
+        "templates_in_real_time": round(value / f0, 1),
+        "triggers_per_step": int(n_trig),
+        "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
+        "roofline": dict(roofs[dominant], kernel=dominant),
+        "roofline_stages": roofs,
+        "p99_stride_latency_ms": None,
+    }
+    err_path = os.path.join(PROFILES, "precision_multirate_c1.json")
+    if os.path.exists(err_path):
+        with open(err_path) as f:
+            out["stated_snr_error"] = json.load(f).get(args.compute)
+
+    if args.f32_steps and args.compute != "f32":
+        log(f"[bench] plain f32 path: steps {args.f32_steps}")
+        w32, _, st32 = run_path(lloid, ctx, wl, xs, "f32", args.f32_steps, 1, tbufs)
+        v32 = samples_per_step / (w32 / args.f32_steps)
+        ms, calls = st32["mix"]
+        out["f32_path"] = {"value": round(v32, 1), "ms_per_step": round(w32 / args.f32_steps * 1e3, 3),
+                           "speedup_of_headline": round(value / v32, 2),
+                           "roofline_mix": roofline_entry("mfma", work["mix"][1], ms / max(calls, 1), "f32")}
+    if args.cpu_sample_s > 0:
+        log(f"[bench] cpu baseline: oracle on {args.cpu_sample_s:g} s")
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_s)
+    lloid.lloid_ctx_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

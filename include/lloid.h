@@ -133,6 +133,28 @@ const char *lloid_version(void);
 lloid_status lloid_ctx_create(int device, void *hip_stream, lloid_ctx **out);
 lloid_status lloid_ctx_destroy(lloid_ctx *ctx);
 
+/* Stages of the filtering path, for per-stage device timing. */
+typedef enum {
+  LLOID_STAGE_INGEST = 0,    /* strain upload and conversion */
+  LLOID_STAGE_DECIMATE = 1,  /* half-band decimation to every slice rate */
+  LLOID_STAGE_FIR = 2,       /* basis-filter correlation, all slices */
+  LLOID_STAGE_INTERP = 3,    /* interpolation of low-rate orthogonal SNR to f0 */
+  LLOID_STAGE_MIX = 4,       /* mixing GEMM + complex SNR + window peaks */
+  LLOID_STAGE_TRIGGER = 5,   /* trigger compaction */
+  LLOID_STAGE_D2H = 6,       /* results to the caller's buffers */
+  LLOID_N_STAGES = 7
+} lloid_stage;
+
+/* Turn per-stage timing on (1) or off (0).  While on, every lloid_filter call
+ * brackets each stage with HIP events on the context's stream and adds the
+ * elapsed device time to the context's totals. */
+lloid_status lloid_ctx_profile(lloid_ctx *ctx, int enable);
+
+/* Totals since the last reset: ms[LLOID_N_STAGES] of device time and
+ * calls[LLOID_N_STAGES] (host buffers, either may be NULL); reset != 0 clears
+ * them afterwards. */
+lloid_status lloid_ctx_stage_times(lloid_ctx *ctx, double *ms, int64_t *calls, int reset);
+
 /* Upload one SVD bank (Sec. II.A "SVD bank").  Validates every slice (EINVAL
  * on a rate that is not f0 / 2^k, a start tap that is not a multiple of
  * f0 / r_s, L_s > N_s, a NULL array), scales each slice's basis and the

@@ -157,10 +157,31 @@ extern "C" lloid_status lloid_ctx_create(int device, void *hip_stream, lloid_ctx
   ABI_GUARD_END
 }
 
+extern "C" lloid_status lloid_ctx_profile(lloid_ctx *ctx, int enable) {
+  if (!ctx) return fail(LLOID_EINVAL, "NULL context");
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (enable && !ctx->ev[0])
+    for (auto &e : ctx->ev) HIP_TRY(hipEventCreate(&e));
+  ctx->profile = enable != 0;
+  return LLOID_OK;
+}
+
+extern "C" lloid_status lloid_ctx_stage_times(lloid_ctx *ctx, double *ms, int64_t *calls, int reset) {
+  if (!ctx) return fail(LLOID_EINVAL, "NULL context");
+  for (int i = 0; i < LLOID_N_STAGES; ++i) {
+    if (ms) ms[i] = ctx->stage_ms[i];
+    if (calls) calls[i] = ctx->stage_calls[i];
+    if (reset) ctx->stage_ms[i] = 0.0, ctx->stage_calls[i] = 0;
+  }
+  return LLOID_OK;
+}
+
 extern "C" lloid_status lloid_ctx_destroy(lloid_ctx *ctx) {
   if (!ctx) return LLOID_OK;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (auto &e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->d_halfband) (void)hipFree(ctx->d_halfband);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -464,6 +485,7 @@ extern "C" lloid_status lloid_filter(lloid_bank *b, int32_t detector, const void
 
   Carve cv{(char *)b->ws.base};
   const void *d_strain = strain;
+  if (ctx->profile) HIP_TRY(hipEventRecord(ctx->ev[2 * LLOID_STAGE_INGEST], st));
   if (host_strain) {
     void *tmp = cv.take<char>((size_t)n * dtype_size(sdt));
     HIP_TRY(hipMemcpyAsync(tmp, strain, (size_t)n * dtype_size(sdt), hipMemcpyHostToDevice, st));
@@ -490,24 +512,38 @@ extern "C" lloid_status lloid_filter(lloid_bank *b, int32_t detector, const void
   pa.win_p = p.win_p;
   pa.win_q = p.win_q;
 
+  auto mark = [&](int stage, int end) -> hipError_t {
+    return ctx->profile ? hipEventRecord(ctx->ev[2 * stage + end], st) : hipSuccess;
+  };
   // 1. strain -> FP32 at full rate, zero outside [0, n)
   HIP_TRY(launch_fill_u8(bad, sizeof(int), st));
   HIP_TRY(launch_convert(d_strain, sdt, n, xl[0], p.sup[0].lo, p.sup[0].size(), sscale, bad, st));
+  HIP_TRY(mark(LLOID_STAGE_INGEST, 1));
   // 2. half-band decimation to every level
+  HIP_TRY(mark(LLOID_STAGE_DECIMATE, 0));
   for (int k = 1; k < p.n_levels; ++k)
     HIP_TRY(launch_decimate(xl[k - 1], p.sup[k - 1].lo, p.sup[k - 1].size(), xl[k], p.sup[k].lo, p.sup[k].size(),
                             ctx->d_halfband, st));
-  // 3. FIR bank per slice; 4. interpolation of low-rate slices to f0
+  HIP_TRY(mark(LLOID_STAGE_DECIMATE, 1));
+  // 3. FIR bank per slice
+  HIP_TRY(mark(LLOID_STAGE_FIR, 0));
   for (size_t s = 0; s < b->slices.size(); ++s) {
     const SliceDev &sl = b->slices[s];
     const int k = sl.level;
-    if (k == 0) {
+    if (k == 0)
       HIP_TRY(launch_fir(b->compute, sl, xl[0], p.sup[0].lo, p.sup[0].size(), 0, n, ocat, 0, b->kcat, sl.koff, sl.lp,
                          st));
-      continue;
-    }
-    HIP_TRY(launch_fir(b->compute, sl, xl[k], p.sup[k].lo, p.sup[k].size(), p.need[k].lo, p.need[k].hi, olow[s],
-                       p.need[k].lo, sl.lp, 0, sl.lp, st));
+    else
+      HIP_TRY(launch_fir(b->compute, sl, xl[k], p.sup[k].lo, p.sup[k].size(), p.need[k].lo, p.need[k].hi, olow[s],
+                         p.need[k].lo, sl.lp, 0, sl.lp, st));
+  }
+  HIP_TRY(mark(LLOID_STAGE_FIR, 1));
+  // 4. interpolation of the low-rate orthogonal SNR to f0, into the concatenated operand
+  HIP_TRY(mark(LLOID_STAGE_INTERP, 0));
+  for (size_t s = 0; s < b->slices.size(); ++s) {
+    const SliceDev &sl = b->slices[s];
+    const int k = sl.level;
+    if (k == 0) continue;
     const float *src = olow[s];
     int64_t src_lo = p.need[k].lo, src_len = p.need[k].size();
     int which = 0;
@@ -526,14 +562,20 @@ extern "C" lloid_status lloid_filter(lloid_bank *b, int32_t detector, const void
       }
     }
   }
+  HIP_TRY(mark(LLOID_STAGE_INTERP, 1));
   // 5. mixing GEMM + complex SNR + per-window peaks
   const float inv_scale = 1.f / (b->mix_scale * sscale);
+  HIP_TRY(mark(LLOID_STAGE_MIX, 0));
   HIP_TRY(launch_mix_peak(b->compute, b->mix, b->rows, b->kcat, F, ocat, n, inv_scale, pa, st));
+  HIP_TRY(mark(LLOID_STAGE_MIX, 1));
   // 6. trigger compaction
+  HIP_TRY(mark(LLOID_STAGE_TRIGGER, 0));
   HIP_TRY(launch_trigger_count(pa.peak_snr, F, p.n_windows, thr, counts, st));
   HIP_TRY(launch_trigger_scan(counts, F, total, st));
   HIP_TRY(launch_trigger_write(pa.peak_snr, pa.peak_n, pa.peak_phase, F, p.n_windows, thr, counts, dev_cap, 0,
                                detector, dtrig, st));
+  HIP_TRY(mark(LLOID_STAGE_TRIGGER, 1));
+  HIP_TRY(mark(LLOID_STAGE_D2H, 0));
   int64_t h_total = 0;
   int h_bad = 0;
   HIP_TRY(hipMemcpyAsync(&h_total, total, sizeof h_total, hipMemcpyDeviceToHost, st));
@@ -547,9 +589,16 @@ extern "C" lloid_status lloid_filter(lloid_bank *b, int32_t detector, const void
   if (host_snr) HIP_TRY(hipMemcpyAsync(snr, dsnr, (size_t)F * n * 2 * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const int64_t ncopy = std::min(h_total, dev_cap);
-  if (ncopy > 0) {
-    HIP_TRY(hipMemcpyAsync(trig, dtrig, (size_t)ncopy * sizeof(lloid_trigger), hipMemcpyDefault, st));
-    HIP_TRY(hipStreamSynchronize(st));
+  if (ncopy > 0) HIP_TRY(hipMemcpyAsync(trig, dtrig, (size_t)ncopy * sizeof(lloid_trigger), hipMemcpyDefault, st));
+  HIP_TRY(mark(LLOID_STAGE_D2H, 1));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (ctx->profile) {
+    for (int i = 0; i < LLOID_N_STAGES; ++i) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[2 * i], ctx->ev[2 * i + 1]));
+      ctx->stage_ms[i] += ms;
+      ctx->stage_calls[i] += 1;
+    }
   }
   *n_trig = h_total;
   if (h_bad) return fail(LLOID_EDATA, "strain holds a non-finite sample");

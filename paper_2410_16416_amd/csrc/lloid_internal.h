@@ -60,6 +60,10 @@ struct lloid_ctx {
   float *d_halfband = nullptr;  // device copy of g[n] (kHalfTaps floats)
   double halfband[lloid::kHalfTaps];
   int n_cu = 0;
+  bool profile = false;
+  hipEvent_t ev[2 * LLOID_N_STAGES] = {};
+  double stage_ms[LLOID_N_STAGES] = {};
+  int64_t stage_calls[LLOID_N_STAGES] = {};
 };
 
 struct lloid_bank {

@@ -79,6 +79,8 @@ def _load():
         "lloid_version": ([], ctypes.c_char_p),
         "lloid_ctx_create": ([ctypes.c_int, vp, ctypes.POINTER(vp)], ctypes.c_int),
         "lloid_ctx_destroy": ([vp], ctypes.c_int),
+        "lloid_ctx_profile": ([vp, ctypes.c_int], ctypes.c_int),
+        "lloid_ctx_stage_times": ([vp, vp, vp, ctypes.c_int], ctypes.c_int),
         "lloid_bank_create": ([vp, ctypes.POINTER(lloid_bank_desc), ctypes.POINTER(vp)], ctypes.c_int),
         "lloid_bank_sigma2": ([vp, vp], ctypes.c_int),
         "lloid_bank_query": ([vp, ctypes.POINTER(lloid_bank_info)], ctypes.c_int),
@@ -112,6 +114,7 @@ def _ptr(a):
 
 def exported_symbols():
     return ["lloid_last_error", "lloid_version", "lloid_ctx_create", "lloid_ctx_destroy",
+            "lloid_ctx_profile", "lloid_ctx_stage_times",
             "lloid_bank_create", "lloid_bank_sigma2", "lloid_bank_query", "lloid_bank_destroy",
             "lloid_filter"]
 
@@ -129,6 +132,21 @@ def lloid_ctx_create(device: int = 0, stream=None):
 
 def lloid_ctx_destroy(ctx):
     _check(_lib.lloid_ctx_destroy(ctx))
+
+
+STAGES = ["ingest", "decimate", "fir", "interp", "mix", "trigger", "d2h"]
+
+
+def lloid_ctx_profile(ctx, enable: bool):
+    _check(_lib.lloid_ctx_profile(ctx, 1 if enable else 0))
+
+
+def lloid_ctx_stage_times(ctx, reset: bool = False):
+    """{stage: (total device ms, calls)} since the last reset."""
+    ms = np.zeros(len(STAGES), dtype=np.float64)
+    calls = np.zeros(len(STAGES), dtype=np.int64)
+    _check(_lib.lloid_ctx_stage_times(ctx, ms.ctypes.data, calls.ctypes.data, 1 if reset else 0))
+    return {k: (float(ms[i]), int(calls[i])) for i, k in enumerate(STAGES)}
 
 
 def lloid_bank_create(ctx, full_rate_hz: int, n_templates: int, slices, compute: str = "f16"):
