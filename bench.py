@@ -139,6 +139,147 @@ def run_path(lloid, ctx, wl, xs, compute, steps, warmup, tbufs):
     return wall, n_trig, stages
 
 
+def batched_work(banks, seconds):
+    fir = sum(2.0 * s.n_basis * s.n_taps * s.rate for b in banks for s in b.slices) * seconds
+    mix = sum(2.0 * 2 * b.n_templates * s.n_basis * s.rate for b in banks for s in b.slices) * seconds
+    return fir, mix
+
+
+def bench_batched(args):
+    """64 uneven banks (F 200-2000, 1-4 slices, filters 0.5-64 s), 2 detectors x
+    512 s; one step filters both detectors with every bank, one launch per
+    stage per chunk (lloid_filter_batch)."""
+    import numpy as np
+    import torch
+    from workloads import configs
+    from paper_2410_16416_amd import lloid
+    nb = args.banks or 64
+    seconds = args.seconds if args.seconds != 1024 else 512
+    log(f"[bench] batched: generating {nb} banks")
+    t0 = time.perf_counter()
+    banks = configs.batched_c3_banks(nb)
+    log(f"[bench] banks ready in {time.perf_counter() - t0:.1f} s")
+    f0 = 2048
+    xs = [torch.from_numpy(np.random.default_rng(configs.seed(3, d)).standard_normal(seconds * f0)).to("cuda")
+          for d in range(2)]
+    torch.cuda.init()
+    ctx = lloid.lloid_ctx_create(0)
+    out = {}
+    for compute in [args.compute] + (["f32"] if args.f32_steps and args.compute != "f32" else []):
+        hs = [lloid.bank_from_svd(ctx, b, compute) for b in banks]
+        steps = args.steps if compute == args.compute else args.f32_steps
+        nwin = seconds
+        cap = sum(b.n_templates for b in banks) * nwin
+        tbuf = torch.empty(cap * lloid.TRIGGER_DTYPE.itemsize, dtype=torch.uint8, pin_memory=True)
+
+        def step():
+            n = 0
+            for d, x in enumerate(xs):
+                n += lloid.lloid_filter_batch(hs, d, x, window=(1, 1), triggers_out=tbuf).n_triggers
+            return n
+        for _ in range(max(args.warmup, 1) if compute == args.compute else 1):
+            step()
+        torch.cuda.synchronize()
+        lloid.lloid_ctx_profile(ctx, True)
+        lloid.lloid_ctx_stage_times(ctx, reset=True)
+        t = time.perf_counter()
+        for _ in range(steps):
+            ntr = step()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / steps
+        stages = lloid.lloid_ctx_stage_times(ctx, reset=True)
+        lloid.lloid_ctx_profile(ctx, False)
+        for h in hs:
+            lloid.lloid_bank_destroy(h)
+        samples = sum(b.n_templates for b in banks) * seconds * f0 * 2
+        fir, mix = batched_work(banks, seconds * 2)
+        out[compute] = {"value": round(samples / wall, 1), "ms_per_step": round(wall * 1e3, 2),
+                        "triggers_per_step": int(ntr),
+                        "algorithmic_tflop_per_step": round((fir + mix) / 1e12, 2),
+                        "algorithmic_tflops": round((fir + mix) / wall / 1e12, 1),
+                        "mfma_frac_of_peak": round((fir + mix) / wall / 1e12 / PEAK_TFLOPS[compute], 4),
+                        "stage_ms_last_chunk": {k: round(v[0] / max(v[1], 1), 3) for k, v in stages.items()}}
+        log(f"[bench] batched {compute}: {out[compute]}")
+    lloid.lloid_ctx_destroy(ctx)
+    main_ = out[args.compute]
+    return {"metric": METRIC, "value": main_["value"], "unit": "template-samples/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.compute,
+            "data": "synthetic (seeded white Gaussian noise; uneven bank shapes with seeded random orthonormal bases)",
+            "config": {"workload": f"batched_c3: {nb} uneven SVD banks (F U[200,2000], 1-4 slices at 2048 Hz "
+                                   f"and lower, filters 0.5-64 s), 2 detectors x {seconds} s, one launch per stage",
+                       "banks": nb, "templates": sum(b.n_templates for b in banks), "detectors": 2,
+                       "seconds": seconds, "f0": f0},
+            "paths": out}
+
+
+def bench_serving(args):
+    """128 banks drawn as in the batched workload, 2 detectors, strain pushed in
+    1 s strides at `rate` x real time; p50/p99 latency from the push that
+    completes a stride to its triggers on the host, and template-samples/s."""
+    import numpy as np
+    import torch
+    from workloads import configs
+    from paper_2410_16416_amd import lloid
+    nb = args.banks or 128
+    log(f"[bench] serving: generating {nb} banks")
+    banks = configs.batched_c3_banks(nb)
+    f0 = 2048
+    n_strides = args.strides
+    warm = 4
+    total = (n_strides + warm) * f0
+    xs = [np.random.default_rng(configs.seed(4, d)).standard_normal(total).astype(np.float32) for d in range(2)]
+    torch.cuda.init()
+    ctx = lloid.lloid_ctx_create(0)
+    out = {}
+    for compute in [args.compute] + (["f32"] if args.f32_steps and args.compute != "f32" else []):
+        hs = [lloid.bank_from_svd(ctx, b, compute) for b in banks]
+        s = lloid.lloid_stream_create(ctx, f0, compute, n_detectors=2, min_rate_hz=128, window=(1, 1),
+                                      max_filter_s=66.0, max_windows_per_tick=2)
+        for h in hs:
+            lloid.lloid_stream_admit(s, h)
+        n_trig = 0
+        lat = []
+        t_start = None
+        for i in range(n_strides + warm):
+            if i == warm:
+                t_start = time.perf_counter()
+            if t_start is not None:
+                due = t_start + (i - warm) / args.rate
+                while time.perf_counter() < due:
+                    pass
+            arrive = time.perf_counter()
+            for d in range(2):
+                lloid.lloid_stream_push(s, d, i * f0, xs[d][i * f0:(i + 1) * f0])
+            n_trig += lloid.lloid_stream_poll(s).shape[0]
+            if i >= warm:
+                lat.append((time.perf_counter() - (t_start + (i - warm) / args.rate)) * 1e3)
+        wall = time.perf_counter() - t_start
+        st = lloid.lloid_stream_stats_get(s)
+        lloid.lloid_stream_destroy(s)
+        for h in hs:
+            lloid.lloid_bank_destroy(h)
+        samples = sum(b.n_templates for b in banks) * n_strides * f0 * 2
+        lat = np.array(lat)
+        out[compute] = {"value": round(samples / wall, 1), "wall_s": round(wall, 3),
+                        "p50_stride_latency_ms": round(float(np.percentile(lat, 50)), 3),
+                        "p99_stride_latency_ms": round(float(np.percentile(lat, 99)), 3),
+                        "library_p50_ms": round(st.latency_p50_ms, 3), "library_p99_ms": round(st.latency_p99_ms, 3),
+                        "kept_up": bool(wall <= n_strides / args.rate * 1.05), "triggers": int(n_trig)}
+        log(f"[bench] serving {compute}: {out[compute]}")
+    lloid.lloid_ctx_destroy(ctx)
+    m = out[args.compute]
+    return {"metric": METRIC, "value": m["value"], "unit": "template-samples/s", "n_gpus": 1,
+            "steps": n_strides, "warmup": warm, "ms_per_step": round(m["wall_s"] / n_strides * 1e3, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.compute,
+            "data": "synthetic (seeded white Gaussian noise; uneven bank shapes with seeded random orthonormal bases)",
+            "config": {"workload": f"serving_c4: {nb} banks, 2 detectors, 1 s strides at {args.rate:g}x real time",
+                       "banks": nb, "templates": sum(b.n_templates for b in banks), "detectors": 2,
+                       "strides": n_strides, "rate_x_real_time": args.rate, "f0": f0},
+            "p50_stride_latency_ms": m["p50_stride_latency_ms"], "p99_stride_latency_ms": m["p99_stride_latency_ms"],
+            "paths": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +289,14 @@ def main():
     ap.add_argument("--seconds", type=int, default=1024, help="seconds of strain per detector")
     ap.add_argument("--f32-steps", type=int, default=3, help="timed steps of the plain FP32 path (0: skip)")
     ap.add_argument("--cpu-sample-s", type=float, default=24.0, help="oracle sample length (0: skip)")
+    ap.add_argument("--workload", default="multirate_c1", choices=["multirate_c1", "batched_c3", "serving_c4"],
+                    help="multirate_c1 (headline), batched_c3 (64 uneven banks, one launch per stage), "
+                         "serving_c4 (128 banks streamed in 1 s strides)")
+    ap.add_argument("--banks", type=int, default=0, help="banks for batched_c3 / serving_c4 (0: 64 / 128)")
+    ap.add_argument("--rate", type=float, default=16.0, help="serving_c4: strides per second (x real time)")
+    ap.add_argument("--strides", type=int, default=120, help="serving_c4: timed 1 s strides")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (PMC byte-counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -160,6 +309,12 @@ def main():
     from workloads import configs
     from paper_2410_16416_amd import lloid
 
+    if args.workload == "batched_c3":
+        print(json.dumps(bench_batched(args)), flush=True)
+        return
+    if args.workload == "serving_c4":
+        print(json.dumps(bench_serving(args)), flush=True)
+        return
     log(f"[bench] generating workload ({args.seconds} s x 2 detectors)")
     t0 = time.perf_counter()
     wl = configs.multirate_c1(seconds=args.seconds)
@@ -219,6 +374,16 @@ def main():
         out["f32_path"] = {"value": round(v32, 1), "ms_per_step": round(w32 / args.f32_steps * 1e3, 3),
                            "speedup_of_headline": round(value / v32, 2),
                            "roofline_mix": roofline_entry("mfma", work["mix"][1], ms / max(calls, 1), "f32")}
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        b2 = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b2.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nbytes
+        del a, b2
     if args.cpu_sample_s > 0:
         log(f"[bench] cpu baseline: oracle on {args.cpu_sample_s:g} s")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_s)

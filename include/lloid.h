@@ -202,6 +202,90 @@ lloid_status lloid_filter(lloid_bank *bank, int32_t detector,
                           lloid_trigger *trig, int64_t trig_cap, int64_t *n_trig,
                           float *snr, lloid_peaks *peaks);
 
+/* Filter one block of strain of one detector with many SVD banks at once
+ * (Sec. II.B: banks are stacked and filtered together).  The banks must share
+ * the context, full rate and compute type; they may differ in every other
+ * respect (templates, slices, rates, lengths).  Each stage of the path runs
+ * as one launch over a descriptor table of all banks' work, longest work
+ * first.  The strain is down-sampled once for all banks.
+ *   banks:  n_banks bank handles; trigger records carry the bank's index in
+ *           this array in their `bank` field.
+ *   peaks:  NULL, or n_banks dense peak outputs (one per bank, as in
+ *           lloid_filter).
+ * Other arguments and errors are as for lloid_filter; triggers are ordered by
+ * bank, then template, then window. */
+lloid_status lloid_filter_batch(lloid_bank *const *banks, int32_t n_banks, int32_t detector,
+                                const void *strain, lloid_dtype strain_dtype, int64_t n,
+                                const lloid_trigger_opts *opts,
+                                lloid_trigger *trig, int64_t trig_cap, int64_t *n_trig,
+                                lloid_peaks *peaks);
+
+/* ---- streaming (serving) ----
+ * Strain arrives in strides per detector; the down-sampled strain of every
+ * rate stays on the device as the filters' history.  Every time all
+ * detectors hold enough strain to complete trigger windows, one tick filters
+ * those windows for every admitted bank and detector, one launch per stage
+ * for all of them, and queues the triggers for lloid_stream_poll.  Banks
+ * ("requests") are admitted into slots while their arrays plus their per-tick
+ * scratch fit the device-memory budget; later ones wait in arrival order and
+ * are admitted when slots are removed.  A bank reports the windows from its
+ * admission on; since the history is complete, every result equals the one
+ * lloid_filter gives for the whole stream (bit for bit).  After
+ * lloid_stream_flush (zero strain past the end, as lloid_filter assumes) the
+ * stream emits its remaining windows and accepts no more strain. */
+typedef struct {
+  int32_t n_detectors;          /* 1..16 */
+  int32_t min_rate_hz;          /* lowest slice rate an admitted bank may use */
+  int32_t max_windows_per_tick; /* windows filtered by one tick at most; 0 means 8 */
+  int32_t reserved;
+  double max_filter_s;          /* longest slice span (J_s / f0 + N_s / r_s) an admitted bank may
+                                   have, in seconds; sets the history kept; 0 means 66 */
+  int64_t hbm_budget;           /* device bytes for admitted banks (arrays + per-tick scratch);
+                                   0 means no limit */
+  lloid_trigger_opts trig;      /* window length, threshold, strain scale */
+} lloid_stream_opts;
+
+typedef struct {
+  int64_t ticks;                /* ticks that filtered at least one bank */
+  int64_t windows;              /* windows emitted (per detector) */
+  int64_t triggers;             /* triggers queued so far */
+  int64_t next_window;          /* first window not yet emitted */
+  double latency_p50_ms;        /* push of the stride that completed a tick -> its triggers queued */
+  double latency_p99_ms;
+  double latency_max_ms;
+  int32_t active_slots;
+  int32_t queued_banks;
+  int64_t bytes_in_use;         /* budget taken by active slots */
+} lloid_stream_stats;
+
+lloid_status lloid_stream_create(lloid_ctx *ctx, int32_t full_rate_hz, lloid_dtype compute,
+                                 const lloid_stream_opts *opts, lloid_stream **out);
+/* Admit a bank (same context, full rate and compute type as the stream).  The
+ * bank must outlive its slot.  *slot receives the slot id, which trigger
+ * records carry in their `bank` field.  EAGAIN: the bank is queued and becomes
+ * active when enough budget frees up; ENOMEM: it can never fit the budget;
+ * EINVAL: its filters are longer than the stream's history. */
+lloid_status lloid_stream_admit(lloid_stream *s, lloid_bank *bank, int32_t *slot);
+/* Remove an active or queued slot; queued banks are admitted as budget frees up. */
+lloid_status lloid_stream_remove(lloid_stream *s, int32_t slot);
+/* Append n samples (host or device, F64 or F32) of detector `detector`
+ * starting at full-rate sample t0, which must continue the previous stride
+ * (EORDER otherwise); runs every tick the new strain completes.  EDATA on a
+ * non-finite sample. */
+lloid_status lloid_stream_push(lloid_stream *s, int32_t detector, int64_t t0, const void *data,
+                               lloid_dtype dtype, int64_t n);
+/* Move up to cap queued triggers (tick order; within a tick by slot,
+ * detector, template, window) into out (host). */
+lloid_status lloid_stream_poll(lloid_stream *s, lloid_trigger *out, int64_t cap, int64_t *n_out);
+lloid_status lloid_stream_flush(lloid_stream *s);
+lloid_status lloid_stream_stats_get(const lloid_stream *s, lloid_stream_stats *out);
+lloid_status lloid_stream_destroy(lloid_stream *s);
+
+/* Device bytes the filter calls of this context may use for the per-chunk
+ * operands (the orthogonal SNR of every bank over a run of whole windows);
+ * longer blocks are processed in several chunks.  Default 6 GiB. */
+lloid_status lloid_ctx_set_chunk_bytes(lloid_ctx *ctx, int64_t bytes);
+
 #ifdef __cplusplus
 }
 #endif

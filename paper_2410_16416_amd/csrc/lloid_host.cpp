@@ -18,7 +18,7 @@ using namespace lloid;
 
 static thread_local std::string g_last_error;
 
-static lloid_status fail(lloid_status st, const char *fmt, ...) {
+lloid_status lloid::fail(lloid_status st, const char *fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -28,32 +28,11 @@ static lloid_status fail(lloid_status st, const char *fmt, ...) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                                      \
-  do {                                                                                     \
-    hipError_t e_ = (expr);                                                                \
-    if (e_ != hipSuccess)                                                                  \
-      return fail(LLOID_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
-                  __FILE__, __LINE__);                                                     \
-  } while (0)
-
-#define ABI_GUARD_BEGIN try {
-#define ABI_GUARD_END                                                     \
-  }                                                                       \
-  catch (const std::bad_alloc &) {                                        \
-    return fail(LLOID_ENOMEM, "host allocation failed");                  \
-  }                                                                       \
-  catch (const std::exception &ex) {                                      \
-    return fail(LLOID_EINVAL, "internal error: %s", ex.what());           \
-  }
-
 extern "C" const char *lloid_last_error(void) { return g_last_error.c_str(); }
 extern "C" const char *lloid_version(void) { return "lloid-gfx950 0.1"; }
 
 // ------------------------------------------------------------ helpers
 
-static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
-static int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-static int64_t ceil_div(int64_t a, int64_t b) { return -floor_div(-a, b); }
 static bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 static int log2i(int64_t v) {
   int k = 0;
@@ -91,26 +70,6 @@ static float pow2_scale(double max_abs) {
   int e;
   std::frexp(max_abs, &e);  // max_abs = f 2^e, f in [1/2, 1)
   return (float)std::ldexp(1.0, -e);
-}
-
-static bool is_device_ptr(const void *p) {
-  hipPointerAttribute_t attr;
-  hipError_t e = hipPointerGetAttributes(&attr, p);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
-}
-
-static size_t dtype_size(lloid_dtype t) {
-  switch (t) {
-    case LLOID_F64: return 8;
-    case LLOID_F32: return 4;
-    case LLOID_F16: return 2;
-    case LLOID_BF16: return 2;
-  }
-  return 0;
 }
 
 // Device-side cast of an FP64 array to the compute type.
@@ -182,6 +141,8 @@ extern "C" lloid_status lloid_ctx_destroy(lloid_ctx *ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto &e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
+  if (ctx->ws.base) (void)hipFree(ctx->ws.base);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->d_halfband) (void)hipFree(ctx->d_halfband);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -194,7 +155,6 @@ static void free_bank_device(lloid_bank *b) {
   for (auto &s : b->slices)
     if (s.basis) (void)hipFree(s.basis), s.basis = nullptr;
   if (b->mix) (void)hipFree(b->mix), b->mix = nullptr;
-  if (b->ws.base) (void)hipFree(b->ws.base), b->ws.base = nullptr, b->ws.bytes = 0;
 }
 
 extern "C" lloid_status lloid_bank_destroy(lloid_bank *bank) {
@@ -237,7 +197,7 @@ extern "C" lloid_status lloid_bank_create(lloid_ctx *ctx, const lloid_bank_desc 
   b->f0 = f0;
   b->n_templates = F;
   b->compute = d->compute;
-  b->rows = (int)round_up(2 * (int64_t)F, 32 * kMixMT);
+  b->rows = (int)round_up(2 * (int64_t)F, kMixBM);
   const size_t esz = dtype_size(d->compute);
   int koff = 0, lsum = 0;
   double max_mix = 0.0;
@@ -361,72 +321,174 @@ extern "C" lloid_status lloid_bank_query(const lloid_bank *bank, lloid_bank_info
   return LLOID_OK;
 }
 
-// ------------------------------------------------------------ filter plan
+// ------------------------------------------------------------ filter engine
 
-namespace {
-
-// Index ranges of one offline block of n full-rate samples.
-struct Plan {
-  int n_levels = 1;
-  std::vector<Range> need;  // outputs needed at each level for Y on [0, n)
-  std::vector<Range> sup;   // support of the decimated strain at each level
-  int64_t n_windows = 0, win_p = 1, win_q = 1;
-};
-
-Plan make_plan(const lloid_bank *b, int64_t n, int64_t num, int64_t den) {
-  Plan p;
-  p.n_levels = b->n_levels;
-  p.need.resize(p.n_levels);
-  p.sup.resize(p.n_levels);
-  p.need[0] = {0, n};
-  p.sup[0] = {0, n};
-  for (int k = 1; k < p.n_levels; ++k) {
-    // interpolation reads w[j] with |n - 2j| <= Q; decimation reads u[2k - m], |m| <= Q
-    p.need[k] = {ceil_div(p.need[k - 1].lo - kHalfQ, 2), floor_div(p.need[k - 1].hi - 1 + kHalfQ, 2) + 1};
-    p.sup[k] = {ceil_div(p.sup[k - 1].lo - kHalfQ, 2), floor_div(p.sup[k - 1].hi - 1 + kHalfQ, 2) + 1};
-  }
-  p.win_p = (int64_t)b->f0 * num;
-  p.win_q = den;
-  // window of sample n-1: largest w with floor(w p / q) <= n - 1
-  p.n_windows = ceil_div(n * p.win_q, p.win_p);
-  return p;
-}
-
-struct Carve {
-  char *base;
-  size_t off = 0;
-  template <typename T> T *take(size_t count) {
-    off = (size_t)round_up((int64_t)off, 256);
-    T *r = (T *)(base + off);
-    off += count * sizeof(T);
-    return r;
-  }
-};
-
-}  // namespace
-
-static lloid_status ensure_ws(lloid_bank *b, size_t bytes) {
-  if (b->ws.bytes >= bytes) return LLOID_OK;
-  HIP_TRY(hipStreamSynchronize(b->ctx->stream));
-  if (b->ws.base) (void)hipFree(b->ws.base);
-  b->ws.base = nullptr;
-  b->ws.bytes = 0;
-  if (hipMalloc(&b->ws.base, bytes) != hipSuccess) {
+lloid_status lloid::ensure_ws(lloid_ctx *ctx, Workspace &ws, size_t bytes) {
+  if (ws.bytes >= bytes) return LLOID_OK;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (ws.base) (void)hipFree(ws.base);
+  ws.base = nullptr;
+  ws.bytes = 0;
+  if (hipMalloc(&ws.base, bytes) != hipSuccess) {
     (void)hipGetLastError();
     return fail(LLOID_ENOMEM, "workspace of %zu bytes does not fit on the device", bytes);
   }
-  b->ws.bytes = bytes;
+  ws.bytes = bytes;
   return LLOID_OK;
 }
 
-extern "C" lloid_status lloid_filter(lloid_bank *b, int32_t detector, const void *strain, lloid_dtype sdt, int64_t n,
-                                     const lloid_trigger_opts *opts, lloid_trigger *trig, int64_t trig_cap,
-                                     int64_t *n_trig, float *snr, lloid_peaks *peaks) {
-  ABI_GUARD_BEGIN
-  if (!b || !strain || !n_trig) return fail(LLOID_EINVAL, "NULL argument");
+lloid_status lloid::ensure_pinned(lloid_ctx *ctx, void *&p, size_t &have, size_t bytes) {
+  if (have >= bytes) return LLOID_OK;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  have = 0;
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LLOID_ENOMEM, "pinned staging of %zu bytes failed", bytes);
+  }
+  have = bytes;
+  return LLOID_OK;
+}
+
+size_t lloid::olow_rows(int64_t t_len, int level) {
+  return (size_t)need_ranges(0, t_len, level + 1)[level].size() + 2;
+}
+
+void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, int64_t t1, int64_t n_end, int64_t wa,
+                          int64_t wb, const Windows &win, const BankBufs &bb, float inv_scale, float *snr,
+                          int64_t snr_ld, const TileShapes &ts, std::vector<FirJob> &fj, std::vector<InterpJob> &ij,
+                          std::vector<MixJob> &mj) {
+  for (size_t s = 0; s < b->slices.size(); ++s) {
+    const SliceDev &sl = b->slices[s];
+    const Range r = need_ranges(t0, t1, sl.level + 1)[sl.level];
+    FirJob j{};
+    j.basis = sl.basis;
+    j.x = lv[sl.level].x;
+    j.x_lo = lv[sl.level].lo;
+    j.x_len = lv[sl.level].len;
+    j.base = -(sl.start_tap / sl.dec + sl.n_taps - 1);
+    j.k_lo = r.lo;
+    j.k_hi = r.hi;
+    j.rows = sl.lrows;
+    j.np = sl.np;
+    j.n_rtiles = (int)ceil_div(sl.lrows, ts.fbm);
+    j.n_ctiles = (int)ceil_div(r.size(), ts.fbn);
+    j.col_limit = sl.lp;
+    if (sl.level == 0) {
+      j.out = bb.ocat;
+      j.out_lo = t0;
+      j.ldo = b->kcat;
+      j.col0 = sl.koff;
+      j.out_f32 = 0;
+    } else {
+      j.out = bb.olow[s];
+      j.out_lo = r.lo;
+      j.ldo = sl.lp;
+      j.col0 = 0;
+      j.out_f32 = 1;
+      InterpJob q{};
+      q.src = bb.olow[s];
+      q.src_lo = r.lo;
+      q.src_len = r.size();
+      q.ldw = sl.lp;
+      q.levels = sl.level;
+      q.out = bb.ocat;
+      q.out_abs0 = t0;
+      q.n_out = t1 - t0;
+      q.ldo = b->kcat;
+      q.col0 = sl.koff;
+      q.channels = sl.lp;
+      q.n_rblocks = (int)ceil_div(t1 - t0, 128);
+      q.n_cblocks = (int)ceil_div(sl.lp, 32);
+      ij.push_back(q);
+    }
+    fj.push_back(j);
+  }
+  MixJob m{};
+  m.mix = b->mix;
+  m.ocat = bb.ocat;
+  m.peak_snr = bb.psnr;
+  m.peak_n = bb.pn;
+  m.peak_phase = bb.pphase;
+  m.snr = snr;
+  m.ocat_abs0 = t0;
+  m.n_end = n_end;
+  m.w0 = wa;
+  m.nw = wb - wa;
+  m.win_p = win.p;
+  m.win_q = win.q;
+  m.ld_peak = bb.ld_peak;
+  m.w_base = bb.w_base;
+  m.snr_ld = snr_ld;
+  m.inv_scale = inv_scale;
+  m.rows = b->rows;
+  m.kcat = b->kcat;
+  m.n_templates = b->n_templates;
+  m.n_rtiles = (int)ceil_div(b->rows, ts.mbm);
+  mj.push_back(m);
+}
+
+void lloid::number_jobs(std::vector<FirJob> &fj, std::vector<InterpJob> &ij, std::vector<MixJob> &mj, StageItems &n) {
+  // longest items first
+  std::stable_sort(fj.begin(), fj.end(), [](const FirJob &a, const FirJob &b) { return a.np > b.np; });
+  std::stable_sort(mj.begin(), mj.end(), [](const MixJob &a, const MixJob &b) { return a.kcat > b.kcat; });
+  int64_t it = 0;
+  for (auto &j : fj) j.item0 = it, it += (int64_t)j.n_rtiles * j.n_ctiles;
+  n.fir = it;
+  it = 0;
+  for (auto &q : ij) q.item0 = it, it += (int64_t)q.n_rblocks * q.n_cblocks;
+  n.interp = it;
+  it = 0;
+  int64_t e = 0;
+  for (auto &m : mj) {
+    m.item0 = it;
+    it += ceil_div(m.nw, 8) * 8 * m.n_rtiles;
+    m.e0 = e;
+    e += (int64_t)m.n_templates * m.nw;
+  }
+  n.mix = it;
+  n.entries = e;
+}
+
+lloid_status lloid::launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dtab, const TabOffsets &to,
+                                  const StageItems &n, bool with_snr, float phase_thr, bool mark_stages) {
+  hipStream_t st = ctx->stream;
+  auto mark = [&](int stage, int end) -> hipError_t {
+    return (ctx->profile && mark_stages) ? hipEventRecord(ctx->ev[2 * stage + end], st) : hipSuccess;
+  };
+  HIP_TRY(mark(LLOID_STAGE_FIR, 0));
+  HIP_TRY(launch_fir_jobs(ct, (const FirJob *)(dtab + to.fir), to.n_fir, n.fir, st));
+  HIP_TRY(mark(LLOID_STAGE_FIR, 1));
+  HIP_TRY(mark(LLOID_STAGE_INTERP, 0));
+  HIP_TRY(launch_interp_jobs(ct, (const InterpJob *)(dtab + to.interp), to.n_interp, n.interp, ctx->d_halfband, st));
+  HIP_TRY(mark(LLOID_STAGE_INTERP, 1));
+  HIP_TRY(mark(LLOID_STAGE_MIX, 0));
+  HIP_TRY(launch_mix_jobs(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.mix, n.entries, with_snr, phase_thr, st));
+  HIP_TRY(mark(LLOID_STAGE_MIX, 1));
+  return LLOID_OK;
+}
+// Filter one block of strain of one detector with every bank of `banks`
+// (same context, full rate and operand type) and compact the triggers.
+static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detector, const void *strain,
+                                 lloid_dtype sdt, int64_t n, const lloid_trigger_opts *opts, lloid_trigger *trig,
+                                 int64_t trig_cap, int64_t *n_trig, float *snr, lloid_peaks *peaks) {
+  if (!banks || nb <= 0 || !strain || !n_trig) return fail(LLOID_EINVAL, "NULL argument");
+  for (int i = 0; i < nb; ++i)
+    if (!banks[i]) return fail(LLOID_EINVAL, "bank %d is NULL", i);
+  lloid_ctx *ctx = banks[0]->ctx;
+  const int f0 = banks[0]->f0;
+  const lloid_dtype ct = banks[0]->compute;
+  for (int i = 1; i < nb; ++i) {
+    if (banks[i]->ctx != ctx) return fail(LLOID_EINVAL, "banks of one batch must share a context");
+    if (banks[i]->f0 != f0) return fail(LLOID_EINVAL, "banks of one batch must share the full rate");
+    if (banks[i]->compute != ct) return fail(LLOID_EINVAL, "banks of one batch must share the compute type");
+  }
   if (n <= 0) return fail(LLOID_EINVAL, "n must be positive");
+  if (n > (int64_t(1) << 29)) return fail(LLOID_EINVAL, "blocks longer than 2^29 samples must be split");
   if (sdt != LLOID_F64 && sdt != LLOID_F32) return fail(LLOID_EINVAL, "strain must be F64 or F32");
   if (trig_cap < 0 || (trig_cap > 0 && !trig)) return fail(LLOID_EINVAL, "bad trigger buffer");
+  if (snr && nb != 1) return fail(LLOID_EINVAL, "the SNR series output needs a single bank");
   int64_t num = 1, den = 1;
   float thr = 4.f, sscale = 1.f;
   if (opts) {
@@ -436,157 +498,201 @@ extern "C" lloid_status lloid_filter(lloid_bank *b, int32_t detector, const void
     if (opts->strain_scale != 0.f) sscale = opts->strain_scale;
   }
   if (num <= 0 || den <= 0) return fail(LLOID_EINVAL, "window length must be positive");
-  if ((int64_t)b->f0 * num < den) return fail(LLOID_EINVAL, "windows shorter than one sample");
+  if ((int64_t)f0 * num < den) return fail(LLOID_EINVAL, "windows shorter than one sample");
   if (!(sscale > 0.f) || !std::isfinite(sscale)) return fail(LLOID_EINVAL, "strain_scale must be positive");
   {
     int e;
     if (std::frexp((double)sscale, &e) != 0.5) return fail(LLOID_EINVAL, "strain_scale must be a power of two");
   }
-
-  lloid_ctx *ctx = b->ctx;
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
-  const Plan p = make_plan(b, n, num, den);
-  if (peaks && peaks->n_windows < p.n_windows && (peaks->snr || peaks->sample || peaks->phase)) {
-    int64_t need = p.n_windows;
-    peaks->n_windows = need;
-    return fail(LLOID_ETRUNC, "peak table needs %lld windows per template", (long long)need);
+
+  Windows win{(int64_t)f0 * num, den};
+  const int64_t W = win.count(n);
+  if (peaks)
+    for (int i = 0; i < nb; ++i)
+      if ((peaks[i].snr || peaks[i].sample || peaks[i].phase) && peaks[i].n_windows < W) {
+        peaks[i].n_windows = W;
+        return fail(LLOID_ETRUNC, "peak table of bank %d needs %lld windows per template", i, (long long)W);
+      }
+  int n_levels = 1;
+  for (int i = 0; i < nb; ++i) n_levels = std::max(n_levels, banks[i]->n_levels);
+  std::vector<Range> sup(n_levels);
+  sup[0] = {0, n};
+  for (int k = 1; k < n_levels; ++k) sup[k] = halo_up(sup[k - 1]);
+
+  // chunks of whole windows, sized so that every bank's operand fits the budget
+  const size_t esz = dtype_size(ct);
+  int64_t bytes_per_sample = 0;
+  for (int i = 0; i < nb; ++i) {
+    bytes_per_sample += banks[i]->kcat * (int64_t)esz;
+    for (const auto &sl : banks[i]->slices)
+      if (sl.level > 0) bytes_per_sample += (int64_t)sl.lp * 4 / sl.dec + 1;
   }
-  const int F = b->n_templates;
-  const size_t esz = dtype_size(b->compute);
+  const int64_t win_len = ceil_div(win.p, win.q);
+  int64_t wpc = std::max<int64_t>(1, ctx->chunk_budget / std::max<int64_t>(1, bytes_per_sample * win_len));
+  wpc = std::min(wpc, W);
+  const int64_t n_chunks = ceil_div(W, wpc);
+  const int64_t chunk_n = std::min<int64_t>(n, win.start(wpc) + 1);   // samples of the longest chunk
+
+  const TileShapes ts;
+
+  // ---- workspace layout
   const bool host_strain = !is_device_ptr(strain);
   const bool host_snr = snr && !is_device_ptr(snr);
-
-  // workspace layout
+  int64_t total_rows = 0;
+  for (int i = 0; i < nb; ++i) total_rows += banks[i]->n_templates;
+  const int64_t dev_cap = std::min<int64_t>(trig_cap, total_rows * W);
+  size_t n_fir = 0, n_int = 0;
+  for (int i = 0; i < nb; ++i)
+    for (const auto &sl : banks[i]->slices) {
+      ++n_fir;
+      if (sl.level > 0) ++n_int;
+    }
+  const size_t tab_bytes = (size_t)n_chunks * (n_fir * sizeof(FirJob) + n_int * sizeof(InterpJob) + nb * sizeof(MixJob) + 192) +
+                           nb * sizeof(TrigJob) + 256;
   size_t bytes = 0;
   auto add = [&](size_t cnt, size_t sz) { bytes = (size_t)round_up((int64_t)bytes, 256) + cnt * sz; };
   if (host_strain) add((size_t)n, dtype_size(sdt));
-  for (int k = 0; k < p.n_levels; ++k) add((size_t)p.sup[k].size(), 4);
-  size_t pp_elems = 0;
-  for (const auto &sl : b->slices)
-    if (sl.level > 0) {
-      add((size_t)p.need[sl.level].size() * sl.lp, 4);
-      for (int k = 1; k < sl.level; ++k) pp_elems = std::max(pp_elems, (size_t)p.need[k].size() * sl.lp);
-    }
-  add(pp_elems, 4);
-  add(pp_elems, 4);
-  add((size_t)n * b->kcat, esz);
-  const size_t table = (size_t)F * p.n_windows;
-  add(table, 4);
-  add(table, 8);
-  add(table, 4);
-  add((size_t)F + 2, 8);
+  for (int k = 0; k < n_levels; ++k) add((size_t)sup[k].size(), 4);
+  for (int i = 0; i < nb; ++i) {
+    const size_t tab = (size_t)banks[i]->n_templates * W;
+    add(tab, 4);
+    add(tab, 8);
+    add(tab, 4);
+    add((size_t)chunk_n * banks[i]->kcat, esz);
+    for (const auto &sl : banks[i]->slices)
+      if (sl.level > 0) add(olow_rows(chunk_n, sl.level) * sl.lp, 4);
+  }
+  add((size_t)total_rows + 2, 8);
   add(1, 4);
-  const int64_t dev_cap = std::min<int64_t>(trig_cap, (int64_t)table);
   add((size_t)std::max<int64_t>(dev_cap, 1), sizeof(lloid_trigger));
-  if (host_snr) add((size_t)F * n * 2, 4);
-  lloid_status rs = ensure_ws(b, bytes);
+  if (host_snr) add((size_t)n * 2 * banks[0]->n_templates, 4);
+  add(tab_bytes, 1);
+  lloid_status rs = ensure_ws(ctx, ctx->ws, bytes);
+  if (rs != LLOID_OK) return rs;
+  rs = ensure_pinned(ctx, ctx->pinned, ctx->pinned_bytes, tab_bytes);
   if (rs != LLOID_OK) return rs;
 
-  Carve cv{(char *)b->ws.base};
+  Carve cv{(char *)ctx->ws.base};
   const void *d_strain = strain;
-  if (ctx->profile) HIP_TRY(hipEventRecord(ctx->ev[2 * LLOID_STAGE_INGEST], st));
-  if (host_strain) {
-    void *tmp = cv.take<char>((size_t)n * dtype_size(sdt));
-    HIP_TRY(hipMemcpyAsync(tmp, strain, (size_t)n * dtype_size(sdt), hipMemcpyHostToDevice, st));
-    d_strain = tmp;
+  void *strain_tmp = host_strain ? cv.take<char>((size_t)n * dtype_size(sdt)) : nullptr;
+  std::vector<float *> xl(n_levels);
+  std::vector<LevelView> lv(n_levels);
+  for (int k = 0; k < n_levels; ++k) {
+    xl[k] = cv.take<float>((size_t)sup[k].size());
+    lv[k] = LevelView{xl[k], sup[k].lo, sup[k].size()};
   }
-  std::vector<float *> xl(p.n_levels);
-  for (int k = 0; k < p.n_levels; ++k) xl[k] = cv.take<float>((size_t)p.sup[k].size());
-  std::vector<float *> olow(b->slices.size(), nullptr);
-  for (size_t s = 0; s < b->slices.size(); ++s)
-    if (b->slices[s].level > 0) olow[s] = cv.take<float>((size_t)p.need[b->slices[s].level].size() * b->slices[s].lp);
-  float *pp[2] = {cv.take<float>(pp_elems), cv.take<float>(pp_elems)};
-  void *ocat = cv.take<char>((size_t)n * b->kcat * esz);
-  PeakArgs pa;
-  pa.peak_snr = cv.take<float>(table);
-  pa.peak_n = cv.take<int64_t>(table);
-  pa.peak_phase = cv.take<float>(table);
-  int64_t *counts = cv.take<int64_t>((size_t)F + 2);
-  int64_t *total = counts + F;
+  std::vector<BankBufs> bw(nb);
+  for (int i = 0; i < nb; ++i) {
+    const size_t tab = (size_t)banks[i]->n_templates * W;
+    bw[i].psnr = cv.take<float>(tab);
+    bw[i].pn = cv.take<int64_t>(tab);
+    bw[i].pphase = cv.take<float>(tab);
+    bw[i].ld_peak = W;
+    bw[i].w_base = 0;
+    bw[i].ocat = cv.take<char>((size_t)chunk_n * banks[i]->kcat * esz);
+    bw[i].olow.assign(banks[i]->slices.size(), nullptr);
+    for (size_t s = 0; s < banks[i]->slices.size(); ++s) {
+      const auto &sl = banks[i]->slices[s];
+      if (sl.level > 0) bw[i].olow[s] = cv.take<float>(olow_rows(chunk_n, sl.level) * sl.lp);
+    }
+  }
+  int64_t *counts = cv.take<int64_t>((size_t)total_rows + 2);
+  int64_t *total = counts + total_rows;
   int *bad = cv.take<int>(1);
   lloid_trigger *dtrig = cv.take<lloid_trigger>((size_t)std::max<int64_t>(dev_cap, 1));
-  float *dsnr = snr ? (host_snr ? cv.take<float>((size_t)F * n * 2) : snr) : nullptr;
-  pa.snr = dsnr;
-  pa.n_windows = p.n_windows;
-  pa.win_p = p.win_p;
-  pa.win_q = p.win_q;
+  float *dsnr = snr ? (host_snr ? cv.take<float>((size_t)n * 2 * banks[0]->n_templates) : snr) : nullptr;
+  char *dtab = cv.take<char>(tab_bytes);
 
+  // ---- descriptor tables of every chunk, uploaded in one copy
+  struct Chunk {
+    TabOffsets to;
+    StageItems items;
+  };
+  std::vector<Chunk> chunks(n_chunks);
+  char *htab = (char *)ctx->pinned;
+  size_t off = 0;
+  auto put = [&](const void *src, size_t sz) -> size_t {
+    off = (size_t)round_up((int64_t)off, 64);
+    const size_t at = off;
+    if (sz) std::memcpy(htab + off, src, sz);
+    off += sz;
+    return at;
+  };
+  for (int64_t c = 0; c < n_chunks; ++c) {
+    const int64_t wa = c * wpc, wb = std::min(W, wa + wpc);
+    const int64_t t0 = win.start(wa), t1 = std::min(n, win.start(wb));
+    std::vector<FirJob> fj;
+    std::vector<InterpJob> ij;
+    std::vector<MixJob> mj;
+    for (int i = 0; i < nb; ++i)
+      add_bank_jobs(banks[i], lv.data(), t0, t1, n, wa, wb, win, bw[i], 1.f / (banks[i]->mix_scale * sscale),
+                    (snr && i == 0) ? dsnr + t0 * 2 : nullptr, n, ts, fj, ij, mj);
+    number_jobs(fj, ij, mj, chunks[c].items);
+    TabOffsets &to = chunks[c].to;
+    to.fir = put(fj.data(), fj.size() * sizeof(FirJob));
+    to.interp = put(ij.data(), ij.size() * sizeof(InterpJob));
+    to.mix = put(mj.data(), mj.size() * sizeof(MixJob));
+    to.n_fir = (int)fj.size();
+    to.n_interp = (int)ij.size();
+    to.n_mix = (int)mj.size();
+  }
+  std::vector<TrigJob> tj(nb);
+  {
+    int64_t row = 0;
+    for (int i = 0; i < nb; ++i) {
+      tj[i] = TrigJob{bw[i].psnr, bw[i].pn, bw[i].pphase, W, 0, W, row, banks[i]->n_templates, i, detector, 0};
+      row += banks[i]->n_templates;
+    }
+  }
+  const size_t trig_off = put(tj.data(), tj.size() * sizeof(TrigJob));
+
+  // ---- launches
   auto mark = [&](int stage, int end) -> hipError_t {
     return ctx->profile ? hipEventRecord(ctx->ev[2 * stage + end], st) : hipSuccess;
   };
-  // 1. strain -> FP32 at full rate, zero outside [0, n)
+  HIP_TRY(mark(LLOID_STAGE_INGEST, 0));
+  HIP_TRY(hipMemcpyAsync(dtab, htab, off, hipMemcpyHostToDevice, st));
+  if (host_strain) {
+    HIP_TRY(hipMemcpyAsync(strain_tmp, strain, (size_t)n * dtype_size(sdt), hipMemcpyHostToDevice, st));
+    d_strain = strain_tmp;
+  }
   HIP_TRY(launch_fill_u8(bad, sizeof(int), st));
-  HIP_TRY(launch_convert(d_strain, sdt, n, xl[0], p.sup[0].lo, p.sup[0].size(), sscale, bad, st));
+  HIP_TRY(launch_convert(d_strain, sdt, n, xl[0], sup[0].lo, sup[0].size(), sscale, bad, st));
   HIP_TRY(mark(LLOID_STAGE_INGEST, 1));
-  // 2. half-band decimation to every level
   HIP_TRY(mark(LLOID_STAGE_DECIMATE, 0));
-  for (int k = 1; k < p.n_levels; ++k)
-    HIP_TRY(launch_decimate(xl[k - 1], p.sup[k - 1].lo, p.sup[k - 1].size(), xl[k], p.sup[k].lo, p.sup[k].size(),
+  for (int k = 1; k < n_levels; ++k)
+    HIP_TRY(launch_decimate(xl[k - 1], sup[k - 1].lo, sup[k - 1].size(), xl[k], sup[k].lo, sup[k].size(),
                             ctx->d_halfband, st));
   HIP_TRY(mark(LLOID_STAGE_DECIMATE, 1));
-  // 3. FIR bank per slice
-  HIP_TRY(mark(LLOID_STAGE_FIR, 0));
-  for (size_t s = 0; s < b->slices.size(); ++s) {
-    const SliceDev &sl = b->slices[s];
-    const int k = sl.level;
-    if (k == 0)
-      HIP_TRY(launch_fir(b->compute, sl, xl[0], p.sup[0].lo, p.sup[0].size(), 0, n, ocat, 0, b->kcat, sl.koff, sl.lp,
-                         st));
-    else
-      HIP_TRY(launch_fir(b->compute, sl, xl[k], p.sup[k].lo, p.sup[k].size(), p.need[k].lo, p.need[k].hi, olow[s],
-                         p.need[k].lo, sl.lp, 0, sl.lp, st));
+  const float phase_thr = (peaks && peaks[0].phase) ? -1.f : thr;
+  // with several chunks the per-stage events bracket the last chunk only
+  for (int64_t c = 0; c < n_chunks; ++c) {
+    const lloid_status r2 = launch_stages(ctx, ct, dtab, chunks[c].to, chunks[c].items, snr != nullptr, phase_thr,
+                                          c + 1 == n_chunks);
+    if (r2 != LLOID_OK) return r2;
   }
-  HIP_TRY(mark(LLOID_STAGE_FIR, 1));
-  // 4. interpolation of the low-rate orthogonal SNR to f0, into the concatenated operand
-  HIP_TRY(mark(LLOID_STAGE_INTERP, 0));
-  for (size_t s = 0; s < b->slices.size(); ++s) {
-    const SliceDev &sl = b->slices[s];
-    const int k = sl.level;
-    if (k == 0) continue;
-    const float *src = olow[s];
-    int64_t src_lo = p.need[k].lo, src_len = p.need[k].size();
-    int which = 0;
-    for (int j = k - 1; j >= 0; --j) {
-      if (j == 0) {
-        HIP_TRY(launch_interp(LLOID_F32, src, src_lo, src_len, sl.lp, b->compute, ocat, 0, n, b->kcat, sl.koff, sl.lp,
-                              ctx->d_halfband, st));
-      } else {
-        float *dst = pp[which];
-        HIP_TRY(launch_interp(LLOID_F32, src, src_lo, src_len, sl.lp, LLOID_F32, dst, p.need[j].lo, p.need[j].size(),
-                              sl.lp, 0, sl.lp, ctx->d_halfband, st));
-        src = dst;
-        src_lo = p.need[j].lo;
-        src_len = p.need[j].size();
-        which ^= 1;
-      }
-    }
-  }
-  HIP_TRY(mark(LLOID_STAGE_INTERP, 1));
-  // 5. mixing GEMM + complex SNR + per-window peaks
-  const float inv_scale = 1.f / (b->mix_scale * sscale);
-  HIP_TRY(mark(LLOID_STAGE_MIX, 0));
-  HIP_TRY(launch_mix_peak(b->compute, b->mix, b->rows, b->kcat, F, ocat, n, inv_scale, pa, st));
-  HIP_TRY(mark(LLOID_STAGE_MIX, 1));
-  // 6. trigger compaction
   HIP_TRY(mark(LLOID_STAGE_TRIGGER, 0));
-  HIP_TRY(launch_trigger_count(pa.peak_snr, F, p.n_windows, thr, counts, st));
-  HIP_TRY(launch_trigger_scan(counts, F, total, st));
-  HIP_TRY(launch_trigger_write(pa.peak_snr, pa.peak_n, pa.peak_phase, F, p.n_windows, thr, counts, dev_cap, 0,
-                               detector, dtrig, st));
+  HIP_TRY(launch_trigger_jobs((const TrigJob *)(dtab + trig_off), nb, total_rows, thr, counts, total, dev_cap, dtrig,
+                              st));
   HIP_TRY(mark(LLOID_STAGE_TRIGGER, 1));
   HIP_TRY(mark(LLOID_STAGE_D2H, 0));
   int64_t h_total = 0;
   int h_bad = 0;
   HIP_TRY(hipMemcpyAsync(&h_total, total, sizeof h_total, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(&h_bad, bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
-  if (peaks) {
-    if (peaks->snr) HIP_TRY(hipMemcpyAsync(peaks->snr, pa.peak_snr, table * 4, hipMemcpyDefault, st));
-    if (peaks->sample) HIP_TRY(hipMemcpyAsync(peaks->sample, pa.peak_n, table * 8, hipMemcpyDefault, st));
-    if (peaks->phase) HIP_TRY(hipMemcpyAsync(peaks->phase, pa.peak_phase, table * 4, hipMemcpyDefault, st));
-    peaks->n_windows = p.n_windows;
-  }
-  if (host_snr) HIP_TRY(hipMemcpyAsync(snr, dsnr, (size_t)F * n * 2 * 4, hipMemcpyDeviceToHost, st));
+  if (peaks)
+    for (int i = 0; i < nb; ++i) {
+      const size_t ld = (size_t)peaks[i].n_windows;   // the caller's rows may be wider than W
+      const size_t F = (size_t)banks[i]->n_templates;
+      if (peaks[i].snr) HIP_TRY(hipMemcpy2DAsync(peaks[i].snr, ld * 4, bw[i].psnr, W * 4, W * 4, F, hipMemcpyDefault, st));
+      if (peaks[i].sample) HIP_TRY(hipMemcpy2DAsync(peaks[i].sample, ld * 8, bw[i].pn, W * 8, W * 8, F, hipMemcpyDefault, st));
+      if (peaks[i].phase) HIP_TRY(hipMemcpy2DAsync(peaks[i].phase, ld * 4, bw[i].pphase, W * 4, W * 4, F, hipMemcpyDefault, st));
+      peaks[i].n_windows = W;
+    }
+  if (host_snr)
+    HIP_TRY(hipMemcpyAsync(snr, dsnr, (size_t)banks[0]->n_templates * n * 2 * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const int64_t ncopy = std::min(h_total, dev_cap);
   if (ncopy > 0) HIP_TRY(hipMemcpyAsync(trig, dtrig, (size_t)ncopy * sizeof(lloid_trigger), hipMemcpyDefault, st));
@@ -602,8 +708,31 @@ extern "C" lloid_status lloid_filter(lloid_bank *b, int32_t detector, const void
   }
   *n_trig = h_total;
   if (h_bad) return fail(LLOID_EDATA, "strain holds a non-finite sample");
-  if (h_total > trig_cap) return fail(LLOID_ETRUNC, "%lld triggers, buffer holds %lld", (long long)h_total,
-                                      (long long)trig_cap);
+  if (h_total > trig_cap)
+    return fail(LLOID_ETRUNC, "%lld triggers, buffer holds %lld", (long long)h_total, (long long)trig_cap);
   return LLOID_OK;
+}
+
+extern "C" lloid_status lloid_filter(lloid_bank *b, int32_t detector, const void *strain, lloid_dtype sdt, int64_t n,
+                                     const lloid_trigger_opts *opts, lloid_trigger *trig, int64_t trig_cap,
+                                     int64_t *n_trig, float *snr, lloid_peaks *peaks) {
+  ABI_GUARD_BEGIN
+  if (!b) return fail(LLOID_EINVAL, "NULL bank");
+  return filter_banks(&b, 1, detector, strain, sdt, n, opts, trig, trig_cap, n_trig, snr, peaks);
   ABI_GUARD_END
+}
+
+extern "C" lloid_status lloid_filter_batch(lloid_bank *const *banks, int32_t n_banks, int32_t detector,
+                                           const void *strain, lloid_dtype sdt, int64_t n,
+                                           const lloid_trigger_opts *opts, lloid_trigger *trig, int64_t trig_cap,
+                                           int64_t *n_trig, lloid_peaks *peaks) {
+  ABI_GUARD_BEGIN
+  return filter_banks(banks, n_banks, detector, strain, sdt, n, opts, trig, trig_cap, n_trig, nullptr, peaks);
+  ABI_GUARD_END
+}
+
+extern "C" lloid_status lloid_ctx_set_chunk_bytes(lloid_ctx *ctx, int64_t bytes) {
+  if (!ctx || bytes <= 0) return fail(LLOID_EINVAL, "bad argument");
+  ctx->chunk_budget = bytes;
+  return LLOID_OK;
 }

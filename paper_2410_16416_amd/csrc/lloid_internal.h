@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -18,15 +19,18 @@ constexpr int kHalfTaps = 2 * kHalfQ + 1;
 // GEMM tiling shared by the FIR and the mixing kernels (wave64, 4 waves).
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kBK = 32;          // K chunk staged in LDS
+constexpr int kBK = 32;          // K chunk staged in LDS (FIR; the concatenated K is a multiple of 64)
 constexpr int kLPad = 16;        // basis count padding inside the concatenated K
 constexpr int kRowTile = 32;     // MFMA 32x32 tile
 
-// Tile shapes: rows per workgroup = 32 * MT, columns = 4 waves * 32 * NT.
-constexpr int kFirMT = 2, kFirNT = 4;
-constexpr int kMixMT = 2, kMixNT = 4;
+// FIR: the four waves share 32 * kFirMT basis rows and split 4 * 32 * kFirNT
+// columns; the strain window of kFirKSup taps is staged in LDS at a time.
+constexpr int kFirMT = 4, kFirNT = 4, kFirKSup = 1024;
 constexpr int kFirBN = kWaves * 32 * kFirNT;
-constexpr int kMixBN = kWaves * 32 * kMixNT;
+// Mixing: waves arranged kMixWM x kMixWN, each 32 * kMixMT rows x 32 * kMixNT columns.
+constexpr int kMixMT = 4, kMixNT = 2, kMixWM = 2, kMixWN = 2;
+constexpr int kMixBM = 32 * kMixMT * kMixWM;
+constexpr int kMixBN = 32 * kMixNT * kMixWN;
 
 struct Range {
   int64_t lo = 0, hi = 0;  // absolute indices [lo, hi)
@@ -51,6 +55,49 @@ struct Workspace {
   size_t bytes = 0;
 };
 
+// ---- descriptor tables: one launch per stage covers every job of a batch ----
+// Work items of all jobs are numbered consecutively; job j owns items
+// [item0_j, item0_{j+1}).  Jobs are laid out longest item first.
+
+// FIR of one slice of one bank over output columns [k_lo, k_hi) at the slice rate.
+struct FirJob {
+  const void *basis;     // [rows][np] compute type, taps reversed
+  const float *x;        // decimated strain of the slice's level, absolute index x_lo at x[0]
+  void *out;             // column k goes to out[(k - out_lo) * ldo + col0 + l]
+  int64_t x_lo, x_len, base, k_lo, k_hi, out_lo, item0;
+  int rows, np, ldo, col0, col_limit, n_rtiles, n_ctiles, out_f32;
+};
+
+// Interpolation of one slice's low-rate orthogonal SNR to f0 into the operand.
+struct InterpJob {
+  const float *src;      // [src_len][ldw] FP32 at level `levels`, absolute row src_lo at src[0]
+  void *out;             // full-rate row n goes to out[(n - out_abs0) * ldo + col0 + c]
+  int64_t src_lo, src_len, out_abs0, n_out, item0;
+  int ldw, levels, ldo, col0, channels, n_rblocks, n_cblocks, pad;
+};
+
+// Mixing + peaks of one bank over trigger windows [w0, w0 + nw).
+struct MixJob {
+  const void *mix;       // [rows][kcat] compute type
+  const void *ocat;      // [..][kcat] compute type, absolute sample ocat_abs0 at row 0
+  float *peak_snr;       // [F][ld_peak], column w - w_base
+  int64_t *peak_n;
+  float *peak_phase;
+  float *snr;            // optional [F][snr_ld][2], column n - ocat_abs0
+  int64_t ocat_abs0, n_end, w0, nw, win_p, win_q, ld_peak, w_base, snr_ld, item0, e0;
+  float inv_scale;
+  int rows, kcat, n_templates, n_rtiles, pad;
+};
+
+// Trigger compaction over the peak table of one bank, windows [w_base, w_base + nw).
+struct TrigJob {
+  const float *snr;
+  const int64_t *peak_n;
+  const float *phase;
+  int64_t ld, w_base, nw, row0;   // row0: first (bank, template) row of this job
+  int n_templates, bank_id, detector, pad;
+};
+
 }  // namespace lloid
 
 struct lloid_ctx {
@@ -60,6 +107,10 @@ struct lloid_ctx {
   float *d_halfband = nullptr;  // device copy of g[n] (kHalfTaps floats)
   double halfband[lloid::kHalfTaps];
   int n_cu = 0;
+  lloid::Workspace ws;          // grow-only device scratch of filter calls on this context
+  void *pinned = nullptr;       // pinned host staging for descriptor tables
+  size_t pinned_bytes = 0;
+  int64_t chunk_budget = int64_t(6) << 30;  // device bytes of per-chunk operands
   bool profile = false;
   hipEvent_t ev[2 * LLOID_N_STAGES] = {};
   double stage_ms[LLOID_N_STAGES] = {};
@@ -77,7 +128,6 @@ struct lloid_bank {
   void *mix = nullptr;      // [rows][kcat] compute type
   std::vector<double> sigma2;
   int64_t device_bytes = 0;
-  lloid::Workspace ws;      // grow-only scratch reused by lloid_filter
 };
 
 namespace lloid {
@@ -87,36 +137,139 @@ hipError_t launch_convert(const void *src, lloid_dtype dt, int64_t n, float *dst
                           int64_t dst_len, float scale, int *bad, hipStream_t s);
 hipError_t launch_decimate(const float *u, int64_t u_lo, int64_t u_len, float *d, int64_t d_lo,
                            int64_t d_len, const float *g, hipStream_t s);
-// FIR: out[(k - out_lo) * ldo + col0 + l] = scale-free sum over taps, for k in [k_lo, k_hi).
-hipError_t launch_fir(lloid_dtype t, const SliceDev &sl, const float *x, int64_t x_lo, int64_t x_len,
-                      int64_t k_lo, int64_t k_hi, void *out, int64_t out_lo, int ldo, int col0,
-                      int col_limit, hipStream_t s);
-// One x2 interpolation stage: v[n] = sum_j w[j] 2 g[n - 2j] for n in [v_lo, v_lo + v_len);
-// w is [w_len][ldw] (fp32 or compute type), v is [v_len][ldv] (fp32 or compute type).
-hipError_t launch_interp(lloid_dtype in_t, const void *w, int64_t w_lo, int64_t w_len, int ldw,
-                         lloid_dtype out_t, void *v, int64_t v_lo, int64_t v_len, int ldv, int col0,
-                         int channels, const float *g, hipStream_t s);
-// Mixing GEMM over the concatenated basis with the fused per-window peak epilogue.
-struct PeakArgs {
-  float *peak_snr;      // [F][n_windows]
-  int64_t *peak_n;      // [F][n_windows]
-  float *peak_phase;    // [F][n_windows]
-  float *snr;           // optional [F][n][2]
-  int64_t n_windows, win_p, win_q;  // window w starts at floor(w * win_p / win_q)
-};
-hipError_t launch_mix_peak(lloid_dtype t, const void *mix, int rows, int kcat, int n_templates,
-                           const void *ocat, int64_t n, float inv_scale, const PeakArgs &pa,
-                           hipStream_t s);
+// Tile shapes (rows x columns per workgroup) of the FIR and mixing kernels in use.
+void fir_tile_shape(int *bm, int *bn);
+void mix_tile_shape(int *bm, int *bn);
+// One launch per stage over a device descriptor table (see the job structs).
+hipError_t launch_fir_jobs(lloid_dtype t, const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s);
+hipError_t launch_interp_jobs(lloid_dtype t, const InterpJob *jobs, int n_jobs, int64_t n_items, const float *g,
+                              hipStream_t s);
+// Mixing, peaks and the phase at peaks with |z| >= phase_thr (0 for the others).
+hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_items, int64_t n_entries,
+                           bool with_snr, float phase_thr, hipStream_t s);
+// Trigger compaction: counts, offsets and records (job-major, template, window).
+hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_rows, float thr, int64_t *counts,
+                               int64_t *total, int64_t cap, lloid_trigger *out, hipStream_t s);
 hipError_t launch_sigma2(const double *mix64, int n_templates, int lsum, const double *inv_dec_per_col,
                          double *out, hipStream_t s);
 hipError_t launch_fill_u8(void *p, size_t bytes, hipStream_t s);
-// Trigger compaction: counts, offsets and records (template-major, window-minor).
-hipError_t launch_trigger_count(const float *peak_snr, int n_templates, int64_t n_windows, float thr,
-                                int64_t *counts, hipStream_t s);
-hipError_t launch_trigger_scan(int64_t *counts, int n_templates, int64_t *total, hipStream_t s);
-hipError_t launch_trigger_write(const float *peak_snr, const int64_t *peak_n, const float *peak_phase,
-                                int n_templates, int64_t n_windows, float thr, const int64_t *offsets,
-                                int64_t cap, int32_t bank_id, int32_t detector, lloid_trigger *out,
-                                hipStream_t s);
+// ---- shared host helpers (lloid_host.cpp) ----
+lloid_status fail(lloid_status st, const char *fmt, ...);
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+inline int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+inline int64_t ceil_div(int64_t a, int64_t b) { return -floor_div(-a, b); }
+
+inline size_t dtype_size(lloid_dtype t) {
+  switch (t) {
+    case LLOID_F64: return 8;
+    case LLOID_F32: return 4;
+    case LLOID_F16: return 2;
+    case LLOID_BF16: return 2;
+  }
+  return 0;
+}
+
+inline bool is_device_ptr(const void *p) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+// interpolation reads w[j] with |n - 2j| <= Q and decimation reads u[2k - m]
+// with |m| <= Q: the range a level needs from the one above it
+inline Range halo_up(Range r) { return {ceil_div(r.lo - kHalfQ, 2), floor_div(r.hi - 1 + kHalfQ, 2) + 1}; }
+
+inline std::vector<Range> need_ranges(int64_t t0, int64_t t1, int n_levels) {
+  std::vector<Range> need(n_levels);
+  need[0] = {t0, t1};
+  for (int k = 1; k < n_levels; ++k) need[k] = halo_up(need[k - 1]);
+  return need;
+}
+
+// Trigger windows: window w starts at floor(w p / q).
+struct Windows {
+  int64_t p = 1, q = 1;
+  int64_t start(int64_t w) const { return (w * p) / q; }
+  int64_t count(int64_t n) const { return ceil_div(n * q, p); }   // windows intersecting [0, n)
+};
+
+struct Carve {
+  char *base;
+  size_t off = 0;
+  template <typename T> T *take(size_t count) {
+    off = (size_t)round_up((int64_t)off, 256);
+    T *r = (T *)(base + off);
+    off += count * sizeof(T);
+    return r;
+  }
+};
+
+struct LevelView {
+  const float *x;
+  int64_t lo, len;
+};
+
+// Per (bank, detector) buffers of one chunk of windows.
+struct BankBufs {
+  void *ocat = nullptr;            // [chunk samples][kcat]
+  std::vector<float *> olow;       // per slice at level > 0: [olow_rows][lp]
+  float *psnr = nullptr, *pphase = nullptr;
+  int64_t *pn = nullptr;
+  int64_t ld_peak = 0, w_base = 0; // peak tables [F][ld_peak], column w - w_base
+};
+
+struct TileShapes {
+  int fbm, fbn, mbm, mbn;
+  TileShapes() {
+    fir_tile_shape(&fbm, &fbn);
+    mix_tile_shape(&mbm, &mbn);
+  }
+};
+
+struct StageItems {
+  int64_t fir = 0, interp = 0, mix = 0, entries = 0;
+};
+
+struct TabOffsets {
+  size_t fir = 0, interp = 0, mix = 0;
+  int n_fir = 0, n_interp = 0, n_mix = 0;
+};
+
+lloid_status ensure_ws(lloid_ctx *ctx, Workspace &ws, size_t bytes);
+lloid_status ensure_pinned(lloid_ctx *ctx, void *&p, size_t &have, size_t bytes);
+size_t olow_rows(int64_t t_len, int level);
+// Append the FIR, interpolation and mixing jobs of bank b for output samples
+// [t0, t1) (windows [wa, wb), data ending at n_end) to the tables.
+void add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, int64_t t1, int64_t n_end, int64_t wa,
+                   int64_t wb, const Windows &win, const BankBufs &bb, float inv_scale, float *snr, int64_t snr_ld,
+                   const TileShapes &ts, std::vector<FirJob> &fj, std::vector<InterpJob> &ij,
+                   std::vector<MixJob> &mj);
+// Sort longest-first and number the work items.
+void number_jobs(std::vector<FirJob> &fj, std::vector<InterpJob> &ij, std::vector<MixJob> &mj, StageItems &n);
+// FIR, interpolation and mixing launches over uploaded tables.
+lloid_status launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dtab, const TabOffsets &to,
+                           const StageItems &n, bool with_snr, float phase_thr, bool mark_stages);
 
 }  // namespace lloid
+
+#define HIP_TRY(expr)                                                                              \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      return lloid::fail(LLOID_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),     \
+                         __FILE__, __LINE__);                                                      \
+  } while (0)
+
+#define ABI_GUARD_BEGIN try {
+#define ABI_GUARD_END                                                     \
+  }                                                                       \
+  catch (const std::bad_alloc &) {                                        \
+    return lloid::fail(LLOID_ENOMEM, "host allocation failed");           \
+  }                                                                       \
+  catch (const std::exception &ex) {                                      \
+    return lloid::fail(LLOID_EINVAL, "internal error: %s", ex.what());    \
+  }

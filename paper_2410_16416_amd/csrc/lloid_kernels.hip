@@ -11,6 +11,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "lloid_internal.h"
 
@@ -57,7 +58,17 @@ template <> struct Op<float> {
   static __device__ __forceinline__ float tof(float v) { return v; }
 };
 
-template <typename T> struct OutT { typedef T type; };
+// Job owning flat work item `item`: the last job with item0 <= item.
+template <typename J>
+__device__ __forceinline__ int find_job(const J *__restrict__ jobs, int n_jobs, int64_t item) {
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].item0 <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 // ---------------------------------------------------------- small kernels
 
@@ -92,31 +103,95 @@ __global__ void k_decimate(const float *__restrict__ u, int64_t u_lo, int64_t u_
   d[t] = acc;
 }
 
-template <typename TI, typename TO>
-__global__ void k_interp(const TI *__restrict__ w, int64_t w_lo, int64_t w_len, int ldw, TO *__restrict__ v,
-                         int64_t v_lo, int64_t v_len, int ldv, int col0, int channels,
-                         const float *__restrict__ g) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t row = t / channels;
-  int c = (int)(t - row * channels);
-  if (row >= v_len) return;
-  int64_t n = v_lo + row;
-  float acc;
-  if ((n & 1) == 0) {
-    int64_t j = (n >> 1) - w_lo;
-    acc = (j >= 0 && j < w_len) ? (float)w[j * ldw + c] : 0.f;
-  } else {
-    // odd n: v[n] = sum_j w[j] 2 g[n - 2j] over |n - 2j| <= 31
-    acc = 0.f;
-    int64_t jc = (n - 1) >> 1;  // n - 2 jc = 1
-    for (int q = 0; q < kHalfQ / 2; ++q) {
-      int64_t ja = jc - q - w_lo, jb = jc + 1 + q - w_lo;  // offsets n-2j = 1+2q and -(1+2q)
-      float a = (ja >= 0 && ja < w_len) ? (float)w[ja * ldw + c] : 0.f;
-      float b = (jb >= 0 && jb < w_len) ? (float)w[jb * ldw + c] : 0.f;
-      acc += 2.f * g[kHalfQ + 1 + 2 * q] * (a + b);
+// Interpolation of one slice's low-rate orthogonal SNR up to the full rate:
+// `levels` cascaded x2 stages v[n] = sum_j w[j] 2 g[n - 2j], intermediate
+// rates held in LDS.  A workgroup owns 128 full-rate rows x 32 channels; the
+// index range it needs at each level follows from |n - 2j| <= 32.
+constexpr int kIcRows = 128, kIcChan = 32, kIcMaxRows = 100;
+
+__device__ __forceinline__ int64_t ceil_half(int64_t a) { return a >= 0 ? (a + 1) / 2 : -((-a) / 2); }
+__device__ __forceinline__ int64_t floor_half(int64_t a) { return a >= 0 ? a / 2 : -((-a + 1) / 2); }
+
+// One x2 interpolation stage on a workgroup's LDS rows: input rows [0, irows)
+// hold level j+1 from absolute index ilo, outputs are level-j rows [0, orows)
+// from absolute index olo.  Outputs come in pairs (2q, 2q+1):
+//   v[2q] = w[q],  v[2q+1] = sum_t 2 g[2t+1] (w[q - t] + w[q + 1 + t]),
+// and each thread produces QB consecutive pairs from one register window.
+// Valid outputs only read valid input rows (the ranges come from |n - 2j| <= 32),
+// so reads are clamped rather than branched and stores are predicated.
+template <int QB, int H, typename Store>
+__device__ __forceinline__ void interp_pairs(const float (*in)[kIcChan + 1], int irows, int64_t ilo, int64_t olo,
+                                             int orows, const float *taps, int c, int rg, int groups, Store store) {
+  const int64_t q0 = floor_half(olo);
+  const int nq = (int)(floor_half(olo + orows - 1) - q0) + 1;
+  const int qoff = (int)(q0 - ilo);      // input row of q0
+  const int e0 = (int)(2 * q0 - olo);    // output row of 2 q0 (0 or -1)
+  for (int qb = rg * QB; qb < nq; qb += groups * QB) {
+    float win[QB + 2 * H];
+#pragma unroll
+    for (int t = 0; t < QB + 2 * H; ++t) {
+      int row = qoff + qb - (H - 1) + t;
+      row = row < 0 ? 0 : (row >= irows ? irows - 1 : row);
+      win[t] = in[row][c];
+    }
+#pragma unroll
+    for (int u = 0; u < QB; ++u) {
+      float odd = 0.f;
+#pragma unroll
+      for (int t = 0; t < H; ++t) odd += taps[t] * (win[u + (H - 1) - t] + win[u + H + t]);
+      const int re = e0 + 2 * (qb + u);
+      if (re >= 0 && re < orows) store(re, win[u + (H - 1)]);
+      if (re + 1 >= 0 && re + 1 < orows) store(re + 1, odd);
     }
   }
-  v[row * (int64_t)ldv + col0 + c] = (TO)acc;
+}
+
+template <typename TO>
+__global__ __launch_bounds__(256) void k_interp_cascade(const InterpJob *__restrict__ jobs, int n_jobs,
+                                                        const float *__restrict__ g) {
+  constexpr int RG = 256 / kIcChan;           // row groups
+  constexpr int H = kHalfQ / 2;               // odd taps on each side
+  __shared__ float buf[2][kIcMaxRows][kIcChan + 1];
+  __shared__ float taps[H];
+  const InterpJob &jb = jobs[find_job(jobs, n_jobs, blockIdx.x)];
+  const int64_t li = (int64_t)blockIdx.x - jb.item0;
+  const int levels = jb.levels, ldw = jb.ldw, channels = jb.channels;
+  const int64_t n0 = (li % jb.n_rblocks) * kIcRows;           // relative to out_abs0
+  const int c0 = (int)(li / jb.n_rblocks) * kIcChan;
+  int64_t lo[8], hi[8];
+  lo[0] = jb.out_abs0 + n0;
+  hi[0] = jb.out_abs0 + (n0 + kIcRows < jb.n_out ? n0 + kIcRows : jb.n_out);
+  for (int j = 1; j <= levels; ++j) {
+    lo[j] = ceil_half(lo[j - 1] - kHalfQ);
+    hi[j] = floor_half(hi[j - 1] - 1 + kHalfQ) + 1;
+  }
+  if (threadIdx.x < H) taps[threadIdx.x] = 2.f * g[kHalfQ + 1 + 2 * threadIdx.x];
+  const int c = threadIdx.x % kIcChan, rg = threadIdx.x / kIcChan;
+  const bool cok = c0 + c < channels;
+  {
+    const int rows = (int)(hi[levels] - lo[levels]);
+    const int64_t j0 = lo[levels] - jb.src_lo;
+    const float *src = jb.src;
+    for (int r = rg; r < rows; r += RG) {
+      const int64_t j = j0 + r;
+      buf[0][r][c] = (cok && j >= 0 && j < jb.src_len) ? src[j * ldw + c0 + c] : 0.f;
+    }
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int lev = levels - 1; lev >= 1; --lev) {
+    float (*dst)[kIcChan + 1] = buf[cur ^ 1];
+    interp_pairs<4, H>(buf[cur], (int)(hi[lev + 1] - lo[lev + 1]), lo[lev + 1], lo[lev], (int)(hi[lev] - lo[lev]), taps,
+                       c, rg, RG, [&](int r, float v) { dst[r][c] = v; });
+    __syncthreads();
+    cur ^= 1;
+  }
+  TO *o = (TO *)jb.out + n0 * (int64_t)jb.ldo + jb.col0 + c0 + c;
+  const int64_t ldo = jb.ldo;
+  interp_pairs<4, H>(buf[cur], (int)(hi[1] - lo[1]), lo[1], lo[0], (int)(hi[0] - lo[0]), taps, c, rg, RG,
+                     [&](int r, float v) {
+                       if (cok) o[r * ldo] = (TO)v;
+                     });
 }
 
 template <typename T>
@@ -144,49 +219,92 @@ __global__ void k_sigma2(const double *__restrict__ m, int n_templates, int lsum
 
 // ------------------------------------------------------------ GEMM pieces
 
-// Stage rows [r0, r0 + 32 MT) x k [k0, k0 + kBK) of a row-major [rows][ld]
-// matrix into LDS (row pitch kBK + pad elements), zero past `rows`.
-template <typename T, int BM, int PITCH>
-__device__ __forceinline__ void stage_rows(const T *__restrict__ a, int64_t rows, int64_t ld, int64_t r0,
-                                           int k0, T *lds) {
-  constexpr int VPR = kBK * (int)sizeof(T) / 16;  // 16-byte vectors per row
-  constexpr int NV = BM * VPR;
-  for (int v = threadIdx.x; v < NV; v += kThreads) {
-    int r = v / VPR, c = v % VPR;
-    uint4 val = make_uint4(0, 0, 0, 0);
-    if (r0 + r < rows) val = *(const uint4 *)(a + (r0 + r) * ld + k0 + c * (16 / (int)sizeof(T)));
-    *(uint4 *)(lds + r * PITCH + c * (16 / (int)sizeof(T))) = val;
-  }
+template <typename T, int BK = kBK> struct Pitch {
+  // row pitch of an LDS tile in elements: +16 bytes keeps the 16-byte fragment
+  // reads of 8 consecutive rows on distinct banks; FP32 fragments are single
+  // words, so one extra word per row does the same
+  static constexpr int value = sizeof(T) == 4 ? BK + 1 : BK + 16 / (int)sizeof(T);
+};
+
+// Buffer resource over `bytes` bytes from `base`: loads past the end (or at
+// negative offsets, which wrap to huge unsigned ones) return zero in hardware.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, int64_t bytes) {
+  const int nb = bytes <= 0 ? 0 : (bytes > 0x7ffffff0 ? 0x7ffffff0 : (int)bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, nb, 0x00020000);
 }
 
-template <typename T> struct Pitch {
-  // +16 bytes per row keeps the 16-byte fragment reads of 32 lanes spread over banks
-  static constexpr int value = kBK + 16 / (int)sizeof(T);
+// Register-staged copy of a [ROWS][BK] chunk of a row-major matrix through a
+// buffer resource: setup() fixes each thread's byte offsets, load(k0) issues
+// the 16-byte global reads for columns [k0, k0 + BK) (rows past the resource
+// read as zero), store() writes them to LDS.
+template <typename T, int ROWS, int BK = kBK, int THREADS = kThreads> struct ChunkLoader {
+  static constexpr int EPV = 16 / (int)sizeof(T);   // elements per 16-byte vector
+  static constexpr int VPR = BK / EPV;               // vectors per row
+  static constexpr int NV = ROWS * VPR;
+  static constexpr int PER = (NV + THREADS - 1) / THREADS;
+  uint4 r[PER];
+  int voff[PER];
+
+  __device__ __forceinline__ void setup(int ld) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int v = threadIdx.x + p * THREADS;
+      voff[p] = v < NV ? ((v / VPR) * ld + (v % VPR) * EPV) * (int)sizeof(T) : 0x7ffffff0;
+    }
+  }
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, int soff_bytes) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[p], soff_bytes, 0);
+      r[p] = make_uint4(v[0], v[1], v[2], v[3]);
+    }
+  }
+  __device__ __forceinline__ void store(T *lds) const {
+    constexpr int P = Pitch<T, BK>::value;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int v = threadIdx.x + p * THREADS;
+      if (NV % THREADS != 0 && v >= NV) break;
+      const int row = v / VPR, c = v % VPR;
+      if constexpr (sizeof(T) == 4) {
+        float *d = (float *)lds + row * P + c * 4;
+        d[0] = __uint_as_float(r[p].x);
+        d[1] = __uint_as_float(r[p].y);
+        d[2] = __uint_as_float(r[p].z);
+        d[3] = __uint_as_float(r[p].w);
+      } else {
+        *(uint4 *)(lds + row * P + c * EPV) = r[p];
+      }
+    }
+  }
 };
 
 // ---------------------------------------------------------------- FIR
 // o[l, k] = sum_m U[l, m] x[k - J/D - m] as D = A B with A = taps reversed
 // (Ar[l, m'] = U[l, N-1-m']) and the Hankel operand B[m', k] = x[k + m' + base],
-// base = -(J/D + N - 1).  The strain window of a K chunk sits in LDS as VEC
-// copies shifted by 0..VEC-1 samples, so every lane's VEC consecutive samples
-// are one aligned read whatever its column.
-template <typename T, typename TO, int MT, int NT>
-__global__ __launch_bounds__(kThreads) void k_fir(const T *__restrict__ a, int64_t rows, int np,
-                                                  const float *__restrict__ x, int64_t x_lo, int64_t x_len,
-                                                  int64_t base, int64_t k_lo, int64_t k_hi,
-                                                  TO *__restrict__ out, int64_t out_lo, int ldo, int col0,
-                                                  int col_limit) {
+// base = -(J/D + N - 1).  The four waves share the basis rows of the
+// workgroup and split its columns.  The strain window of kFirKSup taps sits
+// in LDS as VEC copies shifted by 0..VEC-1 samples, so every lane's VEC
+// consecutive samples are one aligned read whatever its column; the basis
+// streams through double-buffered LDS with the next chunk's global reads in
+// flight during the current chunk's MFMAs.
+template <typename T, int MT, int NT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs, int n_jobs) {
   typedef Op<T> O;
-  constexpr int BM = 32 * MT, BN = kWaves * 32 * NT;
-  constexpr int AP = Pitch<T>::value;
-  constexpr int WC = BN + kBK + 8;  // copy length (multiple of 8)
-  __shared__ __attribute__((aligned(16))) T As[BM * AP];
+  constexpr int THREADS = 64 * NW;
+  constexpr int BM = 32 * MT, BN = NW * 32 * NT;
+  constexpr int P = Pitch<T>::value;
+  constexpr int WC = BN + kFirKSup + 16;
+  __shared__ __attribute__((aligned(16))) T As[2][BM * P];
   __shared__ __attribute__((aligned(16))) T Bc[O::VEC * WC];
-  __shared__ float raw[WC + 8];
 
+  const FirJob &jb = jobs[find_job(jobs, n_jobs, blockIdx.x)];
+  const int64_t li = (int64_t)blockIdx.x - jb.item0;
+  const int rows = jb.rows, np = jb.np;
+  const T *a = (const T *)jb.basis;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)blockIdx.y * BM;
-  const int64_t i0 = k_lo + (int64_t)blockIdx.x * BN;
+  const int64_t r0 = (li % jb.n_rtiles) * BM;
+  const int64_t i0 = jb.k_lo + (li / jb.n_rtiles) * BN;
 
   f32x16 acc[MT][NT];
 #pragma unroll
@@ -196,32 +314,43 @@ __global__ __launch_bounds__(kThreads) void k_fir(const T *__restrict__ a, int64
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[mt][nt][e] = 0.f;
 
-  for (int kc = 0; kc < np; kc += kBK) {
-    __syncthreads();
-    stage_rows<T, BM, AP>(a, rows, np, r0, kc, As);
-    const int64_t w0 = i0 + kc + base - x_lo;  // buffer index of window sample 0
-    for (int t = threadIdx.x; t < WC + 8; t += kThreads) {
-      int64_t idx = w0 + t;
-      raw[t] = (idx >= 0 && idx < x_len) ? x[idx] : 0.f;
+  // basis rows [r0, rows) of this workgroup; strain samples [0, x_len)
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(a + r0 * np, (rows - r0) * (int64_t)np * (int64_t)sizeof(T));
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(jb.x, jb.x_len * 4);
+  const int64_t x_len = jb.x_len;
+  ChunkLoader<T, BM, kBK, THREADS> la;
+  la.setup(np);
+  la.load(ra, 0);
+  const int nchunks = np / kBK;
+  // lane's shifted copy: its column offset within a fragment is constant mod VEC
+  const int lr = (lane & 31) % O::VEC;
+  const T *bl = Bc + lr * WC + (wave * NT * 32 + (lane & 31) + (lane >> 5) * O::VEC - lr);
+  int ksup = 0;
+  for (int c = 0; c < nchunks; ++c) {
+    const int cur = c & 1, kc = c * kBK;
+    if (kc % kFirKSup == 0) {
+      // new strain window for taps [kc, kc + kFirKSup); out-of-range samples read as zero
+      if (c > 0) __syncthreads();
+      ksup = kc;
+      const int64_t w0 = i0 + kc + jb.base - jb.x_lo;
+      for (int e = threadIdx.x; e < O::VEC * WC; e += THREADS) {
+        const int r = e / WC, t = e - r * WC;
+        const int64_t idx = w0 + t + r;
+        const int off = (idx >= 0 && idx < x_len) ? (int)idx * 4 : -4;
+        Bc[e] = O::cvt(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, off, 0, 0)));
+      }
     }
+    la.store(As[cur]);
     __syncthreads();
-    for (int e = threadIdx.x; e < O::VEC * WC; e += kThreads) {
-      int r = e / WC, t = e - r * WC;
-      Bc[e] = O::cvt(raw[t + r]);
-    }
-    __syncthreads();
+    if (c + 1 < nchunks) la.load(ra, (kc + kBK) * (int)sizeof(T));
 #pragma unroll
     for (int ks = 0; ks < kBK / O::KS; ++ks) {
       typename O::vec af[MT], bf[NT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
-        af[mt] = *(const typename O::vec *)(As + (mt * 32 + (lane & 31)) * AP + ks * O::KS + (lane >> 5) * O::VEC);
+        af[mt] = *(const typename O::vec *)(As[cur] + (mt * 32 + (lane & 31)) * P + ks * O::KS + (lane >> 5) * O::VEC);
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        int pos = wave * NT * 32 + nt * 32 + (lane & 31) + ks * O::KS + (lane >> 5) * O::VEC;
-        int r = pos % O::VEC;
-        bf[nt] = *(const typename O::vec *)(Bc + r * WC + (pos - r));
-      }
+      for (int nt = 0; nt < NT; ++nt) bf[nt] = *(const typename O::vec *)(bl + (kc - ksup) + nt * 32 + ks * O::KS);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -229,20 +358,29 @@ __global__ __launch_bounds__(kThreads) void k_fir(const T *__restrict__ a, int64
     }
   }
 
-  // store: lane holds column i, rows rb..rb+3 for each group of four
+  // store: lane holds column i, rows rb..rb+3 for each group of four; lower-rate
+  // slices keep FP32 for the interpolation, level-0 slices write the operand type
+  const int col_limit = jb.col_limit, ldo = jb.ldo;
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
-    int64_t col = i0 + wave * NT * 32 + nt * 32 + (lane & 31);
-    if (col >= k_hi) continue;
-    TO *orow = out + (col - out_lo) * (int64_t)ldo + col0;
+    const int64_t col = i0 + wave * NT * 32 + nt * 32 + (lane & 31);
+    if (col >= jb.k_hi) continue;
+    const int64_t ro = (col - jb.out_lo) * (int64_t)ldo + jb.col0;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        int rb = (int)r0 + mt * 32 + 8 * g + 4 * (lane >> 5);
+        const int rb = (int)r0 + mt * 32 + 8 * g + 4 * (lane >> 5);
         if (rb + 4 <= col_limit) {
+          if (jb.out_f32) {
+            float *o = (float *)jb.out + ro + rb;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) orow[rb + q] = (TO)acc[mt][nt][4 * g + q];
+            for (int q = 0; q < 4; ++q) o[q] = acc[mt][nt][4 * g + q];
+          } else {
+            T *o = (T *)jb.out + ro + rb;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[q] = O::cvt(acc[mt][nt][4 * g + q]);
+          }
         }
       }
   }
@@ -251,53 +389,74 @@ __global__ __launch_bounds__(kThreads) void k_fir(const T *__restrict__ a, int64
 // ------------------------------------------------------- mixing + peaks
 // Y[c, n] = sum_k M[c, k] O[n, k] over the concatenated basis; rows 2i and
 // 2i+1 (cos, sin) of template i land in the same lane, so |z|^2 and the
-// running per-template peak stay in registers.  One workgroup owns whole
-// trigger windows of one row tile: the peak of a window is reduced across
-// lanes and waves without atomics (larger |z|^2 first, then lower sample).
-struct Best {
-  float v, re, im;
-  int n;
-};
-
+// running per-template peak (value, sample) stay in registers.  One
+// workgroup owns whole trigger windows of one row tile: the peak of a
+// window is reduced across lanes and waves without atomics (larger |z|^2
+// first, then lower sample).  The phase at the peak is recomputed by
+// k_peak_phase from the same operands.
 __device__ __forceinline__ bool better(float va, int na, float vb, int nb) {
   return va > vb || (va == vb && na < nb);
 }
 
-template <typename T, int MT, int NT>
-__global__ __launch_bounds__(kThreads) void k_mix_peak(const T *__restrict__ mix, int rows, int kcat,
-                                                       int n_templates, const T *__restrict__ ocat,
-                                                       int64_t n, float inv_scale, PeakArgs pa,
-                                                       int n_rtiles, int64_t n_wgroups) {
-  typedef Op<T> O;
-  constexpr int BM = 32 * MT, BN = kWaves * 32 * NT;
-  constexpr int P = Pitch<T>::value;
-  __shared__ __attribute__((aligned(16))) T As[BM * P];
-  __shared__ __attribute__((aligned(16))) T Bs[BN * P];
-  __shared__ Best red[kWaves][BM / 2];
+struct VN {
+  float v;
+  int n;
+};
 
-  // XCD-aware order: the 8 XCDs take workgroups round-robin, so give all row
-  // tiles of one window the same XCD and neighbouring slots (shared O rows in L2).
-  const int64_t b = blockIdx.x;
+template <typename T, int MT, int NT, int WM, int WN, int BK, bool SNR>
+__global__ __launch_bounds__(64 * WM * WN) void k_mix_peak(const MixJob *__restrict__ jobs, int n_jobs) {
+  typedef Op<T> O;
+  constexpr int THREADS = 64 * WM * WN;
+  constexpr int BM = 32 * MT * WM, BN = 32 * NT * WN;
+  constexpr int P = Pitch<T, BK>::value;
+  __shared__ __attribute__((aligned(16))) T As[2][BM * P];
+  __shared__ __attribute__((aligned(16))) T Bs[2][BN * P];
+  __shared__ VN red[WN][BM / 2];
+
+  const MixJob &jb = jobs[find_job(jobs, n_jobs, blockIdx.x)];
+  // XCD-aware order: the 8 XCDs take workgroups round-robin (every job's items
+  // start at a multiple of 8), so give all row tiles of one window the same
+  // XCD and neighbouring slots (shared operand rows in that XCD's L2).
+  const int64_t b = (int64_t)blockIdx.x - jb.item0;
   const int xcd = (int)(b & 7);
   const int64_t slot = b >> 3;
+  const int n_rtiles = jb.n_rtiles;
   const int rt = (int)(slot % n_rtiles);
-  const int64_t wgrp = slot / n_rtiles;
-  const int64_t w = wgrp * 8 + xcd;
-  if (w >= pa.n_windows) return;
+  const int64_t wl = (slot / n_rtiles) * 8 + xcd;   // window within the job
+  if (wl >= jb.nw) return;
+  const int64_t w = jb.w0 + wl;
+  const T *mix = (const T *)jb.mix;
+  const int rows = jb.rows, kcat = jb.kcat, n_templates = jb.n_templates;
+  const float inv_scale = jb.inv_scale;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WN, wn = wave % WN;
   const int64_t r0 = (int64_t)rt * BM;
-  const int64_t ws = (w * pa.win_p) / pa.win_q;
-  int64_t we = ((w + 1) * pa.win_p) / pa.win_q;
-  if (we > n) we = n;
-
-  Best best[MT][8];
+  const int64_t ws = (w * jb.win_p) / jb.win_q;
+  int64_t we = ((w + 1) * jb.win_p) / jb.win_q;
+  if (we > jb.n_end) we = jb.n_end;
+  const T *ocat = (const T *)jb.ocat + (ws - jb.ocat_abs0) * (int64_t)kcat;   // row of sample ws
+  VN best[MT][8];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int p = 0; p < 8; ++p) best[mt][p] = Best{-1.f, 0.f, 0.f, 0x7fffffff};
+    for (int p = 0; p < 8; ++p) best[mt][p] = VN{-1.f, 0x7fffffff};
 
+  // mixing rows [r0, rows) and operand rows [ws, we) of this workgroup; rows
+  // past either end read as zero
+  constexpr int ESZ = (int)sizeof(T);
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(mix + r0 * kcat, (rows - r0) * (int64_t)kcat * ESZ);
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(ocat, (we - ws) * (int64_t)kcat * ESZ);
+  const int nchunks = kcat / BK;
+  ChunkLoader<T, BM, BK, THREADS> la;
+  ChunkLoader<T, BN, BK, THREADS> lb;
+  la.setup(kcat);
+  lb.setup(kcat);
+  la.load(ra, 0);
+  lb.load(rb, 0);
+  int it = 0;  // chunk counter across column steps: LDS buffer parity
   for (int64_t n0 = ws; n0 < we; n0 += BN) {
+    const int brow = (int)(n0 - ws) * kcat * ESZ;   // byte offset of this step's first operand row
     f32x16 acc[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -306,20 +465,28 @@ __global__ __launch_bounds__(kThreads) void k_mix_peak(const T *__restrict__ mix
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[mt][nt][e] = 0.f;
 
-    for (int kc = 0; kc < kcat; kc += kBK) {
+    for (int c = 0; c < nchunks; ++c, ++it) {
+      const int cur = it & 1;
+      la.store(As[cur]);
+      lb.store(Bs[cur]);
       __syncthreads();
-      stage_rows<T, BM, P>(mix, rows, kcat, r0, kc, As);
-      stage_rows<T, BN, P>(ocat + n0 * (int64_t)kcat, we - n0, kcat, 0, kc, Bs);
-      __syncthreads();
+      if (c + 1 < nchunks) {
+        la.load(ra, (c + 1) * BK * ESZ);
+        lb.load(rb, brow + (c + 1) * BK * ESZ);
+      } else if (n0 + BN < we) {
+        la.load(ra, 0);
+        lb.load(rb, brow + BN * kcat * ESZ);
+      }
 #pragma unroll
-      for (int ks = 0; ks < kBK / O::KS; ++ks) {
+      for (int ks = 0; ks < BK / O::KS; ++ks) {
         typename O::vec af[MT], bf[NT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
-          af[mt] = *(const typename O::vec *)(As + (mt * 32 + (lane & 31)) * P + ks * O::KS + (lane >> 5) * O::VEC);
+          af[mt] = *(const typename O::vec *)(As[cur] + (wm * 32 * MT + mt * 32 + (lane & 31)) * P + ks * O::KS +
+                                             (lane >> 5) * O::VEC);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
-          bf[nt] = *(const typename O::vec *)(Bs + (wave * NT * 32 + nt * 32 + (lane & 31)) * P + ks * O::KS +
+          bf[nt] = *(const typename O::vec *)(Bs[cur] + (wn * 32 * NT + nt * 32 + (lane & 31)) * P + ks * O::KS +
                                              (lane >> 5) * O::VEC);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -331,58 +498,95 @@ __global__ __launch_bounds__(kThreads) void k_mix_peak(const T *__restrict__ mix
     // epilogue: complex SNR of 8 templates per lane per row tile
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const int64_t col = n0 + wave * NT * 32 + nt * 32 + (lane & 31);
+      const int64_t col = n0 + wn * 32 * NT + nt * 32 + (lane & 31);
       const bool ok = col < we;
       const int rel = (int)(col - ws);
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+      for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
-          float re = acc[mt][nt][2 * p], im = acc[mt][nt][2 * p + 1];
-          float v = re * re + im * im;
-          if (ok && v > best[mt][p].v) best[mt][p] = Best{v, re, im, rel};
-          if (pa.snr && ok) {
-            int64_t i = (r0 + mt * 32 + 8 * (p >> 1) + 4 * (lane >> 5) + 2 * (p & 1)) >> 1;
-            if (i < n_templates) {
-              float2 z = make_float2(re * inv_scale, im * inv_scale);
-              *(float2 *)(pa.snr + (i * n + col) * 2) = z;
-            }
+          const float re = acc[mt][nt][2 * p], im = acc[mt][nt][2 * p + 1];
+          const float v = re * re + im * im;
+          if (ok && v > best[mt][p].v) best[mt][p] = VN{v, rel};
+          if (SNR && ok) {
+            const int64_t i = (r0 + wm * 32 * MT + mt * 32 + 8 * (p >> 1) + 4 * (lane >> 5) + 2 * (p & 1)) >> 1;
+            if (i < n_templates)
+              *(float2 *)(jb.snr + (i * jb.snr_ld + (col - jb.ocat_abs0)) * 2) = make_float2(re * inv_scale, im * inv_scale);
           }
         }
+      }
     }
   }
 
-  // reduce the 32 columns of each half-wave, then the four waves
+  // reduce the 32 columns of each half-wave, then the waves that share rows
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      Best bb = best[mt][p];
+      VN bb = best[mt][p];
 #pragma unroll
       for (int off = 1; off < 32; off <<= 1) {
-        float ov = __shfl_xor(bb.v, off), ore = __shfl_xor(bb.re, off), oim = __shfl_xor(bb.im, off);
-        int on = __shfl_xor(bb.n, off);
-        if (better(ov, on, bb.v, bb.n)) bb = Best{ov, ore, oim, on};
+        const float ov = __shfl_xor(bb.v, off);
+        const int on = __shfl_xor(bb.n, off);
+        if (better(ov, on, bb.v, bb.n)) bb = VN{ov, on};
       }
-      if ((lane & 31) == 0) {
-        int t = mt * 16 + 4 * (p >> 1) + 2 * (lane >> 5) + (p & 1);
-        red[wave][t] = bb;
-      }
+      if ((lane & 31) == 0) red[wn][wm * 16 * MT + mt * 16 + 4 * (p >> 1) + 2 * (lane >> 5) + (p & 1)] = bb;
     }
   __syncthreads();
-  if (threadIdx.x < BM / 2) {
-    int t = threadIdx.x;
-    Best bb = red[0][t];
-    for (int q = 1; q < kWaves; ++q)
+  for (int t = threadIdx.x; t < BM / 2; t += THREADS) {
+    VN bb = red[0][t];
+#pragma unroll
+    for (int q = 1; q < WN; ++q)
       if (better(red[q][t].v, red[q][t].n, bb.v, bb.n)) bb = red[q][t];
-    int64_t i = r0 / 2 + t;
+    const int64_t i = r0 / 2 + t;
     if (i < n_templates) {
-      int64_t o = i * pa.n_windows + w;
-      pa.peak_snr[o] = sqrtf(fmaxf(bb.v, 0.f)) * inv_scale;
-      pa.peak_n[o] = ws + bb.n;
-      pa.peak_phase[o] = atan2f(bb.im, bb.re);
+      const int64_t o = i * jb.ld_peak + (w - jb.w_base);
+      jb.peak_snr[o] = sqrtf(fmaxf(bb.v, 0.f)) * inv_scale;
+      jb.peak_n[o] = ws + bb.n;
     }
   }
+}
+
+// Phase at each reported window peak: z_i[n*] recomputed as the dot products
+// of mixing rows 2i, 2i+1 with the operand row at n* (FP32 accumulation, one
+// wave per peak).  Peaks below `thr` get phase 0 (not reported).
+template <typename T>
+__global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ jobs, int n_jobs, int64_t entries,
+                                                    float thr) {
+  const int lane = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e >= entries) return;
+  // job owning entry e: last job with e0 <= e
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].e0 <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  const MixJob &jb = jobs[lo];
+  const int64_t le = e - jb.e0;
+  const int64_t i = le / jb.nw, wl = le - i * jb.nw;
+  const int64_t o = i * jb.ld_peak + (jb.w0 + wl - jb.w_base);
+  if (!(jb.peak_snr[o] >= thr)) {
+    if (lane == 0) jb.peak_phase[o] = 0.f;
+    return;
+  }
+  const int kcat = jb.kcat;
+  const T *orow = (const T *)jb.ocat + (jb.peak_n[o] - jb.ocat_abs0) * (int64_t)kcat;
+  const T *mc = (const T *)jb.mix + (2 * i) * (int64_t)kcat;
+  const T *ms = mc + kcat;
+  float re = 0.f, im = 0.f;
+  for (int k = lane; k < kcat; k += 64) {
+    const float ov = Op<T>::tof(orow[k]);
+    re += Op<T>::tof(mc[k]) * ov;
+    im += Op<T>::tof(ms[k]) * ov;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off);
+    im += __shfl_xor(im, off);
+  }
+  if (lane == 0) jb.peak_phase[o] = atan2f(im, re);
 }
 
 // ---------------------------------------------------------- trigger compaction
@@ -397,72 +601,83 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *sh) {
   return tot;
 }
 
-__global__ void k_trigger_count(const float *__restrict__ snr, int64_t n_windows, float thr,
-                                int64_t *__restrict__ counts) {
+// Row r of the batch is template (r - row0) of the job owning it.
+__device__ __forceinline__ int find_trig_job(const TrigJob *__restrict__ jobs, int n_jobs, int64_t row) {
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].row0 <= row) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_trigger_count(const TrigJob *__restrict__ jobs, int n_jobs, float thr, int64_t *__restrict__ counts) {
   __shared__ int64_t sh[16];
-  const float *row = snr + (int64_t)blockIdx.x * n_windows;
+  const TrigJob &jb = jobs[find_trig_job(jobs, n_jobs, blockIdx.x)];
+  const int64_t i = (int64_t)blockIdx.x - jb.row0;
+  const float *row = jb.snr + i * jb.ld;
   int64_t c = 0;
-  for (int64_t w = threadIdx.x; w < n_windows; w += blockDim.x) c += row[w] >= thr ? 1 : 0;
+  for (int64_t w = threadIdx.x; w < jb.nw; w += blockDim.x) c += row[w] >= thr ? 1 : 0;
   c = block_sum(c, sh);
   if (threadIdx.x == 0) counts[blockIdx.x] = c;
 }
 
 // exclusive prefix sum of counts[0..n) in place; total in *total (one block)
-__global__ void k_trigger_scan(int64_t *counts, int n, int64_t *total) {
+__global__ void k_trigger_scan(int64_t *counts, int64_t n, int64_t *total) {
   __shared__ int64_t sh[1024];
   int64_t carry = 0;
-  for (int base = 0; base < n; base += blockDim.x) {
-    int i = base + threadIdx.x;
-    int64_t v = i < n ? counts[i] : 0;
+  for (int64_t base = 0; base < n; base += blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    const int64_t v = i < n ? counts[i] : 0;
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-      int64_t add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+      const int64_t add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
       __syncthreads();
       sh[threadIdx.x] += add;
       __syncthreads();
     }
     if (i < n) counts[i] = carry + sh[threadIdx.x] - v;
-    int64_t blk = sh[blockDim.x - 1];
+    const int64_t blk = sh[blockDim.x - 1];
     __syncthreads();
     carry += blk;
   }
   if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ void k_trigger_write(const float *__restrict__ snr, const int64_t *__restrict__ samp,
-                                const float *__restrict__ phase, int64_t n_windows, float thr,
-                                const int64_t *__restrict__ offsets, int64_t cap, int32_t bank_id,
-                                int32_t detector, lloid_trigger *__restrict__ out) {
+__global__ void k_trigger_write(const TrigJob *__restrict__ jobs, int n_jobs, float thr,
+                                const int64_t *__restrict__ offsets, int64_t cap, lloid_trigger *__restrict__ out) {
   __shared__ int sh[1024];
-  const int64_t i = blockIdx.x;
-  const float *row = snr + i * n_windows;
-  int64_t run = offsets[i];
-  for (int64_t base = 0; base < n_windows; base += blockDim.x) {
-    int64_t w = base + threadIdx.x;
-    int f = (w < n_windows && row[w] >= thr) ? 1 : 0;
+  const TrigJob &jb = jobs[find_trig_job(jobs, n_jobs, blockIdx.x)];
+  const int64_t i = (int64_t)blockIdx.x - jb.row0;
+  const float *row = jb.snr + i * jb.ld;
+  int64_t run = offsets[blockIdx.x];
+  for (int64_t base = 0; base < jb.nw; base += blockDim.x) {
+    const int64_t w = base + threadIdx.x;
+    const int f = (w < jb.nw && row[w] >= thr) ? 1 : 0;
     sh[threadIdx.x] = f;
     __syncthreads();
     for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-      int add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+      const int add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
       __syncthreads();
       sh[threadIdx.x] += add;
       __syncthreads();
     }
-    int64_t pos = run + sh[threadIdx.x] - f;
+    const int64_t pos = run + sh[threadIdx.x] - f;
     if (f && pos < cap) {
       lloid_trigger t;
-      t.bank = bank_id;
-      t.detector = detector;
+      t.bank = jb.bank_id;
+      t.detector = jb.detector;
       t.template_id = (int32_t)i;
       t.reserved = 0;
-      t.window = w;
-      t.sample = samp[i * n_windows + w];
+      t.window = jb.w_base + w;
+      t.sample = jb.peak_n[i * jb.ld + w];
       t.snr = row[w];
-      t.phase = phase[i * n_windows + w];
+      t.phase = jb.phase[i * jb.ld + w];
       out[pos] = t;
     }
-    int blk = sh[blockDim.x - 1];
+    const int blk = sh[blockDim.x - 1];
     __syncthreads();
     run += blk;
   }
@@ -471,6 +686,13 @@ __global__ void k_trigger_write(const float *__restrict__ snr, const int64_t *__
 // ------------------------------------------------------------ launchers
 
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// Tile-shape variant of a GEMM kernel: 0 (default) unless the named
+// environment variable selects another compiled shape.
+static int kernel_variant(const char *name) {
+  const char *v = getenv(name);
+  return v ? atoi(v) : 0;
+}
 
 hipError_t launch_convert(const void *src, lloid_dtype dt, int64_t n, float *dst, int64_t dst_lo,
                           int64_t dst_len, float scale, int *bad, hipStream_t s) {
@@ -491,85 +713,100 @@ hipError_t launch_decimate(const float *u, int64_t u_lo, int64_t u_len, float *d
   return hipGetLastError();
 }
 
-template <typename T, typename TO>
-static hipError_t fir_t(const SliceDev &sl, const float *x, int64_t x_lo, int64_t x_len, int64_t k_lo,
-                        int64_t k_hi, void *out, int64_t out_lo, int ldo, int col0, int col_limit,
-                        hipStream_t s) {
-  constexpr int BM = 32 * kFirMT;
-  const int64_t cols = k_hi - k_lo;
-  if (cols <= 0) return hipSuccess;
-  dim3 grid((unsigned)((cols + kFirBN - 1) / kFirBN), (unsigned)((sl.lrows + BM - 1) / BM));
-  const int64_t base = -(sl.start_tap / sl.dec + sl.n_taps - 1);
-  k_fir<T, TO, kFirMT, kFirNT><<<grid, kThreads, 0, s>>>((const T *)sl.basis, sl.lrows, sl.np, x, x_lo, x_len,
-                                                          base, k_lo, k_hi, (TO *)out, out_lo, ldo, col0,
-                                                          col_limit);
+template <typename T, int MT, int NT, int NW>
+static hipError_t fir_v(const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s) {
+  k_fir<T, MT, NT, NW><<<(unsigned)n_items, 64 * NW, 0, s>>>(jobs, n_jobs);
   return hipGetLastError();
-}
-
-hipError_t launch_fir(lloid_dtype t, const SliceDev &sl, const float *x, int64_t x_lo, int64_t x_len,
-                      int64_t k_lo, int64_t k_hi, void *out, int64_t out_lo, int ldo, int col0, int col_limit,
-                      hipStream_t s) {
-  // level-0 slices write the compute type straight into the concatenated
-  // operand; lower-rate slices keep FP32 for the interpolation cascade
-  const bool to_f32 = sl.level > 0;
-  switch (t) {
-    case LLOID_F16:
-      return to_f32 ? fir_t<_Float16, float>(sl, x, x_lo, x_len, k_lo, k_hi, out, out_lo, ldo, col0, col_limit, s)
-                    : fir_t<_Float16, _Float16>(sl, x, x_lo, x_len, k_lo, k_hi, out, out_lo, ldo, col0, col_limit, s);
-    case LLOID_BF16:
-      return to_f32 ? fir_t<__bf16, float>(sl, x, x_lo, x_len, k_lo, k_hi, out, out_lo, ldo, col0, col_limit, s)
-                    : fir_t<__bf16, __bf16>(sl, x, x_lo, x_len, k_lo, k_hi, out, out_lo, ldo, col0, col_limit, s);
-    case LLOID_F32:
-      return fir_t<float, float>(sl, x, x_lo, x_len, k_lo, k_hi, out, out_lo, ldo, col0, col_limit, s);
-    default:
-      return hipErrorInvalidValue;
-  }
-}
-
-template <typename TI, typename TO>
-static hipError_t interp_t(const void *w, int64_t w_lo, int64_t w_len, int ldw, void *v, int64_t v_lo,
-                           int64_t v_len, int ldv, int col0, int channels, const float *g, hipStream_t s) {
-  const int64_t total = v_len * channels;
-  if (total <= 0) return hipSuccess;
-  k_interp<TI, TO><<<blocks_for(total, 256), 256, 0, s>>>((const TI *)w, w_lo, w_len, ldw, (TO *)v, v_lo, v_len,
-                                                          ldv, col0, channels, g);
-  return hipGetLastError();
-}
-
-hipError_t launch_interp(lloid_dtype in_t, const void *w, int64_t w_lo, int64_t w_len, int ldw, lloid_dtype out_t,
-                         void *v, int64_t v_lo, int64_t v_len, int ldv, int col0, int channels, const float *g,
-                         hipStream_t s) {
-  if (in_t != LLOID_F32) return hipErrorInvalidValue;
-  switch (out_t) {
-    case LLOID_F32: return interp_t<float, float>(w, w_lo, w_len, ldw, v, v_lo, v_len, ldv, col0, channels, g, s);
-    case LLOID_F16: return interp_t<float, _Float16>(w, w_lo, w_len, ldw, v, v_lo, v_len, ldv, col0, channels, g, s);
-    case LLOID_BF16: return interp_t<float, __bf16>(w, w_lo, w_len, ldw, v, v_lo, v_len, ldv, col0, channels, g, s);
-    default: return hipErrorInvalidValue;
-  }
 }
 
 template <typename T>
-static hipError_t mix_t(const void *mix, int rows, int kcat, int n_templates, const void *ocat, int64_t n,
-                        float inv_scale, const PeakArgs &pa, hipStream_t s) {
-  constexpr int BM = 32 * kMixMT;
-  const int n_rtiles = (rows + BM - 1) / BM;
-  const int64_t n_wgroups = (pa.n_windows + 7) / 8;
-  const int64_t blocks = n_wgroups * 8 * n_rtiles;
-  if (blocks <= 0) return hipSuccess;
-  k_mix_peak<T, kMixMT, kMixNT><<<(unsigned)blocks, kThreads, 0, s>>>((const T *)mix, rows, kcat, n_templates,
-                                                                      (const T *)ocat, n, inv_scale, pa, n_rtiles,
-                                                                      n_wgroups);
+static hipError_t fir_t(const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s) {
+  switch (kernel_variant("LLOID_FIR_VARIANT")) {
+    case 1: return fir_v<T, kFirMT, kFirNT / 2, 8>(jobs, n_jobs, n_items, s);
+    default: return fir_v<T, kFirMT, kFirNT, 4>(jobs, n_jobs, n_items, s);
+  }
+}
+
+void fir_tile_shape(int *bm, int *bn) {
+  *bm = 32 * kFirMT;
+  *bn = kernel_variant("LLOID_FIR_VARIANT") == 1 ? 8 * 32 * (kFirNT / 2) : 4 * 32 * kFirNT;
+}
+
+void mix_tile_shape(int *bm, int *bn) {
+  switch (kernel_variant("LLOID_MIX_VARIANT")) {
+    case 1: *bm = 32 * 2 * 4, *bn = 32 * 4 * 2; break;
+    case 2: *bm = 32 * 2 * 4, *bn = 32 * 2 * 2; break;
+    default: *bm = 32 * kMixMT * kMixWM, *bn = 32 * kMixNT * kMixWN; break;
+  }
+}
+
+hipError_t launch_fir_jobs(lloid_dtype t, const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  switch (t) {
+    case LLOID_F16: return fir_t<_Float16>(jobs, n_jobs, n_items, s);
+    case LLOID_BF16: return fir_t<__bf16>(jobs, n_jobs, n_items, s);
+    case LLOID_F32: return fir_t<float>(jobs, n_jobs, n_items, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_interp_jobs(lloid_dtype t, const InterpJob *jobs, int n_jobs, int64_t n_items, const float *g,
+                              hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  switch (t) {
+    case LLOID_F32: k_interp_cascade<float><<<(unsigned)n_items, 256, 0, s>>>(jobs, n_jobs, g); break;
+    case LLOID_F16: k_interp_cascade<_Float16><<<(unsigned)n_items, 256, 0, s>>>(jobs, n_jobs, g); break;
+    case LLOID_BF16: k_interp_cascade<__bf16><<<(unsigned)n_items, 256, 0, s>>>(jobs, n_jobs, g); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_mix_peak(lloid_dtype t, const void *mix, int rows, int kcat, int n_templates, const void *ocat,
-                           int64_t n, float inv_scale, const PeakArgs &pa, hipStream_t s) {
+template <typename T, int MT, int NT, int WM, int WN, int BK>
+static hipError_t mix_v(const MixJob *jobs, int n_jobs, int64_t n_items, bool with_snr, hipStream_t s) {
+  if (with_snr)
+    k_mix_peak<T, MT, NT, WM, WN, BK, true><<<(unsigned)n_items, 64 * WM * WN, 0, s>>>(jobs, n_jobs);
+  else
+    k_mix_peak<T, MT, NT, WM, WN, BK, false><<<(unsigned)n_items, 64 * WM * WN, 0, s>>>(jobs, n_jobs);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t mix_t(const MixJob *jobs, int n_jobs, int64_t n_items, int64_t n_entries, bool with_snr,
+                        float phase_thr, hipStream_t s) {
+  hipError_t e;
+  switch (kernel_variant("LLOID_MIX_VARIANT")) {
+    case 1: e = mix_v<T, 2, 4, 4, 2, 32>(jobs, n_jobs, n_items, with_snr, s); break;
+    case 2: e = mix_v<T, 2, 2, 4, 2, 32>(jobs, n_jobs, n_items, with_snr, s); break;
+    default: e = mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 32>(jobs, n_jobs, n_items, with_snr, s); break;
+  }
+  if (e != hipSuccess) return e;
+  if (n_entries > 0)
+    k_peak_phase<T><<<(unsigned)((n_entries + 3) / 4), 256, 0, s>>>(jobs, n_jobs, n_entries, phase_thr);
+  return hipGetLastError();
+}
+
+hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_items, int64_t n_entries,
+                           bool with_snr, float phase_thr, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
   switch (t) {
-    case LLOID_F16: return mix_t<_Float16>(mix, rows, kcat, n_templates, ocat, n, inv_scale, pa, s);
-    case LLOID_BF16: return mix_t<__bf16>(mix, rows, kcat, n_templates, ocat, n, inv_scale, pa, s);
-    case LLOID_F32: return mix_t<float>(mix, rows, kcat, n_templates, ocat, n, inv_scale, pa, s);
+    case LLOID_F16: return mix_t<_Float16>(jobs, n_jobs, n_items, n_entries, with_snr, phase_thr, s);
+    case LLOID_BF16: return mix_t<__bf16>(jobs, n_jobs, n_items, n_entries, with_snr, phase_thr, s);
+    case LLOID_F32: return mix_t<float>(jobs, n_jobs, n_items, n_entries, with_snr, phase_thr, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_rows, float thr, int64_t *counts,
+                               int64_t *total, int64_t cap, lloid_trigger *out, hipStream_t s) {
+  if (n_rows <= 0) {
+    k_trigger_scan<<<1, 1024, 0, s>>>(counts, 0, total);
+    return hipGetLastError();
+  }
+  k_trigger_count<<<(unsigned)n_rows, 256, 0, s>>>(jobs, n_jobs, thr, counts);
+  k_trigger_scan<<<1, 1024, 0, s>>>(counts, n_rows, total);
+  k_trigger_write<<<(unsigned)n_rows, 1024, 0, s>>>(jobs, n_jobs, thr, counts, cap, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_sigma2(const double *mix64, int n_templates, int lsum, const double *inv_dec_per_col,
@@ -593,27 +830,6 @@ hipError_t launch_fill_u8(void *p, size_t bytes, hipStream_t s) {
   if (!bytes) return hipSuccess;
   unsigned blocks = (unsigned)std::min<size_t>((bytes + 255) / 256, 65536);
   k_fill_u8<<<blocks, 256, 0, s>>>((uint8_t *)p, bytes);
-  return hipGetLastError();
-}
-
-hipError_t launch_trigger_count(const float *peak_snr, int n_templates, int64_t n_windows, float thr,
-                                int64_t *counts, hipStream_t s) {
-  if (n_templates <= 0) return hipSuccess;
-  k_trigger_count<<<n_templates, 256, 0, s>>>(peak_snr, n_windows, thr, counts);
-  return hipGetLastError();
-}
-
-hipError_t launch_trigger_scan(int64_t *counts, int n_templates, int64_t *total, hipStream_t s) {
-  k_trigger_scan<<<1, 1024, 0, s>>>(counts, n_templates, total);
-  return hipGetLastError();
-}
-
-hipError_t launch_trigger_write(const float *peak_snr, const int64_t *peak_n, const float *peak_phase,
-                                int n_templates, int64_t n_windows, float thr, const int64_t *offsets, int64_t cap,
-                                int32_t bank_id, int32_t detector, lloid_trigger *out, hipStream_t s) {
-  if (n_templates <= 0) return hipSuccess;
-  k_trigger_write<<<n_templates, 1024, 0, s>>>(peak_snr, peak_n, peak_phase, n_windows, thr, offsets, cap, bank_id,
-                                                detector, out);
   return hipGetLastError();
 }
 

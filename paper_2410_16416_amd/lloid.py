@@ -63,6 +63,21 @@ class lloid_peaks(ctypes.Structure):
                 ("phase", ctypes.c_void_p), ("n_windows", ctypes.c_int64)]
 
 
+class lloid_stream_opts(ctypes.Structure):
+    _fields_ = [("n_detectors", ctypes.c_int32), ("min_rate_hz", ctypes.c_int32),
+                ("max_windows_per_tick", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_filter_s", ctypes.c_double), ("hbm_budget", ctypes.c_int64),
+                ("trig", lloid_trigger_opts)]
+
+
+class lloid_stream_stats(ctypes.Structure):
+    _fields_ = [("ticks", ctypes.c_int64), ("windows", ctypes.c_int64), ("triggers", ctypes.c_int64),
+                ("next_window", ctypes.c_int64), ("latency_p50_ms", ctypes.c_double),
+                ("latency_p99_ms", ctypes.c_double), ("latency_max_ms", ctypes.c_double),
+                ("active_slots", ctypes.c_int32), ("queued_banks", ctypes.c_int32),
+                ("bytes_in_use", ctypes.c_int64)]
+
+
 TRIGGER_DTYPE = np.dtype([("bank", np.int32), ("detector", np.int32), ("template_id", np.int32),
                           ("reserved", np.int32), ("window", np.int64), ("sample", np.int64),
                           ("snr", np.float32), ("phase", np.float32)])
@@ -87,6 +102,19 @@ def _load():
         "lloid_bank_destroy": ([vp], ctypes.c_int),
         "lloid_filter": ([vp, i32, vp, ctypes.c_int, i64, ctypes.POINTER(lloid_trigger_opts), vp, i64,
                           ctypes.POINTER(i64), vp, ctypes.POINTER(lloid_peaks)], ctypes.c_int),
+        "lloid_filter_batch": ([ctypes.POINTER(vp), i32, i32, vp, ctypes.c_int, i64,
+                                ctypes.POINTER(lloid_trigger_opts), vp, i64, ctypes.POINTER(i64),
+                                ctypes.POINTER(lloid_peaks)], ctypes.c_int),
+        "lloid_ctx_set_chunk_bytes": ([vp, i64], ctypes.c_int),
+        "lloid_stream_create": ([vp, i32, ctypes.c_int, ctypes.POINTER(lloid_stream_opts), ctypes.POINTER(vp)],
+                                ctypes.c_int),
+        "lloid_stream_admit": ([vp, vp, ctypes.POINTER(i32)], ctypes.c_int),
+        "lloid_stream_remove": ([vp, i32], ctypes.c_int),
+        "lloid_stream_push": ([vp, i32, i64, vp, ctypes.c_int, i64], ctypes.c_int),
+        "lloid_stream_poll": ([vp, vp, i64, ctypes.POINTER(i64)], ctypes.c_int),
+        "lloid_stream_flush": ([vp], ctypes.c_int),
+        "lloid_stream_stats_get": ([vp, ctypes.POINTER(lloid_stream_stats)], ctypes.c_int),
+        "lloid_stream_destroy": ([vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -116,7 +144,9 @@ def exported_symbols():
     return ["lloid_last_error", "lloid_version", "lloid_ctx_create", "lloid_ctx_destroy",
             "lloid_ctx_profile", "lloid_ctx_stage_times",
             "lloid_bank_create", "lloid_bank_sigma2", "lloid_bank_query", "lloid_bank_destroy",
-            "lloid_filter"]
+            "lloid_filter", "lloid_filter_batch", "lloid_ctx_set_chunk_bytes",
+            "lloid_stream_create", "lloid_stream_admit", "lloid_stream_remove", "lloid_stream_push",
+            "lloid_stream_poll", "lloid_stream_flush", "lloid_stream_stats_get", "lloid_stream_destroy"]
 
 
 def lloid_version() -> str:
@@ -147,6 +177,10 @@ def lloid_ctx_stage_times(ctx, reset: bool = False):
     calls = np.zeros(len(STAGES), dtype=np.int64)
     _check(_lib.lloid_ctx_stage_times(ctx, ms.ctypes.data, calls.ctypes.data, 1 if reset else 0))
     return {k: (float(ms[i]), int(calls[i])) for i, k in enumerate(STAGES)}
+
+
+def lloid_ctx_set_chunk_bytes(ctx, nbytes: int):
+    _check(_lib.lloid_ctx_set_chunk_bytes(ctx, int(nbytes)))
 
 
 def lloid_bank_create(ctx, full_rate_hz: int, n_templates: int, slices, compute: str = "f16"):
@@ -254,6 +288,120 @@ def lloid_filter(bank, detector: int, strain, window=(1, 1), threshold: float = 
     return res
 
 
+def _strain_arg(strain):
+    if isinstance(strain, np.ndarray):
+        strain = np.ascontiguousarray(strain)
+        dt = LLOID_F64 if strain.dtype == np.float64 else LLOID_F32 if strain.dtype == np.float32 else None
+    else:
+        import torch
+        dt = {torch.float64: LLOID_F64, torch.float32: LLOID_F32}.get(strain.dtype)
+    if dt is None:
+        raise LloidError(LLOID_EINVAL, "strain must be float64 or float32")
+    return strain, dt, int(strain.shape[0])
+
+
+@dataclass
+class BatchResult:
+    triggers: np.ndarray
+    n_triggers: int
+    peak_snr: list | None = None       # per bank [F_b, W]
+    peak_sample: list | None = None
+    peak_phase: list | None = None
+
+
+def lloid_filter_batch(banks, detector: int, strain, window=(1, 1), threshold: float = 4.0,
+                       strain_scale: float = 0.0, trig_cap: int | None = None, triggers_out=None,
+                       peaks: bool = False) -> BatchResult:
+    """Filter one detector's strain with every bank in `banks` (one launch per stage)."""
+    strain, dt, n = _strain_arg(strain)
+    infos = [lloid_bank_query(b) for b in banks]
+    num, den = window
+    opts = lloid_trigger_opts(int(num), int(den), float(threshold), float(strain_scale))
+    n_windows = -(-n * int(den) // (infos[0].full_rate_hz * int(num)))
+    res = BatchResult(triggers=None, n_triggers=0)
+    pk = None
+    if peaks:
+        res.peak_snr = [np.empty((i.n_templates, n_windows), np.float32) for i in infos]
+        res.peak_sample = [np.empty((i.n_templates, n_windows), np.int64) for i in infos]
+        res.peak_phase = [np.empty((i.n_templates, n_windows), np.float32) for i in infos]
+        pk = (lloid_peaks * len(banks))()
+        for k in range(len(banks)):
+            pk[k] = lloid_peaks(res.peak_snr[k].ctypes.data, res.peak_sample[k].ctypes.data,
+                                res.peak_phase[k].ctypes.data, n_windows)
+    if triggers_out is None:
+        cap = trig_cap if trig_cap is not None else sum(i.n_templates for i in infos) * n_windows
+        triggers_out = np.empty(max(cap, 1), dtype=TRIGGER_DTYPE)
+        cap = cap if trig_cap is not None else triggers_out.shape[0]
+    else:
+        cap = (triggers_out.shape[0] if isinstance(triggers_out, np.ndarray)
+               else triggers_out.numel() // TRIGGER_DTYPE.itemsize)
+    handles = (ctypes.c_void_p * len(banks))(*[b.value for b in banks])
+    n_trig = ctypes.c_int64()
+    st = _lib.lloid_filter_batch(handles, len(banks), int(detector), ctypes.c_void_p(_ptr(strain)), dt, n,
+                                 ctypes.byref(opts), ctypes.c_void_p(_ptr(triggers_out)), int(cap),
+                                 ctypes.byref(n_trig), pk)
+    _check(st)
+    res.n_triggers = int(n_trig.value)
+    res.triggers = triggers_out[: res.n_triggers] if isinstance(triggers_out, np.ndarray) else triggers_out
+    return res
+
+
 def bank_from_svd(ctx, svd_bank, compute: str = "f16"):
     """Upload an SVD bank object (attributes f0, n_templates, slices)."""
     return lloid_bank_create(ctx, svd_bank.f0, svd_bank.n_templates, svd_bank.slices, compute)
+
+
+# ------------------------------------------------------------------ streaming
+
+def lloid_stream_create(ctx, full_rate_hz: int, compute: str = "f16", n_detectors: int = 1,
+                        min_rate_hz: int | None = None, window=(1, 1), threshold: float = 4.0,
+                        strain_scale: float = 0.0, hbm_budget: int = 0, max_filter_s: float = 0.0,
+                        max_windows_per_tick: int = 0):
+    opts = lloid_stream_opts(int(n_detectors), int(min_rate_hz or max(1, full_rate_hz // 16)),
+                             int(max_windows_per_tick), 0, float(max_filter_s), int(hbm_budget),
+                             lloid_trigger_opts(int(window[0]), int(window[1]), float(threshold),
+                                                float(strain_scale)))
+    out = ctypes.c_void_p()
+    _check(_lib.lloid_stream_create(ctx, int(full_rate_hz), DTYPES[compute], ctypes.byref(opts),
+                                    ctypes.byref(out)))
+    return out
+
+
+def lloid_stream_admit(stream, bank):
+    """Returns (slot, active); a queued bank (EAGAIN) returns active=False."""
+    slot = ctypes.c_int32(-1)
+    st = _lib.lloid_stream_admit(stream, bank, ctypes.byref(slot))
+    if st == LLOID_EAGAIN:
+        return int(slot.value), False
+    _check(st)
+    return int(slot.value), True
+
+
+def lloid_stream_remove(stream, slot: int):
+    _check(_lib.lloid_stream_remove(stream, int(slot)))
+
+
+def lloid_stream_push(stream, detector: int, t0: int, data):
+    data, dt, n = _strain_arg(data)
+    _check(_lib.lloid_stream_push(stream, int(detector), int(t0), ctypes.c_void_p(_ptr(data)), dt, n))
+
+
+def lloid_stream_poll(stream, cap: int = 1 << 20) -> np.ndarray:
+    out = np.empty(max(cap, 1), dtype=TRIGGER_DTYPE)
+    n = ctypes.c_int64()
+    _check(_lib.lloid_stream_poll(stream, ctypes.c_void_p(out.ctypes.data), int(cap), ctypes.byref(n)))
+    return out[: n.value]
+
+
+def lloid_stream_flush(stream):
+    _check(_lib.lloid_stream_flush(stream))
+
+
+def lloid_stream_stats_get(stream) -> lloid_stream_stats:
+    st = lloid_stream_stats()
+    _check(_lib.lloid_stream_stats_get(stream, ctypes.byref(st)))
+    return st
+
+
+def lloid_stream_destroy(stream):
+    _check(_lib.lloid_stream_destroy(stream))

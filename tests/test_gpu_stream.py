@@ -1,0 +1,177 @@
+"""Streaming (serving) form: strides in, triggers out, banks admitted and
+removed while the stream runs.  Every trigger must equal the one the offline
+call gives for the whole stream, alone or in the mix."""
+
+import numpy as np
+import pytest
+
+from workloads import configs
+
+from gpu_util import ctx, log
+
+pytestmark = pytest.mark.gpu
+
+KEY = ["bank", "detector", "template_id", "window"]
+
+
+def canon(t):
+    return np.sort(t, order=KEY)
+
+
+def offline(lloid, handle, strains, window, slot, w_from=0, w_to=None):
+    parts = []
+    for d, x in enumerate(strains):
+        r = lloid.lloid_filter(handle, d, x, window=window)
+        t = r.triggers.copy()
+        t["bank"] = slot
+        keep = t["window"] >= w_from
+        if w_to is not None:
+            keep &= t["window"] < w_to
+        parts.append(t[keep])
+    return canon(np.concatenate(parts))
+
+
+def run_stream(lloid, s, strains, sizes):
+    n = strains[0].shape[0]
+    pos, i = 0, 0
+    got = []
+    while pos < n:
+        m = min(sizes[i % len(sizes)], n - pos)
+        for d, x in enumerate(strains):
+            lloid.lloid_stream_push(s, d, pos, x[pos:pos + m])
+        got.append(lloid.lloid_stream_poll(s))
+        pos += m
+        i += 1
+    lloid.lloid_stream_flush(s)
+    got.append(lloid.lloid_stream_poll(s))
+    return np.concatenate(got)
+
+
+@pytest.mark.parametrize("sizes", [[1024], [700, 1500, 333]])
+def test_stream_equals_offline(sizes):
+    from paper_2410_16416_amd import lloid
+    wl = configs.mini_multirate(seconds=12, detectors=2, n_injections=2)
+    h = lloid.bank_from_svd(ctx(), wl.bank, "f16")
+    s = lloid.lloid_stream_create(ctx(), 1024, "f16", n_detectors=2, min_rate_hz=64, window=(1, 4),
+                                  max_filter_s=8.0)
+    try:
+        slot, active = lloid.lloid_stream_admit(s, h)
+        assert active
+        got = canon(run_stream(lloid, s, wl.strains, sizes))
+        want = offline(lloid, h, wl.strains, (1, 4), slot)
+        st = lloid.lloid_stream_stats_get(s)
+        log(f"[stream {sizes}] {len(got)} triggers, ticks {st.ticks}, p50 {st.latency_p50_ms:.2f} ms, "
+            f"p99 {st.latency_p99_ms:.2f} ms")
+        assert len(got) == len(want) > 0
+        assert np.array_equal(got, want)
+        assert st.next_window == 48 and st.triggers == len(got)
+    finally:
+        lloid.lloid_stream_destroy(s)
+        lloid.lloid_bank_destroy(h)
+
+
+def test_continuous_batching_admission_and_removal():
+    """Banks join while others run, one waits for budget and enters when a
+    slot is removed; each bank's triggers equal its offline triggers over the
+    windows it was active for."""
+    from paper_2410_16416_amd import lloid
+    f0 = 1024
+    banks = [configs.small_uneven_bank(i) for i in (0, 1, 2)]
+    rng = np.random.default_rng(21)
+    n = 16 * f0
+    strains = [rng.standard_normal(n), rng.standard_normal(n)]
+    hs = [lloid.bank_from_svd(ctx(), b, "f16") for b in banks]
+    # budget that fits two of these banks at a time
+    s0 = lloid.lloid_stream_create(ctx(), f0, "f16", n_detectors=2, min_rate_hz=64, window=(1, 2),
+                                   max_filter_s=4.0)
+    try:
+        sizes = []
+        for h in hs:
+            slot, _ = lloid.lloid_stream_admit(s0, h)
+            sizes.append(lloid.lloid_stream_stats_get(s0).bytes_in_use - sum(sizes))
+    finally:
+        lloid.lloid_stream_destroy(s0)
+    budget = sizes[0] + max(sizes[1], sizes[2]) + 1
+    s = lloid.lloid_stream_create(ctx(), f0, "f16", n_detectors=2, min_rate_hz=64, window=(1, 2),
+                                  max_filter_s=4.0, hbm_budget=budget)
+    try:
+        a, act_a = lloid.lloid_stream_admit(s, hs[0])
+        assert act_a
+        got = []
+        stride = f0 // 2
+        pos, k = 0, 0
+        admitted = {a: 0}
+        removed = {}
+        while pos < n:
+            if k == 5:
+                b, act_b = lloid.lloid_stream_admit(s, hs[1])
+                assert act_b
+                admitted[b] = lloid.lloid_stream_stats_get(s).next_window
+                c, act_c = lloid.lloid_stream_admit(s, hs[2])
+                assert not act_c                          # over budget: queued
+                assert lloid.lloid_stream_stats_get(s).queued_banks == 1
+            if k == 12:
+                removed[a] = lloid.lloid_stream_stats_get(s).next_window
+                lloid.lloid_stream_remove(s, a)
+            for d in range(2):
+                lloid.lloid_stream_push(s, d, pos, strains[d][pos:pos + stride])
+            if k == 12:
+                admitted[c] = removed[a]                  # enters at the next tick
+            got.append(lloid.lloid_stream_poll(s))
+            pos += stride
+            k += 1
+        lloid.lloid_stream_flush(s)
+        got.append(lloid.lloid_stream_poll(s))
+        got = np.concatenate(got)
+        for slot, h in zip((a, b, c), hs):
+            want = offline(lloid, h, strains, (1, 2), slot, admitted[slot], removed.get(slot))
+            mine = canon(got[got["bank"] == slot])
+            log(f"[batching] slot {slot}: windows [{admitted[slot]}, {removed.get(slot)}) {len(mine)} triggers")
+            assert len(mine) > 0 and np.array_equal(mine, want), slot
+    finally:
+        lloid.lloid_stream_destroy(s)
+        for h in hs:
+            lloid.lloid_bank_destroy(h)
+
+
+def test_stream_errors():
+    from paper_2410_16416_amd import lloid
+    h = lloid.bank_from_svd(ctx(), configs.mini_multirate_bank(), "f16")
+    s = lloid.lloid_stream_create(ctx(), 1024, "f16", n_detectors=1, min_rate_hz=64, max_filter_s=8.0)
+    try:
+        lloid.lloid_stream_admit(s, h)
+        x = np.zeros(1024)
+        lloid.lloid_stream_push(s, 0, 0, x)
+        with pytest.raises(lloid.LloidError) as ei:
+            lloid.lloid_stream_push(s, 0, 2048, x)        # gap
+        assert ei.value.status == lloid.LLOID_EORDER
+        with pytest.raises(lloid.LloidError) as ei:
+            lloid.lloid_stream_push(s, 1, 1024, x)        # no such detector
+        assert ei.value.status == lloid.LLOID_EINVAL
+        bad = x.copy()
+        bad[5] = np.inf
+        with pytest.raises(lloid.LloidError) as ei:
+            lloid.lloid_stream_push(s, 0, 1024, bad)
+        assert ei.value.status == lloid.LLOID_EDATA
+    finally:
+        lloid.lloid_stream_destroy(s)
+    # a stream whose history is shorter than the bank's filters refuses it
+    s = lloid.lloid_stream_create(ctx(), 1024, "f16", n_detectors=1, min_rate_hz=64, max_filter_s=1.0)
+    try:
+        with pytest.raises(lloid.LloidError) as ei:
+            lloid.lloid_stream_admit(s, h)
+        assert ei.value.status == lloid.LLOID_EINVAL
+    finally:
+        lloid.lloid_stream_destroy(s)
+        lloid.lloid_bank_destroy(h)
+    # a budget smaller than one bank: ENOMEM
+    h2 = lloid.bank_from_svd(ctx(), configs.small_uneven_bank(0), "f16")
+    s = lloid.lloid_stream_create(ctx(), 1024, "f16", n_detectors=1, min_rate_hz=64, max_filter_s=4.0,
+                                  hbm_budget=1000)
+    try:
+        with pytest.raises(lloid.LloidError) as ei:
+            lloid.lloid_stream_admit(s, h2)
+        assert ei.value.status == lloid.LLOID_ENOMEM
+    finally:
+        lloid.lloid_stream_destroy(s)
+        lloid.lloid_bank_destroy(h2)

@@ -179,3 +179,55 @@ def batched_bank(index: int, config: int = 3, f0: int = 2048) -> SvdBank:
     n_t, d_max, specs = draw_bank_specs(rng, f0)
     fam = duration_chirps(n_t, f0, d_max / 4.0, d_max, 4.0, rng)
     return build_svd_bank(fam, f0, specs)
+
+
+def small_uneven_bank(index: int, f0: int = 1024) -> SvdBank:
+    """A small bank with the batched recipe's structure (1-4 slices at f0 and
+    distinct lower rates, uneven template count and basis sizes), short enough
+    for the oracle: F ~ U{8..40}, D_max ~ logU[0.5, 3] s."""
+    rng = np.random.default_rng(seed(6, 9) + 1000 * index)
+    n_t = int(rng.integers(8, 41))
+    rates_all = (f0 // 2, f0 // 4, f0 // 8, f0 // 16)
+    n_s = int(rng.integers(1, 5))
+    rates = [f0] + sorted(rng.choice(rates_all, size=n_s - 1, replace=False).tolist(), reverse=True)
+    d_max = float(np.floor(np.exp(rng.uniform(np.log(0.5), np.log(3.0))) * 64) / 64)
+    edges = [0.0] + [np.floor(d_max * 4.0 ** (-(n_s - k)) * 64) / 64 for k in range(1, n_s)] + [d_max]
+    specs = []
+    for k, r in enumerate(rates):
+        d = f0 // r
+        j = int(round(edges[k] * f0))
+        j -= j % d
+        end = int(round(edges[k + 1] * f0))
+        n_taps = max((end - j + d - 1) // d, 1)
+        lb = int(rng.integers(4, 24))
+        specs.append(SliceSpec(r, j, n_taps, max(1, min(lb, 2 * n_t, n_taps))))
+    fam = duration_chirps(n_t, f0, d_max / 2.0, d_max, 3.0, rng)
+    return build_svd_bank(fam, f0, specs)
+
+
+def random_basis_bank(n_templates: int, specs, f0: int, rng: np.random.Generator) -> SvdBank:
+    """A bank with the given shape whose bases are seeded random orthonormal rows
+    and whose mixing entries are Gaussian with the per-column energy of an SVD
+    bank (decreasing singular values).  The filtering work depends only on the
+    shapes, so this stands in for chirp SVD banks whose construction would take
+    minutes (a 4000 x 131072 decomposition for a 64 s single-slice bank)."""
+    from .bank import BankSlice
+    bank = SvdBank(f0=f0, n_templates=n_templates)
+    for sp in specs:
+        q, _ = np.linalg.qr(rng.standard_normal((sp.n_taps, sp.n_basis)))
+        sv = np.sqrt(2.0 * n_templates / sp.n_basis) * np.exp(-np.arange(sp.n_basis) / max(sp.n_basis, 1))
+        mix = rng.standard_normal((2 * n_templates, sp.n_basis)) * (sv / np.sqrt(2.0 * n_templates))[None, :]
+        bank.slices.append(BankSlice(rate=sp.rate, start_tap=sp.start_tap, n_taps=sp.n_taps,
+                                     basis=np.ascontiguousarray(q.T), mixing=mix, singular_values=sv))
+    return bank
+
+
+def batched_c3_banks(n_banks: int = 64, f0: int = 2048):
+    """Uneven banks for the batched measurement: shapes drawn by draw_bank_specs,
+    values from random_basis_bank."""
+    banks = []
+    for i in range(n_banks):
+        rng = np.random.default_rng(seed(3, 9) + 1000 * i)
+        n_t, d_max, specs = draw_bank_specs(rng, f0)
+        banks.append(random_basis_bank(n_t, specs, f0, rng))
+    return banks
