@@ -156,7 +156,7 @@ lloid_status lloid_ctx_profile(lloid_ctx *ctx, int enable);
 lloid_status lloid_ctx_stage_times(lloid_ctx *ctx, double *ms, int64_t *calls, int reset);
 
 /* Upload one SVD bank (Sec. II.A "SVD bank").  Validates every slice (EINVAL
- * on a rate that is not f0 / 2^k, a start tap that is not a multiple of
+ * on a rate that is not f0 / 2^k with k <= 7, a start tap that is not a multiple of
  * f0 / r_s, L_s > N_s, a NULL array), scales each slice's basis and the
  * mixing matrices by exact powers of two, converts them to the compute
  * type, lays them out for the kernels and computes sigma^2 in FP64.  The
@@ -195,7 +195,8 @@ lloid_status lloid_bank_destroy(lloid_bank *bank);
  *           complex SNR (Re, Im) of every template at every sample.
  *   peaks:  NULL, or dense per-(template, window) peak outputs.
  * Triggers are ordered by template, then window.  EDATA if a strain sample is
- * not finite.  Blocks until the results are in the caller's buffers. */
+ * not finite; EINVAL if n is not in [1, 2^28] (longer blocks are split by
+ * the caller).  Blocks until the results are in the caller's buffers. */
 lloid_status lloid_filter(lloid_bank *bank, int32_t detector,
                           const void *strain, lloid_dtype strain_dtype, int64_t n,
                           const lloid_trigger_opts *opts,

@@ -111,6 +111,35 @@ extern "C" lloid_status lloid_ctx_create(int device, void *hip_stream, lloid_ctx
     lloid_ctx_destroy(c);
     return fail(LLOID_EDEVICE, "cannot upload resampler taps");
   }
+  // composite interpolation filters as MFMA fragments: FP32 32x32x2 (KS 2,
+  // one value per lane; also used by BF16 operands, whose low-rate buffers
+  // are FP32) and FP16 32x32x16 (KS 16, eight values per lane); 2048 entries
+  // each, built in FP64 and rounded on the device
+  {
+    constexpr size_t kEnt = 2048, kSlot = kEnt * 4;
+    const lloid_dtype types[2] = {LLOID_F32, LLOID_F16};
+    char *mem = nullptr;
+    double *tmp = nullptr;
+    bool ok = hipMalloc((void **)&mem, 4 * kSlot) == hipSuccess && hipMalloc((void **)&tmp, kEnt * 8) == hipSuccess;
+    std::vector<double> frag;
+    for (int ti = 0; ti < 2 && ok; ++ti)
+      for (int ri = 0; ri < 2 && ok; ++ri) {
+        const bool f32 = types[ti] == LLOID_F32;
+        interp_fragments(c->halfband, ri == 0 ? 2 : 4, f32 ? 2 : 16, f32 ? 1 : 8, frag);
+        c->d_hfrag[ti][ri] = mem + (ti * 2 + ri) * kSlot;
+        ok = frag.size() == kEnt &&
+             hipMemcpy(tmp, frag.data(), kEnt * 8, hipMemcpyHostToDevice) == hipSuccess &&
+             launch_cast_f64(tmp, types[ti], c->d_hfrag[ti][ri], (int64_t)kEnt, c->stream) == hipSuccess &&
+             hipStreamSynchronize(c->stream) == hipSuccess;
+      }
+    if (tmp) (void)hipFree(tmp);
+    if (!ok) {
+      if (mem) (void)hipFree(mem);
+      c->d_hfrag[0][0] = nullptr;
+      lloid_ctx_destroy(c);
+      return fail(LLOID_EDEVICE, "cannot build the interpolation filters");
+    }
+  }
   *out = c;
   return LLOID_OK;
   ABI_GUARD_END
@@ -144,6 +173,7 @@ extern "C" lloid_status lloid_ctx_destroy(lloid_ctx *ctx) {
   if (ctx->ws.base) (void)hipFree(ctx->ws.base);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->d_halfband) (void)hipFree(ctx->d_halfband);
+  if (ctx->d_hfrag[0][0]) (void)hipFree(ctx->d_hfrag[0][0]);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return LLOID_OK;
@@ -181,6 +211,8 @@ extern "C" lloid_status lloid_bank_create(lloid_ctx *ctx, const lloid_bank_desc 
     if (sl.rate_hz <= 0 || f0 % sl.rate_hz || !is_pow2(f0 / sl.rate_hz))
       return fail(LLOID_EINVAL, "slice %d: rate %d Hz is not f0 / 2^k (f0 = %d)", s, sl.rate_hz, f0);
     const int dec = f0 / sl.rate_hz;
+    if (dec > (1 << kMaxLevel))
+      return fail(LLOID_EINVAL, "slice %d: rate %d Hz is below f0 / %d", s, sl.rate_hz, 1 << kMaxLevel);
     if (sl.start_tap < 0 || sl.start_tap % dec)
       return fail(LLOID_EINVAL, "slice %d: start tap %lld is not a non-negative multiple of %d", s,
                   (long long)sl.start_tap, dec);
@@ -351,58 +383,148 @@ lloid_status lloid::ensure_pinned(lloid_ctx *ctx, void *&p, size_t &have, size_t
   return LLOID_OK;
 }
 
-size_t lloid::olow_rows(int64_t t_len, int level) {
-  return (size_t)need_ranges(0, t_len, level + 1)[level].size() + 2;
+lloid::UpPlan lloid::up_plan(int64_t t0, int64_t t1, int level) {
+  UpPlan p;
+  // an odd level starts with one x2 hop at its own (lowest) rate, the rest are x4
+  for (int lev = level; lev > 0;) {
+    const int r = (lev % 2) ? 2 : 4;
+    p.r.push_back(r);
+    p.lev_in.push_back(lev);
+    lev -= r == 4 ? 2 : 1;
+    p.lev_out.push_back(lev);
+  }
+  const int H = (int)p.r.size();
+  p.in.resize(H);
+  p.out.resize(H);
+  // top-down: a hop's outputs, in whole 32-sample tiles from a multiple of 32,
+  // read the 64 source samples of each tile from n0 / R - (32 - 32 / R)
+  Range want{t0, t1};
+  for (int h = H - 1; h >= 0; --h) {
+    p.out[h] = want;
+    const int64_t a = floor_div(want.lo, 32) * 32;
+    const int64_t span = round_up(want.hi - a, kUpCols);
+    const int R = p.r[h], c = 32 - 32 / R;
+    p.in[h] = {a / R - c, (a + span - 32) / R - c + 64};
+    want = p.in[h];
+  }
+  return p;
+}
+
+bool lloid::operands_fit(const lloid_bank *b, int64_t t_len) {
+  if (t_len * b->kcat * (int64_t)dtype_size(b->compute) > kMaxBuffer) return false;
+  for (const auto &sl : b->slices)
+    if (sl.level > 0)
+      for (int64_t ld : low_ld(t_len, sl.level))
+        if ((int64_t)sl.lp * ld * (int64_t)low_esz(b->compute) > kMaxBuffer) return false;
+  return true;
+}
+
+std::vector<int64_t> lloid::low_ld(int64_t t_len, int level) {
+  const UpPlan p = up_plan(0, 1, level);   // hop rates only
+  const int H = (int)p.r.size();
+  std::vector<int64_t> ld(H);
+  int64_t want = t_len;
+  for (int h = H - 1; h >= 0; --h) {
+    // worst case: the first output sits 31 samples past a tile start
+    const int64_t span = round_up(want + 31, kUpCols);
+    const int64_t in = (span - 32) / p.r[h] + 64;
+    ld[h] = round_up(in, 64);
+    want = in;
+  }
+  return ld;
+}
+
+void lloid::interp_fragments(const double *g, int R, int ks_elems, int vec, std::vector<double> &out) {
+  // h_R on |t| <= 32 (R - 1), built by the recursion h_2R[t] = sum_m 2 g[m] h_R[t - R m]
+  std::vector<double> h(2 * kHalfQ + 1);
+  int half = kHalfQ;
+  for (int t = -kHalfQ; t <= kHalfQ; ++t) h[t + kHalfQ] = 2.0 * g[t + kHalfQ];
+  for (int r = 2; r < R; r *= 2) {
+    const int nh = kHalfQ * (2 * r - 1);
+    std::vector<double> h2(2 * nh + 1, 0.0);
+    for (int m = -kHalfQ; m <= kHalfQ; ++m)
+      for (int u = -half; u <= half; ++u) h2[r * m + u + nh] += 2.0 * g[m + kHalfQ] * h[u + half];
+    h.swap(h2);
+    half = nh;
+  }
+  const int nks = 64 / ks_elems;
+  out.assign((size_t)nks * 64 * vec, 0.0);
+  for (int ks = 0; ks < nks; ++ks)
+    for (int lane = 0; lane < 64; ++lane)
+      for (int j = 0; j < vec; ++j) {
+        const int kk = ks * ks_elems + (lane / 32) * vec + j;
+        const int t = lane % 32 - R * kk + 32 * R - 32;
+        out[((size_t)ks * 64 + lane) * vec + j] = (t >= -half && t <= half) ? h[t + half] : 0.0;
+      }
 }
 
 void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, int64_t t1, int64_t n_end, int64_t wa,
                           int64_t wb, const Windows &win, const BankBufs &bb, float inv_scale, float *snr,
-                          int64_t snr_ld, const TileShapes &ts, std::vector<FirJob> &fj, std::vector<InterpJob> &ij,
+                          int64_t snr_ld, const TileShapes &ts, std::vector<FirJob> &fj, std::vector<UpJob> *uj,
                           std::vector<MixJob> &mj) {
+  const size_t lsz = low_esz(b->compute);
+  const int ti = b->compute == LLOID_F16 ? 1 : 0;   // BF16 interpolates FP32 buffers
   for (size_t s = 0; s < b->slices.size(); ++s) {
     const SliceDev &sl = b->slices[s];
-    const Range r = need_ranges(t0, t1, sl.level + 1)[sl.level];
     FirJob j{};
     j.basis = sl.basis;
     j.x = lv[sl.level].x;
     j.x_lo = lv[sl.level].lo;
     j.x_len = lv[sl.level].len;
     j.base = -(sl.start_tap / sl.dec + sl.n_taps - 1);
-    j.k_lo = r.lo;
-    j.k_hi = r.hi;
     j.rows = sl.lrows;
     j.np = sl.np;
     j.n_rtiles = (int)ceil_div(sl.lrows, ts.fbm);
-    j.n_ctiles = (int)ceil_div(r.size(), ts.fbn);
     j.col_limit = sl.lp;
     if (sl.level == 0) {
+      j.k_lo = t0;
+      j.k_hi = t1;
       j.out = bb.ocat;
       j.out_lo = t0;
       j.ldo = b->kcat;
       j.col0 = sl.koff;
-      j.out_f32 = 0;
     } else {
-      j.out = bb.olow[s];
-      j.out_lo = r.lo;
-      j.ldo = sl.lp;
-      j.col0 = 0;
-      j.out_f32 = 1;
-      InterpJob q{};
-      q.src = bb.olow[s];
-      q.src_lo = r.lo;
-      q.src_len = r.size();
-      q.ldw = sl.lp;
-      q.levels = sl.level;
-      q.out = bb.ocat;
-      q.out_abs0 = t0;
-      q.n_out = t1 - t0;
-      q.ldo = b->kcat;
-      q.col0 = sl.koff;
-      q.channels = sl.lp;
-      q.n_rblocks = (int)ceil_div(t1 - t0, 128);
-      q.n_cblocks = (int)ceil_div(sl.lp, 32);
-      ij.push_back(q);
+      // FIR at the slice rate into a channel-major buffer, then the hops up to f0
+      const UpPlan p = up_plan(t0, t1, sl.level);
+      const std::vector<int64_t> ld = low_ld(t1 - t0, sl.level);
+      const int H = (int)p.r.size();
+      j.k_lo = p.in[0].lo;
+      j.k_hi = p.in[0].hi;
+      j.out = bb.low[s][0];
+      j.out_lo = p.in[0].lo;
+      j.ldo = (int)ld[0];
+      j.out_cm = 1;
+      j.out_f32 = b->compute == LLOID_BF16;
+      for (int h = 0; h < H; ++h) {
+        UpJob q{};
+        q.hf = b->ctx->d_hfrag[ti][p.r[h] == 2 ? 0 : 1];
+        q.src = bb.low[s][h];
+        q.src_lo = p.in[h].lo;
+        q.ld_src = (int)ld[h];
+        q.src_bytes = (int64_t)sl.lp * ld[h] * (int64_t)lsz;
+        q.channels = sl.lp;
+        q.r = p.r[h];
+        q.n_lo = p.out[h].lo;
+        q.n_hi = p.out[h].hi;
+        q.n_first = floor_div(p.out[h].lo, 32) * 32;
+        q.n_ctiles = (int)ceil_div(p.out[h].hi - q.n_first, kUpCols);
+        q.n_rtiles = (int)ceil_div(sl.lp, 32);
+        if (h + 1 == H) {
+          q.dst = bb.ocat;
+          q.dst_abs0 = t0;
+          q.ld_dst = b->kcat;
+          q.col0 = sl.koff;
+          q.dst_tm = 1;
+        } else {
+          q.dst = bb.low[s][h + 1];
+          q.dst_abs0 = p.in[h + 1].lo;
+          q.ld_dst = (int)ld[h + 1];
+          q.dst_tm = 0;
+        }
+        uj[h].push_back(q);
+      }
     }
+    j.n_ctiles = (int)ceil_div(j.k_hi - j.k_lo, ts.fbn);
     fj.push_back(j);
   }
   MixJob m{};
@@ -429,16 +551,18 @@ void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, 
   mj.push_back(m);
 }
 
-void lloid::number_jobs(std::vector<FirJob> &fj, std::vector<InterpJob> &ij, std::vector<MixJob> &mj, StageItems &n) {
+void lloid::number_jobs(std::vector<FirJob> &fj, std::vector<UpJob> *uj, std::vector<MixJob> &mj, StageItems &n) {
   // longest items first
   std::stable_sort(fj.begin(), fj.end(), [](const FirJob &a, const FirJob &b) { return a.np > b.np; });
   std::stable_sort(mj.begin(), mj.end(), [](const MixJob &a, const MixJob &b) { return a.kcat > b.kcat; });
   int64_t it = 0;
   for (auto &j : fj) j.item0 = it, it += (int64_t)j.n_rtiles * j.n_ctiles;
   n.fir = it;
-  it = 0;
-  for (auto &q : ij) q.item0 = it, it += (int64_t)q.n_rblocks * q.n_cblocks;
-  n.interp = it;
+  for (int h = 0; h < kMaxHops; ++h) {
+    it = 0;
+    for (auto &q : uj[h]) q.item0 = it, it += ceil_div((int64_t)q.n_rtiles * q.n_ctiles, 4);
+    n.up[h] = it;
+  }
   it = 0;
   int64_t e = 0;
   for (auto &m : mj) {
@@ -461,7 +585,8 @@ lloid_status lloid::launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dt
   HIP_TRY(launch_fir_jobs(ct, (const FirJob *)(dtab + to.fir), to.n_fir, n.fir, st));
   HIP_TRY(mark(LLOID_STAGE_FIR, 1));
   HIP_TRY(mark(LLOID_STAGE_INTERP, 0));
-  HIP_TRY(launch_interp_jobs(ct, (const InterpJob *)(dtab + to.interp), to.n_interp, n.interp, ctx->d_halfband, st));
+  for (int h = 0; h < kMaxHops; ++h)
+    HIP_TRY(launch_up_jobs(ct, (const UpJob *)(dtab + to.up[h]), to.n_up[h], n.up[h], st));
   HIP_TRY(mark(LLOID_STAGE_INTERP, 1));
   HIP_TRY(mark(LLOID_STAGE_MIX, 0));
   HIP_TRY(launch_mix_jobs(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.mix, n.entries, with_snr, phase_thr, st));
@@ -485,7 +610,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     if (banks[i]->compute != ct) return fail(LLOID_EINVAL, "banks of one batch must share the compute type");
   }
   if (n <= 0) return fail(LLOID_EINVAL, "n must be positive");
-  if (n > (int64_t(1) << 29)) return fail(LLOID_EINVAL, "blocks longer than 2^29 samples must be split");
+  if (n > kMaxBlock) return fail(LLOID_EINVAL, "blocks longer than 2^28 samples must be split");
   if (sdt != LLOID_F64 && sdt != LLOID_F32) return fail(LLOID_EINVAL, "strain must be F64 or F32");
   if (trig_cap < 0 || (trig_cap > 0 && !trig)) return fail(LLOID_EINVAL, "bad trigger buffer");
   if (snr && nb != 1) return fail(LLOID_EINVAL, "the SNR series output needs a single bank");
@@ -527,11 +652,21 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   for (int i = 0; i < nb; ++i) {
     bytes_per_sample += banks[i]->kcat * (int64_t)esz;
     for (const auto &sl : banks[i]->slices)
-      if (sl.level > 0) bytes_per_sample += (int64_t)sl.lp * 4 / sl.dec + 1;
+      if (sl.level > 0) {
+        // low-rate buffers: one per hop input, at that hop's source rate
+        const UpPlan p = up_plan(0, 1, sl.level);
+        for (int lev : p.lev_in) bytes_per_sample += ((int64_t)sl.lp * (int64_t)low_esz(ct) >> lev) + 1;
+      }
   }
   const int64_t win_len = ceil_div(win.p, win.q);
   int64_t wpc = std::max<int64_t>(1, ctx->chunk_budget / std::max<int64_t>(1, bytes_per_sample * win_len));
   wpc = std::min(wpc, W);
+  // every buffer a kernel addresses through a buffer resource stays under 2 GiB
+  for (int i = 0; i < nb; ++i)
+    while (wpc > 1 && !operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1))) wpc = (wpc + 1) / 2;
+  for (int i = 0; i < nb; ++i)
+    if (!operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1)))
+      return fail(LLOID_EINVAL, "one trigger window of bank %d needs buffers over 2 GiB", i);
   const int64_t n_chunks = ceil_div(W, wpc);
   const int64_t chunk_n = std::min<int64_t>(n, win.start(wpc) + 1);   // samples of the longest chunk
 
@@ -543,13 +678,14 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   int64_t total_rows = 0;
   for (int i = 0; i < nb; ++i) total_rows += banks[i]->n_templates;
   const int64_t dev_cap = std::min<int64_t>(trig_cap, total_rows * W);
-  size_t n_fir = 0, n_int = 0;
+  size_t n_fir = 0, n_up = 0;
   for (int i = 0; i < nb; ++i)
     for (const auto &sl : banks[i]->slices) {
       ++n_fir;
-      if (sl.level > 0) ++n_int;
+      if (sl.level > 0) n_up += up_plan(0, 1, sl.level).r.size();
     }
-  const size_t tab_bytes = (size_t)n_chunks * (n_fir * sizeof(FirJob) + n_int * sizeof(InterpJob) + nb * sizeof(MixJob) + 192) +
+  const size_t tab_bytes = (size_t)n_chunks * (n_fir * sizeof(FirJob) + n_up * sizeof(UpJob) + nb * sizeof(MixJob) +
+                                               64 * (3 + kMaxHops)) +
                            nb * sizeof(TrigJob) + 256;
   size_t bytes = 0;
   auto add = [&](size_t cnt, size_t sz) { bytes = (size_t)round_up((int64_t)bytes, 256) + cnt * sz; };
@@ -562,7 +698,8 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     add(tab, 4);
     add((size_t)chunk_n * banks[i]->kcat, esz);
     for (const auto &sl : banks[i]->slices)
-      if (sl.level > 0) add(olow_rows(chunk_n, sl.level) * sl.lp, 4);
+      if (sl.level > 0)
+        for (int64_t ld : low_ld(chunk_n, sl.level)) add((size_t)sl.lp * ld, low_esz(ct));
   }
   add((size_t)total_rows + 2, 8);
   add(1, 4);
@@ -592,10 +729,12 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     bw[i].ld_peak = W;
     bw[i].w_base = 0;
     bw[i].ocat = cv.take<char>((size_t)chunk_n * banks[i]->kcat * esz);
-    bw[i].olow.assign(banks[i]->slices.size(), nullptr);
+    bw[i].low.assign(banks[i]->slices.size(), {});
     for (size_t s = 0; s < banks[i]->slices.size(); ++s) {
       const auto &sl = banks[i]->slices[s];
-      if (sl.level > 0) bw[i].olow[s] = cv.take<float>(olow_rows(chunk_n, sl.level) * sl.lp);
+      if (sl.level > 0)
+        for (int64_t ld : low_ld(chunk_n, sl.level))
+          bw[i].low[s].push_back(cv.take<char>((size_t)sl.lp * ld * low_esz(ct)));
     }
   }
   int64_t *counts = cv.take<int64_t>((size_t)total_rows + 2);
@@ -624,18 +763,20 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     const int64_t wa = c * wpc, wb = std::min(W, wa + wpc);
     const int64_t t0 = win.start(wa), t1 = std::min(n, win.start(wb));
     std::vector<FirJob> fj;
-    std::vector<InterpJob> ij;
+    std::vector<UpJob> uj[kMaxHops];
     std::vector<MixJob> mj;
     for (int i = 0; i < nb; ++i)
       add_bank_jobs(banks[i], lv.data(), t0, t1, n, wa, wb, win, bw[i], 1.f / (banks[i]->mix_scale * sscale),
-                    (snr && i == 0) ? dsnr + t0 * 2 : nullptr, n, ts, fj, ij, mj);
-    number_jobs(fj, ij, mj, chunks[c].items);
+                    (snr && i == 0) ? dsnr + t0 * 2 : nullptr, n, ts, fj, uj, mj);
+    number_jobs(fj, uj, mj, chunks[c].items);
     TabOffsets &to = chunks[c].to;
     to.fir = put(fj.data(), fj.size() * sizeof(FirJob));
-    to.interp = put(ij.data(), ij.size() * sizeof(InterpJob));
+    for (int h = 0; h < kMaxHops; ++h) {
+      to.up[h] = put(uj[h].data(), uj[h].size() * sizeof(UpJob));
+      to.n_up[h] = (int)uj[h].size();
+    }
     to.mix = put(mj.data(), mj.size() * sizeof(MixJob));
     to.n_fir = (int)fj.size();
-    to.n_interp = (int)ij.size();
     to.n_mix = (int)mj.size();
   }
   std::vector<TrigJob> tj(nb);

@@ -23,12 +23,12 @@ constexpr int kBK = 32;          // K chunk staged in LDS (FIR; the concatenated
 constexpr int kLPad = 16;        // basis count padding inside the concatenated K
 constexpr int kRowTile = 32;     // MFMA 32x32 tile
 
-// FIR: the four waves share 32 * kFirMT basis rows and split 4 * 32 * kFirNT
-// columns; the strain window of kFirKSup taps is staged in LDS at a time.
-constexpr int kFirMT = 4, kFirNT = 4, kFirKSup = 1024;
-constexpr int kFirBN = kWaves * 32 * kFirNT;
+// FIR: kFirWaves waves share 32 * kFirMT basis rows and split
+// kFirWaves * 32 * kFirNT columns; the strain window of kFirKSup taps is
+// staged in LDS at a time.
+constexpr int kFirMT = 4, kFirNT = 2, kFirWaves = 8, kFirKSup = 1024;
 // Mixing: waves arranged kMixWM x kMixWN, each 32 * kMixMT rows x 32 * kMixNT columns.
-constexpr int kMixMT = 4, kMixNT = 2, kMixWM = 2, kMixWN = 2;
+constexpr int kMixMT = 2, kMixNT = 4, kMixWM = 4, kMixWN = 2;
 constexpr int kMixBM = 32 * kMixMT * kMixWM;
 constexpr int kMixBN = 32 * kMixNT * kMixWN;
 
@@ -66,14 +66,22 @@ struct FirJob {
   void *out;             // column k goes to out[(k - out_lo) * ldo + col0 + l]
   int64_t x_lo, x_len, base, k_lo, k_hi, out_lo, item0;
   int rows, np, ldo, col0, col_limit, n_rtiles, n_ctiles, out_f32;
+  int out_cm;            // channel-major output: out[l * ldo + (k - out_lo)]
+  int pad;
 };
 
-// Interpolation of one slice's low-rate orthogonal SNR to f0 into the operand.
-struct InterpJob {
-  const float *src;      // [src_len][ldw] FP32 at level `levels`, absolute row src_lo at src[0]
-  void *out;             // full-rate row n goes to out[(n - out_abs0) * ldo + col0 + c]
-  int64_t src_lo, src_len, out_abs0, n_out, item0;
-  int ldw, levels, ldo, col0, channels, n_rblocks, n_cblocks, pad;
+// Interpolation of channel-major rows by R = 2 or 4 (one or two half-band x2
+// stages as one composite filter) on MFMA: outputs n in [n_lo, n_hi) of the
+// finer rate, computed in 32-sample tiles aligned to multiples of 32.  The
+// source and a channel-major destination hold the low-rate buffer type
+// (low_esz); a time-major destination is the mixing operand.
+struct UpJob {
+  const void *hf;        // MFMA fragments of the composite filter h_r (see interp_fragments)
+  const void *src;       // channel-major [channels][ld_src], absolute column src_lo at column 0
+  void *dst;             // dst_tm: dst[(n - dst_abs0) * ld_dst + col0 + c]; else dst[c * ld_dst + n - dst_abs0]
+  int64_t src_lo, dst_abs0, n_lo, n_hi, n_first, item0;   // n_first: first tile start (multiple of 32)
+  int64_t src_bytes;     // extent of src for the buffer resource
+  int ld_src, ld_dst, col0, channels, r, dst_tm, n_ctiles, n_rtiles;
 };
 
 // Mixing + peaks of one bank over trigger windows [w0, w0 + nw).
@@ -105,6 +113,8 @@ struct lloid_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   float *d_halfband = nullptr;  // device copy of g[n] (kHalfTaps floats)
+  void *d_hfrag[2][2] = {};     // composite interpolation filters as MFMA fragments,
+                                // [F32, F16][R = 2, 4], in one allocation at d_hfrag[0][0]
   double halfband[lloid::kHalfTaps];
   int n_cu = 0;
   lloid::Workspace ws;          // grow-only device scratch of filter calls on this context
@@ -142,8 +152,9 @@ void fir_tile_shape(int *bm, int *bn);
 void mix_tile_shape(int *bm, int *bn);
 // One launch per stage over a device descriptor table (see the job structs).
 hipError_t launch_fir_jobs(lloid_dtype t, const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s);
-hipError_t launch_interp_jobs(lloid_dtype t, const InterpJob *jobs, int n_jobs, int64_t n_items, const float *g,
-                              hipStream_t s);
+hipError_t launch_up_jobs(lloid_dtype t, const UpJob *jobs, int n_jobs, int64_t n_items, hipStream_t s);
+// Work items of an interpolation job: four 32-channel x 128-sample wave tasks each.
+constexpr int kUpCols = 128;
 // Mixing, peaks and the phase at peaks with |z| >= phase_thr (0 for the others).
 hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_items, int64_t n_entries,
                            bool with_snr, float phase_thr, hipStream_t s);
@@ -169,6 +180,11 @@ inline size_t dtype_size(lloid_dtype t) {
   }
   return 0;
 }
+
+// Element size of the channel-major low-rate buffers (FIR outputs and
+// intermediate interpolation hops): BF16 operands keep these in FP32, since
+// two more roundings to an 8-bit significand would double the SNR error.
+inline size_t low_esz(lloid_dtype t) { return t == LLOID_BF16 ? 4 : dtype_size(t); }
 
 inline bool is_device_ptr(const void *p) {
   hipPointerAttribute_t attr;
@@ -216,7 +232,8 @@ struct LevelView {
 // Per (bank, detector) buffers of one chunk of windows.
 struct BankBufs {
   void *ocat = nullptr;            // [chunk samples][kcat]
-  std::vector<float *> olow;       // per slice at level > 0: [olow_rows][lp]
+  std::vector<std::vector<void *>> low;  // per slice at level > 0: FIR output, then each
+                                         // interpolation hop's output except the last
   float *psnr = nullptr, *pphase = nullptr;
   int64_t *pn = nullptr;
   int64_t ld_peak = 0, w_base = 0; // peak tables [F][ld_peak], column w - w_base
@@ -230,26 +247,51 @@ struct TileShapes {
   }
 };
 
+constexpr int kMaxLevel = 7;       // lowest slice rate f0 / 128
+constexpr int kMaxHops = 4;        // interpolation hops of a level-7 slice: x2, x4, x4, x4
+
 struct StageItems {
-  int64_t fir = 0, interp = 0, mix = 0, entries = 0;
+  int64_t fir = 0, mix = 0, entries = 0;
+  int64_t up[kMaxHops] = {};       // items of each interpolation hop
 };
 
 struct TabOffsets {
-  size_t fir = 0, interp = 0, mix = 0;
-  int n_fir = 0, n_interp = 0, n_mix = 0;
+  size_t fir = 0, mix = 0, up[kMaxHops] = {};
+  int n_fir = 0, n_mix = 0, n_up[kMaxHops] = {};
 };
 
 lloid_status ensure_ws(lloid_ctx *ctx, Workspace &ws, size_t bytes);
 lloid_status ensure_pinned(lloid_ctx *ctx, void *&p, size_t &have, size_t bytes);
-size_t olow_rows(int64_t t_len, int level);
+// Interpolation hops of a slice at `level` for full-rate outputs [t0, t1):
+// hop h maps level lev_in[h] to lev_out[h] by r[h] on range out[h] (aligned
+// tiles), reading in[h]; the FIR must produce in[0].
+struct UpPlan {
+  std::vector<int> r, lev_in, lev_out;
+  std::vector<Range> in, out;
+};
+UpPlan up_plan(int64_t t0, int64_t t1, int level);
+// Row pitch (elements) of each channel-major low-rate buffer of a slice for
+// outputs spanning t_len samples, an upper bound over output positions:
+// [0] the FIR output, [h] the output of hop h - 1.
+std::vector<int64_t> low_ld(int64_t t_len, int level);
+// Buffer resources address 32-bit byte offsets: operand and low-rate buffers
+// of a chunk stay below kMaxBuffer bytes, level buffers below 2^30 bytes.
+constexpr int64_t kMaxBuffer = (int64_t(1) << 31) - (int64_t(1) << 24);
+constexpr int64_t kMaxBlock = int64_t(1) << 28;   // samples of one filter call
+bool operands_fit(const lloid_bank *b, int64_t t_len);
+// Composite interpolation filter of log2(R) cascaded half-band x2 stages
+// (h_2[t] = 2 g[t], h_2R[t] = sum_m 2 g[m] h_R[t - R m]) laid out as MFMA B
+// fragments: entry (ks, lane, j) holds h_R[lane % 32 - R kk + 32 R - 32] with
+// kk = ks * KS + (lane / 32) * VEC + j.
+void interp_fragments(const double *g, int R, int ks_elems, int vec, std::vector<double> &out);
 // Append the FIR, interpolation and mixing jobs of bank b for output samples
 // [t0, t1) (windows [wa, wb), data ending at n_end) to the tables.
 void add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, int64_t t1, int64_t n_end, int64_t wa,
                    int64_t wb, const Windows &win, const BankBufs &bb, float inv_scale, float *snr, int64_t snr_ld,
-                   const TileShapes &ts, std::vector<FirJob> &fj, std::vector<InterpJob> &ij,
+                   const TileShapes &ts, std::vector<FirJob> &fj, std::vector<UpJob> *uj,
                    std::vector<MixJob> &mj);
 // Sort longest-first and number the work items.
-void number_jobs(std::vector<FirJob> &fj, std::vector<InterpJob> &ij, std::vector<MixJob> &mj, StageItems &n);
+void number_jobs(std::vector<FirJob> &fj, std::vector<UpJob> *uj, std::vector<MixJob> &mj, StageItems &n);
 // FIR, interpolation and mixing launches over uploaded tables.
 lloid_status launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dtab, const TabOffsets &to,
                            const StageItems &n, bool with_snr, float phase_thr, bool mark_stages);

@@ -103,97 +103,6 @@ __global__ void k_decimate(const float *__restrict__ u, int64_t u_lo, int64_t u_
   d[t] = acc;
 }
 
-// Interpolation of one slice's low-rate orthogonal SNR up to the full rate:
-// `levels` cascaded x2 stages v[n] = sum_j w[j] 2 g[n - 2j], intermediate
-// rates held in LDS.  A workgroup owns 128 full-rate rows x 32 channels; the
-// index range it needs at each level follows from |n - 2j| <= 32.
-constexpr int kIcRows = 128, kIcChan = 32, kIcMaxRows = 100;
-
-__device__ __forceinline__ int64_t ceil_half(int64_t a) { return a >= 0 ? (a + 1) / 2 : -((-a) / 2); }
-__device__ __forceinline__ int64_t floor_half(int64_t a) { return a >= 0 ? a / 2 : -((-a + 1) / 2); }
-
-// One x2 interpolation stage on a workgroup's LDS rows: input rows [0, irows)
-// hold level j+1 from absolute index ilo, outputs are level-j rows [0, orows)
-// from absolute index olo.  Outputs come in pairs (2q, 2q+1):
-//   v[2q] = w[q],  v[2q+1] = sum_t 2 g[2t+1] (w[q - t] + w[q + 1 + t]),
-// and each thread produces QB consecutive pairs from one register window.
-// Valid outputs only read valid input rows (the ranges come from |n - 2j| <= 32),
-// so reads are clamped rather than branched and stores are predicated.
-template <int QB, int H, typename Store>
-__device__ __forceinline__ void interp_pairs(const float (*in)[kIcChan + 1], int irows, int64_t ilo, int64_t olo,
-                                             int orows, const float *taps, int c, int rg, int groups, Store store) {
-  const int64_t q0 = floor_half(olo);
-  const int nq = (int)(floor_half(olo + orows - 1) - q0) + 1;
-  const int qoff = (int)(q0 - ilo);      // input row of q0
-  const int e0 = (int)(2 * q0 - olo);    // output row of 2 q0 (0 or -1)
-  for (int qb = rg * QB; qb < nq; qb += groups * QB) {
-    float win[QB + 2 * H];
-#pragma unroll
-    for (int t = 0; t < QB + 2 * H; ++t) {
-      int row = qoff + qb - (H - 1) + t;
-      row = row < 0 ? 0 : (row >= irows ? irows - 1 : row);
-      win[t] = in[row][c];
-    }
-#pragma unroll
-    for (int u = 0; u < QB; ++u) {
-      float odd = 0.f;
-#pragma unroll
-      for (int t = 0; t < H; ++t) odd += taps[t] * (win[u + (H - 1) - t] + win[u + H + t]);
-      const int re = e0 + 2 * (qb + u);
-      if (re >= 0 && re < orows) store(re, win[u + (H - 1)]);
-      if (re + 1 >= 0 && re + 1 < orows) store(re + 1, odd);
-    }
-  }
-}
-
-template <typename TO>
-__global__ __launch_bounds__(256) void k_interp_cascade(const InterpJob *__restrict__ jobs, int n_jobs,
-                                                        const float *__restrict__ g) {
-  constexpr int RG = 256 / kIcChan;           // row groups
-  constexpr int H = kHalfQ / 2;               // odd taps on each side
-  __shared__ float buf[2][kIcMaxRows][kIcChan + 1];
-  __shared__ float taps[H];
-  const InterpJob &jb = jobs[find_job(jobs, n_jobs, blockIdx.x)];
-  const int64_t li = (int64_t)blockIdx.x - jb.item0;
-  const int levels = jb.levels, ldw = jb.ldw, channels = jb.channels;
-  const int64_t n0 = (li % jb.n_rblocks) * kIcRows;           // relative to out_abs0
-  const int c0 = (int)(li / jb.n_rblocks) * kIcChan;
-  int64_t lo[8], hi[8];
-  lo[0] = jb.out_abs0 + n0;
-  hi[0] = jb.out_abs0 + (n0 + kIcRows < jb.n_out ? n0 + kIcRows : jb.n_out);
-  for (int j = 1; j <= levels; ++j) {
-    lo[j] = ceil_half(lo[j - 1] - kHalfQ);
-    hi[j] = floor_half(hi[j - 1] - 1 + kHalfQ) + 1;
-  }
-  if (threadIdx.x < H) taps[threadIdx.x] = 2.f * g[kHalfQ + 1 + 2 * threadIdx.x];
-  const int c = threadIdx.x % kIcChan, rg = threadIdx.x / kIcChan;
-  const bool cok = c0 + c < channels;
-  {
-    const int rows = (int)(hi[levels] - lo[levels]);
-    const int64_t j0 = lo[levels] - jb.src_lo;
-    const float *src = jb.src;
-    for (int r = rg; r < rows; r += RG) {
-      const int64_t j = j0 + r;
-      buf[0][r][c] = (cok && j >= 0 && j < jb.src_len) ? src[j * ldw + c0 + c] : 0.f;
-    }
-  }
-  __syncthreads();
-  int cur = 0;
-  for (int lev = levels - 1; lev >= 1; --lev) {
-    float (*dst)[kIcChan + 1] = buf[cur ^ 1];
-    interp_pairs<4, H>(buf[cur], (int)(hi[lev + 1] - lo[lev + 1]), lo[lev + 1], lo[lev], (int)(hi[lev] - lo[lev]), taps,
-                       c, rg, RG, [&](int r, float v) { dst[r][c] = v; });
-    __syncthreads();
-    cur ^= 1;
-  }
-  TO *o = (TO *)jb.out + n0 * (int64_t)jb.ldo + jb.col0 + c0 + c;
-  const int64_t ldo = jb.ldo;
-  interp_pairs<4, H>(buf[cur], (int)(hi[1] - lo[1]), lo[1], lo[0], (int)(hi[0] - lo[0]), taps, c, rg, RG,
-                     [&](int r, float v) {
-                       if (cok) o[r * ldo] = (TO)v;
-                     });
-}
-
 template <typename T>
 __global__ void k_cast_f64(const double *__restrict__ src, T *__restrict__ dst, int64_t n) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -358,8 +267,9 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
     }
   }
 
-  // store: lane holds column i, rows rb..rb+3 for each group of four; lower-rate
-  // slices keep FP32 for the interpolation, level-0 slices write the operand type
+  // store: lane holds column i, rows rb..rb+3 for each group of four; level-0
+  // slices write the time-major operand, lower-rate slices a channel-major
+  // buffer for the interpolation (FP32 when the operand type is BF16)
   const int col_limit = jb.col_limit, ldo = jb.ldo;
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
@@ -372,7 +282,15 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
       for (int g = 0; g < 4; ++g) {
         const int rb = (int)r0 + mt * 32 + 8 * g + 4 * (lane >> 5);
         if (rb + 4 <= col_limit) {
-          if (jb.out_f32) {
+          if (jb.out_cm && jb.out_f32) {
+            float *o = (float *)jb.out + (col - jb.out_lo);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[(int64_t)(rb + q) * ldo] = acc[mt][nt][4 * g + q];
+          } else if (jb.out_cm) {
+            T *o = (T *)jb.out + (col - jb.out_lo);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[(int64_t)(rb + q) * ldo] = O::cvt(acc[mt][nt][4 * g + q]);
+          } else if (jb.out_f32) {
             float *o = (float *)jb.out + ro + rb;
 #pragma unroll
             for (int q = 0; q < 4; ++q) o[q] = acc[mt][nt][4 * g + q];
@@ -384,6 +302,95 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
         }
       }
   }
+}
+
+// ----------------------------------------------------- interpolation on MFMA
+// One or two half-band x2 stages as one composite filter h_R (R = 2 or 4):
+// out[c][n] = sum_u src[c][u] h_R[n - R u].  For a 32-sample output tile at n0
+// (a multiple of 32) the taps that matter are u = U0 + kk, kk < 64, with
+// U0 = n0 / R - (32 - 32 / R), and H[kk][t] = h_R[t - R kk + 32 R - 32] is the
+// same matrix for every tile: it stays in registers as MFMA fragments while
+// the channel-major source rows stream in.  A hop into a channel-major buffer
+// computes D[c][t] (source rows as the A operand); the last hop, into the
+// time-major mixing operand, computes D[t][c] with the operands swapped, so
+// each store instruction writes 32 consecutive channels of two samples.
+// TS: source and low-rate buffer type; TD: operand type of the last hop.
+template <typename TS, typename TD, bool TM>
+__device__ __forceinline__ void upsample_task(const UpJob &jb, int lane, int r0, int64_t n0) {
+  typedef Op<TS> O;
+  constexpr int NKS = 64 / O::KS;  // k-steps over the 64 composite taps
+  constexpr int CT = kUpCols / 32; // 32-sample tiles per task
+  const int R = jb.r;
+  const TS *hf = (const TS *)jb.hf;
+  typename O::vec hfr[NKS];
+#pragma unroll
+  for (int ks = 0; ks < NKS; ++ks) hfr[ks] = *(const typename O::vec *)(hf + (ks * 64 + lane) * O::VEC);
+  const int cR = 32 - 32 / R;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(jb.src, jb.src_bytes);
+  const int64_t rowoff = (int64_t)(r0 + (lane & 31)) * jb.ld_src;
+  f32x16 acc[CT];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
+    const int64_t u0 = (n0 + 32 * t) / R - cR;   // n0 + 32 t is a multiple of R: exact
+    const int64_t base = rowoff + (u0 - jb.src_lo) + (lane >> 5) * O::VEC;
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int off = (int)((base + ks * O::KS) * (int64_t)sizeof(TS));
+      typename O::vec a;
+      if constexpr (O::VEC == 8) {
+        auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        a = __builtin_bit_cast(typename O::vec, v);
+      } else {
+        a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+      }
+      acc[t] = TM ? O::mfma(hfr[ks], a, acc[t]) : O::mfma(a, hfr[ks], acc[t]);
+    }
+  }
+  if constexpr (TM) {
+    // lane holds channel r0 + lane % 32 at samples n0 + 32 t + 8 g + 4 (lane / 32) + q
+    const int c = r0 + (lane & 31);
+    if (c >= jb.channels) return;
+    TD *d = (TD *)jb.dst + jb.col0 + c;
+#pragma unroll
+    for (int t = 0; t < CT; ++t)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t n = n0 + 32 * t + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (n >= jb.n_lo && n < jb.n_hi) d[(n - jb.dst_abs0) * jb.ld_dst] = Op<TD>::cvt(acc[t][e]);
+      }
+  } else {
+    // lane holds sample n0 + 32 t + lane % 32 of channels r0 + 8 g + 4 (lane / 32) + q;
+    // channels is a multiple of 16, so a lane's four channels are all in or all out
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int64_t n = n0 + 32 * t + (lane & 31);
+      if (n < jb.n_lo || n >= jb.n_hi) continue;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int rb = r0 + 8 * g + 4 * (lane >> 5);
+        if (rb >= jb.channels) continue;
+        TS *d = (TS *)jb.dst + (int64_t)rb * jb.ld_dst + (n - jb.dst_abs0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[(int64_t)q * jb.ld_dst] = O::cvt(acc[t][4 * g + q]);
+      }
+    }
+  }
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_upsample(const UpJob *__restrict__ jobs, int n_jobs) {
+  const UpJob &jb = jobs[find_job(jobs, n_jobs, blockIdx.x)];
+  const int64_t li = (int64_t)blockIdx.x - jb.item0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // wave task: 32 channels x kUpCols output samples
+  const int64_t task = li * 4 + wave;
+  if (task >= (int64_t)jb.n_rtiles * jb.n_ctiles) return;
+  const int r0 = (int)(task % jb.n_rtiles) * 32;
+  const int64_t n0 = jb.n_first + (task / jb.n_rtiles) * kUpCols;
+  if (jb.dst_tm) upsample_task<TS, TD, true>(jb, lane, r0, n0);
+  else upsample_task<TS, TD, false>(jb, lane, r0, n0);
 }
 
 // ------------------------------------------------------- mixing + peaks
@@ -722,19 +729,19 @@ static hipError_t fir_v(const FirJob *jobs, int n_jobs, int64_t n_items, hipStre
 template <typename T>
 static hipError_t fir_t(const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s) {
   switch (kernel_variant("LLOID_FIR_VARIANT")) {
-    case 1: return fir_v<T, kFirMT, kFirNT / 2, 8>(jobs, n_jobs, n_items, s);
-    default: return fir_v<T, kFirMT, kFirNT, 4>(jobs, n_jobs, n_items, s);
+    case 1: return fir_v<T, 4, 4, 4>(jobs, n_jobs, n_items, s);
+    default: return fir_v<T, kFirMT, kFirNT, kFirWaves>(jobs, n_jobs, n_items, s);
   }
 }
 
 void fir_tile_shape(int *bm, int *bn) {
   *bm = 32 * kFirMT;
-  *bn = kernel_variant("LLOID_FIR_VARIANT") == 1 ? 8 * 32 * (kFirNT / 2) : 4 * 32 * kFirNT;
+  *bn = kernel_variant("LLOID_FIR_VARIANT") == 1 ? 4 * 32 * 4 : kFirWaves * 32 * kFirNT;
 }
 
 void mix_tile_shape(int *bm, int *bn) {
   switch (kernel_variant("LLOID_MIX_VARIANT")) {
-    case 1: *bm = 32 * 2 * 4, *bn = 32 * 4 * 2; break;
+    case 1: *bm = 32 * 4 * 2, *bn = 32 * 2 * 2; break;
     case 2: *bm = 32 * 2 * 4, *bn = 32 * 2 * 2; break;
     default: *bm = 32 * kMixMT * kMixWM, *bn = 32 * kMixNT * kMixWN; break;
   }
@@ -750,13 +757,12 @@ hipError_t launch_fir_jobs(lloid_dtype t, const FirJob *jobs, int n_jobs, int64_
   }
 }
 
-hipError_t launch_interp_jobs(lloid_dtype t, const InterpJob *jobs, int n_jobs, int64_t n_items, const float *g,
-                              hipStream_t s) {
+hipError_t launch_up_jobs(lloid_dtype t, const UpJob *jobs, int n_jobs, int64_t n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   switch (t) {
-    case LLOID_F32: k_interp_cascade<float><<<(unsigned)n_items, 256, 0, s>>>(jobs, n_jobs, g); break;
-    case LLOID_F16: k_interp_cascade<_Float16><<<(unsigned)n_items, 256, 0, s>>>(jobs, n_jobs, g); break;
-    case LLOID_BF16: k_interp_cascade<__bf16><<<(unsigned)n_items, 256, 0, s>>>(jobs, n_jobs, g); break;
+    case LLOID_F32: k_upsample<float, float><<<(unsigned)n_items, 256, 0, s>>>(jobs, n_jobs); break;
+    case LLOID_F16: k_upsample<_Float16, _Float16><<<(unsigned)n_items, 256, 0, s>>>(jobs, n_jobs); break;
+    case LLOID_BF16: k_upsample<float, __bf16><<<(unsigned)n_items, 256, 0, s>>>(jobs, n_jobs); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -776,7 +782,7 @@ static hipError_t mix_t(const MixJob *jobs, int n_jobs, int64_t n_items, int64_t
                         float phase_thr, hipStream_t s) {
   hipError_t e;
   switch (kernel_variant("LLOID_MIX_VARIANT")) {
-    case 1: e = mix_v<T, 2, 4, 4, 2, 32>(jobs, n_jobs, n_items, with_snr, s); break;
+    case 1: e = mix_v<T, 4, 2, 2, 2, 32>(jobs, n_jobs, n_items, with_snr, s); break;
     case 2: e = mix_v<T, 2, 2, 4, 2, 32>(jobs, n_jobs, n_items, with_snr, s); break;
     default: e = mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 32>(jobs, n_jobs, n_items, with_snr, s); break;
   }

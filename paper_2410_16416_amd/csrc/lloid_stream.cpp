@@ -76,7 +76,8 @@ int64_t scratch_bytes(const lloid_stream *s, const lloid_bank *b) {
   const int64_t ts = tick_samples(s);
   int64_t per = (int64_t)ts * b->kcat * (int64_t)dtype_size(b->compute);
   for (const auto &sl : b->slices)
-    if (sl.level > 0) per += (int64_t)olow_rows(ts, sl.level) * sl.lp * 4;
+    if (sl.level > 0)
+      for (int64_t ld : low_ld(ts, sl.level)) per += (int64_t)sl.lp * ld * (int64_t)low_esz(b->compute) + 256;
   per += (int64_t)b->n_templates * s->max_w * (16 + (int64_t)sizeof(lloid_trigger)) + 4096;
   return per * s->n_det;
 }
@@ -87,6 +88,7 @@ lloid_status check_bank(const lloid_stream *s, const lloid_bank *b) {
   if (b->f0 != s->f0) return fail(LLOID_EINVAL, "the bank's full rate differs from the stream's");
   if (b->compute != s->ct) return fail(LLOID_EINVAL, "the bank's compute type differs from the stream's");
   if (b->n_levels > s->n_levels) return fail(LLOID_EINVAL, "the bank's lowest rate is below the stream's");
+  if (!operands_fit(b, tick_samples(s))) return fail(LLOID_EINVAL, "the bank's per-tick buffers exceed 2 GiB");
   for (const auto &sl : b->slices) {
     const int64_t span = sl.start_tap / sl.dec + sl.n_taps + 4 * kHalfQ;
     if (span > s->hist[sl.level]) return fail(LLOID_EINVAL, "a slice spans more than the stream's history");
@@ -187,14 +189,15 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
   size_t bytes = 0;
   auto add = [&](size_t cnt, size_t sz) { bytes = (size_t)round_up((int64_t)bytes, 256) + cnt * sz; };
   int64_t rows = 0;
-  size_t n_fir = 0, n_int = 0;
+  size_t n_fir = 0, n_up = 0;
   for (int i : act) {
     const lloid_bank *b = s->slots[i].bank;
     for (int d = 0; d < s->n_det; ++d) {
       add((size_t)tlen * b->kcat, esz);
       for (const auto &sl : b->slices) {
         ++n_fir;
-        if (sl.level > 0) add(olow_rows(tlen, sl.level) * sl.lp, 4), ++n_int;
+        if (sl.level > 0)
+          for (int64_t ld : low_ld(tlen, sl.level)) add((size_t)sl.lp * ld, low_esz(s->ct)), ++n_up;
       }
       add((size_t)b->n_templates * nw, 4);
       add((size_t)b->n_templates * nw, 8);
@@ -204,8 +207,8 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
   }
   add((size_t)rows + 2, 8);
   add((size_t)rows * nw, sizeof(lloid_trigger));
-  const size_t tab_bytes = n_fir * sizeof(FirJob) + n_int * sizeof(InterpJob) +
-                           act.size() * s->n_det * (sizeof(MixJob) + sizeof(TrigJob)) + 1024;
+  const size_t tab_bytes = n_fir * sizeof(FirJob) + n_up * sizeof(UpJob) +
+                           act.size() * s->n_det * (sizeof(MixJob) + sizeof(TrigJob)) + 64 * (4 + kMaxHops);
   add(tab_bytes, 1);
   lloid_status rs = ensure_ws(ctx, s->ws, bytes);
   if (rs != LLOID_OK) return rs;
@@ -213,7 +216,7 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
   if (rs != LLOID_OK) return rs;
   Carve cv{(char *)s->ws.base};
   std::vector<FirJob> fj;
-  std::vector<InterpJob> ij;
+  std::vector<UpJob> uj[kMaxHops];
   std::vector<MixJob> mj;
   std::vector<TrigJob> tj;
   int64_t row = 0;
@@ -222,9 +225,11 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
     for (int d = 0; d < s->n_det; ++d) {
       BankBufs bb;
       bb.ocat = cv.take<char>((size_t)tlen * b->kcat * esz);
-      bb.olow.assign(b->slices.size(), nullptr);
+      bb.low.assign(b->slices.size(), {});
       for (size_t k = 0; k < b->slices.size(); ++k)
-        if (b->slices[k].level > 0) bb.olow[k] = cv.take<float>(olow_rows(tlen, b->slices[k].level) * b->slices[k].lp);
+        if (b->slices[k].level > 0)
+          for (int64_t ld : low_ld(tlen, b->slices[k].level))
+            bb.low[k].push_back(cv.take<char>((size_t)b->slices[k].lp * ld * low_esz(s->ct)));
       bb.psnr = cv.take<float>((size_t)b->n_templates * nw);
       bb.pn = cv.take<int64_t>((size_t)b->n_templates * nw);
       bb.pphase = cv.take<float>((size_t)b->n_templates * nw);
@@ -234,7 +239,7 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
       const DetState &ds = s->det[d];
       for (int k = 0; k < s->n_levels; ++k) lv[k] = LevelView{ds.x[k], ds.lo[k], ds.avail[k] - ds.lo[k]};
       add_bank_jobs(b, lv.data(), t0, t1, n_end, wa, wb, s->win, bb, 1.f / (b->mix_scale * s->sscale), nullptr, 0, ts,
-                    fj, ij, mj);
+                    fj, uj, mj);
       tj.push_back(TrigJob{bb.psnr, bb.pn, bb.pphase, nw, wa, nw, row, b->n_templates, s->slots[i].id, d, 0});
       row += b->n_templates;
     }
@@ -245,7 +250,7 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
   lloid_trigger *dtrig = cv.take<lloid_trigger>((size_t)std::max<int64_t>(cap, 1));
   char *dtab = cv.take<char>(tab_bytes);
   StageItems items;
-  number_jobs(fj, ij, mj, items);
+  number_jobs(fj, uj, mj, items);
   char *htab = (char *)s->pinned;
   size_t off = 0;
   auto put = [&](const void *src, size_t sz) -> size_t {
@@ -257,10 +262,12 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
   };
   TabOffsets to;
   to.fir = put(fj.data(), fj.size() * sizeof(FirJob));
-  to.interp = put(ij.data(), ij.size() * sizeof(InterpJob));
+  for (int h = 0; h < kMaxHops; ++h) {
+    to.up[h] = put(uj[h].data(), uj[h].size() * sizeof(UpJob));
+    to.n_up[h] = (int)uj[h].size();
+  }
   to.mix = put(mj.data(), mj.size() * sizeof(MixJob));
   to.n_fir = (int)fj.size();
-  to.n_interp = (int)ij.size();
   to.n_mix = (int)mj.size();
   const size_t trig_off = put(tj.data(), tj.size() * sizeof(TrigJob));
   HIP_TRY(hipMemcpyAsync(dtab, htab, off, hipMemcpyHostToDevice, st));
