@@ -670,7 +670,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   const int64_t n_chunks = ceil_div(W, wpc);
   const int64_t chunk_n = std::min<int64_t>(n, win.start(wpc) + 1);   // samples of the longest chunk
 
-  const TileShapes ts;
+  const TileShapes ts(ct);
 
   // ---- workspace layout
   const bool host_strain = !is_device_ptr(strain);

@@ -149,7 +149,7 @@ hipError_t launch_decimate(const float *u, int64_t u_lo, int64_t u_len, float *d
                            int64_t d_len, const float *g, hipStream_t s);
 // Tile shapes (rows x columns per workgroup) of the FIR and mixing kernels in use.
 void fir_tile_shape(int *bm, int *bn);
-void mix_tile_shape(int *bm, int *bn);
+void mix_tile_shape(lloid_dtype t, int *bm, int *bn);
 // One launch per stage over a device descriptor table (see the job structs).
 hipError_t launch_fir_jobs(lloid_dtype t, const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s);
 hipError_t launch_up_jobs(lloid_dtype t, const UpJob *jobs, int n_jobs, int64_t n_items, hipStream_t s);
@@ -241,9 +241,9 @@ struct BankBufs {
 
 struct TileShapes {
   int fbm, fbn, mbm, mbn;
-  TileShapes() {
+  explicit TileShapes(lloid_dtype t) {
     fir_tile_shape(&fbm, &fbn);
-    mix_tile_shape(&mbm, &mbn);
+    mix_tile_shape(t, &mbm, &mbn);
   }
 };
 

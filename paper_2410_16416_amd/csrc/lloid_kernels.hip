@@ -739,10 +739,14 @@ void fir_tile_shape(int *bm, int *bn) {
   *bn = kernel_variant("LLOID_FIR_VARIANT") == 1 ? 4 * 32 * 4 : kFirWaves * 32 * kFirNT;
 }
 
-void mix_tile_shape(int *bm, int *bn) {
-  switch (kernel_variant("LLOID_MIX_VARIANT")) {
+void mix_tile_shape(lloid_dtype t, int *bm, int *bn) {
+  int v = kernel_variant("LLOID_MIX_VARIANT");
+  if (t == LLOID_F32 && v >= 3) v = 0;
+  switch (v) {
     case 1: *bm = 32 * 4 * 2, *bn = 32 * 2 * 2; break;
     case 2: *bm = 32 * 2 * 4, *bn = 32 * 2 * 2; break;
+    case 3: *bm = 32 * 4 * 2, *bn = 32 * 4 * 2; break;    // 16-bit operands only
+    case 4: *bm = 32 * 4 * 4, *bn = 32 * 4 * 2; break;    // 16-bit operands only
     default: *bm = 32 * kMixMT * kMixWM, *bn = 32 * kMixNT * kMixWN; break;
   }
 }
@@ -784,6 +788,18 @@ static hipError_t mix_t(const MixJob *jobs, int n_jobs, int64_t n_items, int64_t
   switch (kernel_variant("LLOID_MIX_VARIANT")) {
     case 1: e = mix_v<T, 4, 2, 2, 2, 32>(jobs, n_jobs, n_items, with_snr, s); break;
     case 2: e = mix_v<T, 2, 2, 4, 2, 32>(jobs, n_jobs, n_items, with_snr, s); break;
+    case 3:
+      if constexpr (sizeof(T) == 2) {
+        e = mix_v<T, 4, 4, 2, 2, 32>(jobs, n_jobs, n_items, with_snr, s);
+        break;
+      }
+      [[fallthrough]];
+    case 4:
+      if constexpr (sizeof(T) == 2) {
+        e = mix_v<T, 4, 4, 4, 2, 32>(jobs, n_jobs, n_items, with_snr, s);
+        break;
+      }
+      [[fallthrough]];
     default: e = mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 32>(jobs, n_jobs, n_items, with_snr, s); break;
   }
   if (e != hipSuccess) return e;

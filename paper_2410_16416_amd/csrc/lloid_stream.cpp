@@ -182,7 +182,7 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
   s->w_next = wb;
   s->windows += nw;
   if (act.empty()) return LLOID_OK;
-  const TileShapes ts;
+  const TileShapes ts(s->ct);
   const size_t esz = dtype_size(s->ct);
   const int64_t tlen = t1 - t0;
   // scratch layout
