@@ -49,12 +49,13 @@ def stage_work(bank, seconds: float, compute: str):
 
     FIR: 2 L_s N_s r_s flops per second of data; mixing: 2 (2F) L_s r_s
     (the method's order: mix at the slice rate).  Interpolation moves the
-    low-rate orthogonal SNR (FP32 read) to the full-rate operand (write in
-    the operand type)."""
+    low-rate orthogonal SNR (read once, in the low-rate buffer type: FP32 for
+    f32 and bf16 operands) to the full-rate operand (written once)."""
     esz = 4 if compute == "f32" else 2
+    lsz = 2 if compute == "f16" else 4
     fir = sum(2.0 * s.n_basis * s.n_taps * s.rate for s in bank.slices) * seconds
     mix = sum(2.0 * 2 * bank.n_templates * s.n_basis * s.rate for s in bank.slices) * seconds
-    interp = sum((s.n_basis * s.rate * 4 + s.n_basis * bank.f0 * esz)
+    interp = sum((s.n_basis * s.rate * lsz + s.n_basis * bank.f0 * esz)
                  for s in bank.slices if s.rate != bank.f0) * seconds
     decim = sum(4.0 * bank.f0 / 2 ** k * 1.5 for k in range(1, 5)) * seconds
     return {"fir": ("mfma", fir), "mix": ("mfma", mix), "interp": ("hbm", interp), "decimate": ("hbm", decim)}

@@ -140,9 +140,10 @@ typedef enum {
   LLOID_STAGE_FIR = 2,       /* basis-filter correlation, all slices */
   LLOID_STAGE_INTERP = 3,    /* interpolation of low-rate orthogonal SNR to f0 */
   LLOID_STAGE_MIX = 4,       /* mixing GEMM + complex SNR + window peaks */
-  LLOID_STAGE_TRIGGER = 5,   /* trigger compaction */
-  LLOID_STAGE_D2H = 6,       /* results to the caller's buffers */
-  LLOID_N_STAGES = 7
+  LLOID_STAGE_PHASE = 5,     /* phase of the complex SNR at each window peak */
+  LLOID_STAGE_TRIGGER = 6,   /* trigger compaction */
+  LLOID_STAGE_D2H = 7,       /* results to the caller's buffers */
+  LLOID_N_STAGES = 8
 } lloid_stage;
 
 /* Turn per-stage timing on (1) or off (0).  While on, every lloid_filter call

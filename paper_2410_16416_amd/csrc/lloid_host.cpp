@@ -589,8 +589,11 @@ lloid_status lloid::launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dt
     HIP_TRY(launch_up_jobs(ct, (const UpJob *)(dtab + to.up[h]), to.n_up[h], n.up[h], st));
   HIP_TRY(mark(LLOID_STAGE_INTERP, 1));
   HIP_TRY(mark(LLOID_STAGE_MIX, 0));
-  HIP_TRY(launch_mix_jobs(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.mix, n.entries, with_snr, phase_thr, st));
+  HIP_TRY(launch_mix_jobs(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.mix, with_snr, st));
   HIP_TRY(mark(LLOID_STAGE_MIX, 1));
+  HIP_TRY(mark(LLOID_STAGE_PHASE, 0));
+  HIP_TRY(launch_peak_phase(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.entries, phase_thr, st));
+  HIP_TRY(mark(LLOID_STAGE_PHASE, 1));
   return LLOID_OK;
 }
 // Filter one block of strain of one detector with every bank of `banks`

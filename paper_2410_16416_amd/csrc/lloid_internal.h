@@ -155,9 +155,11 @@ hipError_t launch_fir_jobs(lloid_dtype t, const FirJob *jobs, int n_jobs, int64_
 hipError_t launch_up_jobs(lloid_dtype t, const UpJob *jobs, int n_jobs, int64_t n_items, hipStream_t s);
 // Work items of an interpolation job: four 32-channel x 128-sample wave tasks each.
 constexpr int kUpCols = 128;
-// Mixing, peaks and the phase at peaks with |z| >= phase_thr (0 for the others).
-hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_items, int64_t n_entries,
-                           bool with_snr, float phase_thr, hipStream_t s);
+// Mixing and window peaks; then the phase at peaks with |z| >= phase_thr (0 for the others).
+hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_items, bool with_snr,
+                           hipStream_t s);
+hipError_t launch_peak_phase(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float phase_thr,
+                             hipStream_t s);
 // Trigger compaction: counts, offsets and records (job-major, template, window).
 hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_rows, float thr, int64_t *counts,
                                int64_t *total, int64_t cap, lloid_trigger *out, hipStream_t s);

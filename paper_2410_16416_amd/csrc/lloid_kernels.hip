@@ -739,14 +739,10 @@ void fir_tile_shape(int *bm, int *bn) {
   *bn = kernel_variant("LLOID_FIR_VARIANT") == 1 ? 4 * 32 * 4 : kFirWaves * 32 * kFirNT;
 }
 
-void mix_tile_shape(lloid_dtype t, int *bm, int *bn) {
-  int v = kernel_variant("LLOID_MIX_VARIANT");
-  if (t == LLOID_F32 && v >= 3) v = 0;
-  switch (v) {
+void mix_tile_shape(lloid_dtype, int *bm, int *bn) {
+  switch (kernel_variant("LLOID_MIX_VARIANT")) {
     case 1: *bm = 32 * 4 * 2, *bn = 32 * 2 * 2; break;
     case 2: *bm = 32 * 2 * 4, *bn = 32 * 2 * 2; break;
-    case 3: *bm = 32 * 4 * 2, *bn = 32 * 4 * 2; break;    // 16-bit operands only
-    case 4: *bm = 32 * 4 * 4, *bn = 32 * 4 * 2; break;    // 16-bit operands only
     default: *bm = 32 * kMixMT * kMixWM, *bn = 32 * kMixNT * kMixWN; break;
   }
 }
@@ -782,41 +778,36 @@ static hipError_t mix_v(const MixJob *jobs, int n_jobs, int64_t n_items, bool wi
 }
 
 template <typename T>
-static hipError_t mix_t(const MixJob *jobs, int n_jobs, int64_t n_items, int64_t n_entries, bool with_snr,
-                        float phase_thr, hipStream_t s) {
-  hipError_t e;
+static hipError_t mix_t(const MixJob *jobs, int n_jobs, int64_t n_items, bool with_snr, hipStream_t s) {
   switch (kernel_variant("LLOID_MIX_VARIANT")) {
-    case 1: e = mix_v<T, 4, 2, 2, 2, 32>(jobs, n_jobs, n_items, with_snr, s); break;
-    case 2: e = mix_v<T, 2, 2, 4, 2, 32>(jobs, n_jobs, n_items, with_snr, s); break;
-    case 3:
-      if constexpr (sizeof(T) == 2) {
-        e = mix_v<T, 4, 4, 2, 2, 32>(jobs, n_jobs, n_items, with_snr, s);
-        break;
-      }
-      [[fallthrough]];
-    case 4:
-      if constexpr (sizeof(T) == 2) {
-        e = mix_v<T, 4, 4, 4, 2, 32>(jobs, n_jobs, n_items, with_snr, s);
-        break;
-      }
-      [[fallthrough]];
-    default: e = mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 32>(jobs, n_jobs, n_items, with_snr, s); break;
+    case 1: return mix_v<T, 4, 2, 2, 2, 32>(jobs, n_jobs, n_items, with_snr, s);
+    case 2: return mix_v<T, 2, 2, 4, 2, 32>(jobs, n_jobs, n_items, with_snr, s);
+    default: return mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 32>(jobs, n_jobs, n_items, with_snr, s);
   }
-  if (e != hipSuccess) return e;
-  if (n_entries > 0)
-    k_peak_phase<T><<<(unsigned)((n_entries + 3) / 4), 256, 0, s>>>(jobs, n_jobs, n_entries, phase_thr);
-  return hipGetLastError();
 }
 
-hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_items, int64_t n_entries,
-                           bool with_snr, float phase_thr, hipStream_t s) {
+hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_items, bool with_snr,
+                           hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   switch (t) {
-    case LLOID_F16: return mix_t<_Float16>(jobs, n_jobs, n_items, n_entries, with_snr, phase_thr, s);
-    case LLOID_BF16: return mix_t<__bf16>(jobs, n_jobs, n_items, n_entries, with_snr, phase_thr, s);
-    case LLOID_F32: return mix_t<float>(jobs, n_jobs, n_items, n_entries, with_snr, phase_thr, s);
+    case LLOID_F16: return mix_t<_Float16>(jobs, n_jobs, n_items, with_snr, s);
+    case LLOID_BF16: return mix_t<__bf16>(jobs, n_jobs, n_items, with_snr, s);
+    case LLOID_F32: return mix_t<float>(jobs, n_jobs, n_items, with_snr, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_peak_phase(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float phase_thr,
+                             hipStream_t s) {
+  if (n_entries <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n_entries + 3) / 4);
+  switch (t) {
+    case LLOID_F16: k_peak_phase<_Float16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, phase_thr); break;
+    case LLOID_BF16: k_peak_phase<__bf16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, phase_thr); break;
+    case LLOID_F32: k_peak_phase<float><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, phase_thr); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_rows, float thr, int64_t *counts,

@@ -164,7 +164,7 @@ def lloid_ctx_destroy(ctx):
     _check(_lib.lloid_ctx_destroy(ctx))
 
 
-STAGES = ["ingest", "decimate", "fir", "interp", "mix", "trigger", "d2h"]
+STAGES = ["ingest", "decimate", "fir", "interp", "mix", "phase", "trigger", "d2h"]
 
 
 def lloid_ctx_profile(ctx, enable: bool):

@@ -92,7 +92,8 @@ def test_continuous_batching_admission_and_removal():
             sizes.append(lloid.lloid_stream_stats_get(s0).bytes_in_use - sum(sizes))
     finally:
         lloid.lloid_stream_destroy(s0)
-    budget = sizes[0] + max(sizes[1], sizes[2]) + 1
+    # a + b fit, b + c fit, a + b + c do not
+    budget = sizes[1] + max(sizes[0], sizes[2])
     s = lloid.lloid_stream_create(ctx(), f0, "f16", n_detectors=2, min_rate_hz=64, window=(1, 2),
                                   threshold=3.0, max_filter_s=4.0, hbm_budget=budget)
     try:
@@ -118,6 +119,8 @@ def test_continuous_batching_admission_and_removal():
                 lloid.lloid_stream_push(s, d, pos, strains[d][pos:pos + stride])
             if k == 12:
                 admitted[c] = removed[a]                  # enters at the next tick
+                st = lloid.lloid_stream_stats_get(s)
+                assert st.active_slots == 2 and st.queued_banks == 0
             got.append(lloid.lloid_stream_poll(s))
             pos += stride
             k += 1
