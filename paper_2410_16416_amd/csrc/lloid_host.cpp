@@ -560,7 +560,8 @@ void lloid::number_jobs(std::vector<FirJob> &fj, std::vector<UpJob> *uj, std::ve
   n.fir = it;
   for (int h = 0; h < kMaxHops; ++h) {
     it = 0;
-    for (auto &q : uj[h]) q.item0 = it, it += ceil_div((int64_t)q.n_rtiles * q.n_ctiles, 4);
+    // 8 runs (one per XCD) of ceil(tasks / 32) items of 4 tasks
+    for (auto &q : uj[h]) q.item0 = it, it += 8 * ceil_div((int64_t)q.n_rtiles * q.n_ctiles, 32);
     n.up[h] = it;
   }
   it = 0;

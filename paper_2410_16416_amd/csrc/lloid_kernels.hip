@@ -197,12 +197,12 @@ template <typename T, int ROWS, int BK = kBK, int THREADS = kThreads> struct Chu
 // consecutive samples are one aligned read whatever its column; the basis
 // streams through double-buffered LDS with the next chunk's global reads in
 // flight during the current chunk's MFMAs.
-template <typename T, int MT, int NT, int NW>
+template <typename T, int MT, int NT, int NW, int BK>
 __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs, int n_jobs) {
   typedef Op<T> O;
   constexpr int THREADS = 64 * NW;
   constexpr int BM = 32 * MT, BN = NW * 32 * NT;
-  constexpr int P = Pitch<T>::value;
+  constexpr int P = Pitch<T, BK>::value;
   constexpr int WC = BN + kFirKSup + 16;
   __shared__ __attribute__((aligned(16))) T As[2][BM * P];
   __shared__ __attribute__((aligned(16))) T Bc[O::VEC * WC];
@@ -227,16 +227,18 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
   const __amdgpu_buffer_rsrc_t ra = make_rsrc(a + r0 * np, (rows - r0) * (int64_t)np * (int64_t)sizeof(T));
   const __amdgpu_buffer_rsrc_t rx = make_rsrc(jb.x, jb.x_len * 4);
   const int64_t x_len = jb.x_len;
-  ChunkLoader<T, BM, kBK, THREADS> la;
+  ChunkLoader<T, BM, BK, THREADS> la;
   la.setup(np);
   la.load(ra, 0);
-  const int nchunks = np / kBK;
+  // np is a multiple of kBK; with BK = 2 kBK the last chunk may hold one
+  // valid half (the k-steps past np are skipped, whatever the loads brought)
+  const int nchunks = (np + BK - 1) / BK;
   // lane's shifted copy: its column offset within a fragment is constant mod VEC
   const int lr = (lane & 31) % O::VEC;
   const T *bl = Bc + lr * WC + (wave * NT * 32 + (lane & 31) + (lane >> 5) * O::VEC - lr);
   int ksup = 0;
   for (int c = 0; c < nchunks; ++c) {
-    const int cur = c & 1, kc = c * kBK;
+    const int cur = c & 1, kc = c * BK;
     if (kc % kFirKSup == 0) {
       // new strain window for taps [kc, kc + kFirKSup); out-of-range samples read as zero
       if (c > 0) __syncthreads();
@@ -251,9 +253,10 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
     }
     la.store(As[cur]);
     __syncthreads();
-    if (c + 1 < nchunks) la.load(ra, (kc + kBK) * (int)sizeof(T));
+    if (c + 1 < nchunks) la.load(ra, (kc + BK) * (int)sizeof(T));
 #pragma unroll
-    for (int ks = 0; ks < kBK / O::KS; ++ks) {
+    for (int ks = 0; ks < BK / O::KS; ++ks) {
+      if (BK > kBK && kc + ks * O::KS >= np) break;
       typename O::vec af[MT], bf[NT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
@@ -382,11 +385,17 @@ __device__ __forceinline__ void upsample_task(const UpJob &jb, int lane, int r0,
 template <typename TS, typename TD>
 __global__ __launch_bounds__(256) void k_upsample(const UpJob *__restrict__ jobs, int n_jobs) {
   const UpJob &jb = jobs[find_job(jobs, n_jobs, blockIdx.x)];
-  const int64_t li = (int64_t)blockIdx.x - jb.item0;
+  // The 8 XCDs take workgroups round-robin and every job's items start at a
+  // multiple of 8: give each XCD one contiguous run of the job's tasks, so
+  // neighbouring column tiles (whose source windows overlap) share one L2.
+  const int64_t n_tasks = (int64_t)jb.n_rtiles * jb.n_ctiles;
+  const int64_t per_xcd = (n_tasks + 31) / 32;          // items per XCD, 4 tasks each
+  const int64_t b = (int64_t)blockIdx.x - jb.item0;
+  const int64_t li = (b & 7) * per_xcd + (b >> 3);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // wave task: 32 channels x kUpCols output samples
   const int64_t task = li * 4 + wave;
-  if (task >= (int64_t)jb.n_rtiles * jb.n_ctiles) return;
+  if (task >= n_tasks) return;
   const int r0 = (int)(task % jb.n_rtiles) * 32;
   const int64_t n0 = jb.n_first + (task / jb.n_rtiles) * kUpCols;
   if (jb.dst_tm) upsample_task<TS, TD, true>(jb, lane, r0, n0);
@@ -454,7 +463,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mix_peak(const MixJob *__restr
   constexpr int ESZ = (int)sizeof(T);
   const __amdgpu_buffer_rsrc_t ra = make_rsrc(mix + r0 * kcat, (rows - r0) * (int64_t)kcat * ESZ);
   const __amdgpu_buffer_rsrc_t rb = make_rsrc(ocat, (we - ws) * (int64_t)kcat * ESZ);
-  const int nchunks = kcat / BK;
+  // kcat is a multiple of 32; with BK = 64 the k-steps past kcat are skipped
+  const int nchunks = (kcat + BK - 1) / BK;
   ChunkLoader<T, BM, BK, THREADS> la;
   ChunkLoader<T, BN, BK, THREADS> lb;
   la.setup(kcat);
@@ -486,6 +496,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mix_peak(const MixJob *__restr
       }
 #pragma unroll
       for (int ks = 0; ks < BK / O::KS; ++ks) {
+        if (BK > 32 && c * BK + ks * O::KS >= kcat) break;
         typename O::vec af[MT], bf[NT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -555,13 +566,18 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mix_peak(const MixJob *__restr
 }
 
 // Phase at each reported window peak: z_i[n*] recomputed as the dot products
-// of mixing rows 2i, 2i+1 with the operand row at n* (FP32 accumulation, one
-// wave per peak).  Peaks below `thr` get phase 0 (not reported).
+// of mixing rows 2i, 2i+1 with the operand row at n* (FP32 accumulation), one
+// thread per (template, window) entry reading 16-byte vectors.  Peaks below
+// `thr` get phase 0 (not reported), so only the entries that become triggers
+// do the work.
+template <typename T> struct Vec16 {
+  T v[16 / sizeof(T)];
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ jobs, int n_jobs, int64_t entries,
                                                     float thr) {
-  const int lane = threadIdx.x & 63;
-  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= entries) return;
   // job owning entry e: last job with e0 <= e
   int lo = 0, hi = n_jobs - 1;
@@ -575,25 +591,27 @@ __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ j
   const int64_t i = le / jb.nw, wl = le - i * jb.nw;
   const int64_t o = i * jb.ld_peak + (jb.w0 + wl - jb.w_base);
   if (!(jb.peak_snr[o] >= thr)) {
-    if (lane == 0) jb.peak_phase[o] = 0.f;
+    jb.peak_phase[o] = 0.f;
     return;
   }
-  const int kcat = jb.kcat;
-  const T *orow = (const T *)jb.ocat + (jb.peak_n[o] - jb.ocat_abs0) * (int64_t)kcat;
-  const T *mc = (const T *)jb.mix + (2 * i) * (int64_t)kcat;
-  const T *ms = mc + kcat;
+  constexpr int EPV = 16 / (int)sizeof(T);
+  const int kcat = jb.kcat;   // a multiple of 32: rows are whole 16-byte vectors
+  const uint4 *orow = (const uint4 *)((const T *)jb.ocat + (jb.peak_n[o] - jb.ocat_abs0) * (int64_t)kcat);
+  const uint4 *mc = (const uint4 *)((const T *)jb.mix + (2 * i) * (int64_t)kcat);
+  const uint4 *ms = mc + kcat / EPV;
   float re = 0.f, im = 0.f;
-  for (int k = lane; k < kcat; k += 64) {
-    const float ov = Op<T>::tof(orow[k]);
-    re += Op<T>::tof(mc[k]) * ov;
-    im += Op<T>::tof(ms[k]) * ov;
-  }
+  for (int k = 0; k < kcat / EPV; ++k) {
+    const Vec16<T> a = __builtin_bit_cast(Vec16<T>, orow[k]);
+    const Vec16<T> c = __builtin_bit_cast(Vec16<T>, mc[k]);
+    const Vec16<T> d = __builtin_bit_cast(Vec16<T>, ms[k]);
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    re += __shfl_xor(re, off);
-    im += __shfl_xor(im, off);
+    for (int j = 0; j < EPV; ++j) {
+      const float ov = Op<T>::tof(a.v[j]);
+      re += Op<T>::tof(c.v[j]) * ov;
+      im += Op<T>::tof(d.v[j]) * ov;
+    }
   }
-  if (lane == 0) jb.peak_phase[o] = atan2f(im, re);
+  jb.peak_phase[o] = atan2f(im, re);
 }
 
 // ---------------------------------------------------------- trigger compaction
@@ -720,17 +738,21 @@ hipError_t launch_decimate(const float *u, int64_t u_lo, int64_t u_len, float *d
   return hipGetLastError();
 }
 
-template <typename T, int MT, int NT, int NW>
+template <typename T, int MT, int NT, int NW, int BK>
 static hipError_t fir_v(const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s) {
-  k_fir<T, MT, NT, NW><<<(unsigned)n_items, 64 * NW, 0, s>>>(jobs, n_jobs);
+  k_fir<T, MT, NT, NW, BK><<<(unsigned)n_items, 64 * NW, 0, s>>>(jobs, n_jobs);
   return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t fir_t(const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s) {
   switch (kernel_variant("LLOID_FIR_VARIANT")) {
-    case 1: return fir_v<T, 4, 4, 4>(jobs, n_jobs, n_items, s);
-    default: return fir_v<T, kFirMT, kFirNT, kFirWaves>(jobs, n_jobs, n_items, s);
+    case 1: return fir_v<T, 4, 4, 4, kBK>(jobs, n_jobs, n_items, s);
+    case 2: return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
+    default:
+      // 16-bit operands: K chunks of 64 (twice the MFMAs per barrier)
+      if constexpr (sizeof(T) == 2) return fir_v<T, kFirMT, kFirNT, kFirWaves, 2 * kBK>(jobs, n_jobs, n_items, s);
+      else return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
   }
 }
 
@@ -743,6 +765,7 @@ void mix_tile_shape(lloid_dtype, int *bm, int *bn) {
   switch (kernel_variant("LLOID_MIX_VARIANT")) {
     case 1: *bm = 32 * 4 * 2, *bn = 32 * 2 * 2; break;
     case 2: *bm = 32 * 2 * 4, *bn = 32 * 2 * 2; break;
+    case 3: *bm = 32 * kMixMT * kMixWM, *bn = 32 * kMixNT * kMixWN; break;
     default: *bm = 32 * kMixMT * kMixWM, *bn = 32 * kMixNT * kMixWN; break;
   }
 }
@@ -782,7 +805,11 @@ static hipError_t mix_t(const MixJob *jobs, int n_jobs, int64_t n_items, bool wi
   switch (kernel_variant("LLOID_MIX_VARIANT")) {
     case 1: return mix_v<T, 4, 2, 2, 2, 32>(jobs, n_jobs, n_items, with_snr, s);
     case 2: return mix_v<T, 2, 2, 4, 2, 32>(jobs, n_jobs, n_items, with_snr, s);
-    default: return mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 32>(jobs, n_jobs, n_items, with_snr, s);
+    case 3: return mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 32>(jobs, n_jobs, n_items, with_snr, s);
+    default:
+      // 16-bit operands: K chunks of 64 (149.5 KB of LDS, one workgroup per CU)
+      if constexpr (sizeof(T) == 2) return mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 64>(jobs, n_jobs, n_items, with_snr, s);
+      else return mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 32>(jobs, n_jobs, n_items, with_snr, s);
   }
 }
 
@@ -800,7 +827,7 @@ hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_
 hipError_t launch_peak_phase(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float phase_thr,
                              hipStream_t s) {
   if (n_entries <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((n_entries + 3) / 4);
+  const unsigned blocks = (unsigned)((n_entries + 255) / 256);
   switch (t) {
     case LLOID_F16: k_peak_phase<_Float16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, phase_thr); break;
     case LLOID_BF16: k_peak_phase<__bf16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, phase_thr); break;
