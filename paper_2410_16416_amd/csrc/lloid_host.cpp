@@ -170,6 +170,7 @@ extern "C" lloid_status lloid_ctx_destroy(lloid_ctx *ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto &e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto &e : ctx->cev) (void)hipEventDestroy(e);
   if (ctx->ws.base) (void)hipFree(ctx->ws.base);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->d_halfband) (void)hipFree(ctx->d_halfband);
@@ -577,10 +578,10 @@ void lloid::number_jobs(std::vector<FirJob> &fj, std::vector<UpJob> *uj, std::ve
 }
 
 lloid_status lloid::launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dtab, const TabOffsets &to,
-                                  const StageItems &n, bool with_snr, float phase_thr, bool mark_stages) {
+                                  const StageItems &n, bool with_snr, float phase_thr, hipEvent_t *ev) {
   hipStream_t st = ctx->stream;
   auto mark = [&](int stage, int end) -> hipError_t {
-    return (ctx->profile && mark_stages) ? hipEventRecord(ctx->ev[2 * stage + end], st) : hipSuccess;
+    return ev ? hipEventRecord(ev[2 * (stage - LLOID_STAGE_FIR) + end], st) : hipSuccess;
   };
   HIP_TRY(mark(LLOID_STAGE_FIR, 0));
   HIP_TRY(launch_fir_jobs(ct, (const FirJob *)(dtab + to.fir), to.n_fir, n.fir, st));
@@ -812,10 +813,17 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
                             ctx->d_halfband, st));
   HIP_TRY(mark(LLOID_STAGE_DECIMATE, 1));
   const float phase_thr = (peaks && peaks[0].phase) ? -1.f : thr;
-  // with several chunks the per-stage events bracket the last chunk only
+  // every chunk's FIR, interpolation, mixing and phase stages get events of their own
+  const size_t nev = (size_t)2 * kChunkStages * n_chunks;
+  if (ctx->profile)
+    while (ctx->cev.size() < nev) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      ctx->cev.push_back(e);
+    }
   for (int64_t c = 0; c < n_chunks; ++c) {
     const lloid_status r2 = launch_stages(ctx, ct, dtab, chunks[c].to, chunks[c].items, snr != nullptr, phase_thr,
-                                          c + 1 == n_chunks);
+                                          ctx->profile ? &ctx->cev[(size_t)2 * kChunkStages * c] : nullptr);
     if (r2 != LLOID_OK) return r2;
   }
   HIP_TRY(mark(LLOID_STAGE_TRIGGER, 0));
@@ -846,7 +854,16 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   if (ctx->profile) {
     for (int i = 0; i < LLOID_N_STAGES; ++i) {
       float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[2 * i], ctx->ev[2 * i + 1]));
+      if (i >= LLOID_STAGE_FIR && i < LLOID_STAGE_FIR + kChunkStages) {
+        for (int64_t c = 0; c < n_chunks; ++c) {
+          float m = 0.f;
+          const size_t k = (size_t)2 * (kChunkStages * c + i - LLOID_STAGE_FIR);
+          HIP_TRY(hipEventElapsedTime(&m, ctx->cev[k], ctx->cev[k + 1]));
+          ms += m;
+        }
+      } else {
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[2 * i], ctx->ev[2 * i + 1]));
+      }
       ctx->stage_ms[i] += ms;
       ctx->stage_calls[i] += 1;
     }

@@ -123,6 +123,7 @@ struct lloid_ctx {
   int64_t chunk_budget = int64_t(6) << 30;  // device bytes of per-chunk operands
   bool profile = false;
   hipEvent_t ev[2 * LLOID_N_STAGES] = {};
+  std::vector<hipEvent_t> cev;  // per chunk: start/end of the FIR, interpolation, mixing and phase stages
   double stage_ms[LLOID_N_STAGES] = {};
   int64_t stage_calls[LLOID_N_STAGES] = {};
 };
@@ -294,9 +295,11 @@ void add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, int64_t
                    std::vector<MixJob> &mj);
 // Sort longest-first and number the work items.
 void number_jobs(std::vector<FirJob> &fj, std::vector<UpJob> *uj, std::vector<MixJob> &mj, StageItems &n);
-// FIR, interpolation and mixing launches over uploaded tables.
+// FIR, interpolation, mixing and phase launches over uploaded tables; ev:
+// NULL, or 8 events bracketing those four stages.
+constexpr int kChunkStages = 4;    // LLOID_STAGE_FIR .. LLOID_STAGE_PHASE
 lloid_status launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dtab, const TabOffsets &to,
-                           const StageItems &n, bool with_snr, float phase_thr, bool mark_stages);
+                           const StageItems &n, bool with_snr, float phase_thr, hipEvent_t *ev);
 
 }  // namespace lloid
 

@@ -271,7 +271,7 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
   to.n_mix = (int)mj.size();
   const size_t trig_off = put(tj.data(), tj.size() * sizeof(TrigJob));
   HIP_TRY(hipMemcpyAsync(dtab, htab, off, hipMemcpyHostToDevice, st));
-  rs = launch_stages(ctx, s->ct, dtab, to, items, false, s->thr, false);
+  rs = launch_stages(ctx, s->ct, dtab, to, items, false, s->thr, nullptr);
   if (rs != LLOID_OK) return rs;
   HIP_TRY(launch_trigger_jobs((const TrigJob *)(dtab + trig_off), (int)tj.size(), rows, s->thr, counts, total, cap,
                               dtrig, st));
