@@ -85,6 +85,19 @@ def load_traffic(stage: str, compute: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def cpu_baseline_1thread(wl, sample_s: float):
+    """The same oracle sample restricted to one BLAS thread (the paper's
+    single-CPU-core framing)."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:
+        return None
+    with threadpool_limits(limits=1):
+        r = cpu_baseline(wl, sample_s)
+    r["cores"] = 1
+    return r
+
+
 def cpu_baseline(wl, sample_s: float):
     """The FP64 oracle on a bounded sample: detector 0, outputs on
     [32 s, 32 s + sample_s) with the 32 s of history the longest slice needs."""
@@ -233,8 +246,8 @@ def bench_serving(args):
     torch.cuda.init()
     ctx = lloid.lloid_ctx_create(0)
     out = {}
-    for compute in [args.compute] + (["f32"] if args.f32_steps and args.compute != "f32" else []):
-        hs = [lloid.bank_from_svd(ctx, b, compute) for b in banks]
+    def serve(hs, compute, rate, n_str):
+        """Push n_str strides (after `warm` untimed ones) at `rate` x real time."""
         s = lloid.lloid_stream_create(ctx, f0, compute, n_detectors=2, min_rate_hz=128, window=(1, 1),
                                       max_filter_s=66.0, max_windows_per_tick=2)
         for h in hs:
@@ -242,32 +255,42 @@ def bench_serving(args):
         n_trig = 0
         lat = []
         t_start = None
-        for i in range(n_strides + warm):
+        for i in range(n_str + warm):
             if i == warm:
                 t_start = time.perf_counter()
             if t_start is not None:
-                due = t_start + (i - warm) / args.rate
+                due = t_start + (i - warm) / rate
                 while time.perf_counter() < due:
                     pass
-            arrive = time.perf_counter()
+            j = i % (total // f0)   # strain cycles through the generated seconds
             for d in range(2):
-                lloid.lloid_stream_push(s, d, i * f0, xs[d][i * f0:(i + 1) * f0])
+                lloid.lloid_stream_push(s, d, i * f0, xs[d][j * f0:(j + 1) * f0])
             n_trig += lloid.lloid_stream_poll(s).shape[0]
             if i >= warm:
-                lat.append((time.perf_counter() - (t_start + (i - warm) / args.rate)) * 1e3)
+                lat.append((time.perf_counter() - (t_start + (i - warm) / rate)) * 1e3)
         wall = time.perf_counter() - t_start
         st = lloid.lloid_stream_stats_get(s)
         lloid.lloid_stream_destroy(s)
+        samples = sum(b.n_templates for b in banks) * n_str * f0 * 2
+        lat = np.array(lat)
+        return {"value": round(samples / wall, 1), "wall_s": round(wall, 3), "strides": n_str,
+                "rate_x_real_time": rate,
+                "p50_stride_latency_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_stride_latency_ms": round(float(np.percentile(lat, 99)), 3),
+                "library_p50_ms": round(st.latency_p50_ms, 3), "library_p99_ms": round(st.latency_p99_ms, 3),
+                "kept_up": bool(wall <= n_str / rate * 1.05), "triggers": int(n_trig)}
+
+    sweep = []
+    for compute in [args.compute] + (["f32"] if args.f32_steps and args.compute != "f32" else []):
+        hs = [lloid.bank_from_svd(ctx, b, compute) for b in banks]
+        out[compute] = serve(hs, compute, args.rate, n_strides)
+        log(f"[bench] serving {compute}: {out[compute]}")
+        if compute == args.compute and args.rates:
+            for r in [float(v) for v in args.rates.split(",") if v]:
+                sweep.append(serve(hs, compute, r, min(1000, int(60 * r))))
+                log(f"[bench] serving {compute} at {r:g}x: {sweep[-1]}")
         for h in hs:
             lloid.lloid_bank_destroy(h)
-        samples = sum(b.n_templates for b in banks) * n_strides * f0 * 2
-        lat = np.array(lat)
-        out[compute] = {"value": round(samples / wall, 1), "wall_s": round(wall, 3),
-                        "p50_stride_latency_ms": round(float(np.percentile(lat, 50)), 3),
-                        "p99_stride_latency_ms": round(float(np.percentile(lat, 99)), 3),
-                        "library_p50_ms": round(st.latency_p50_ms, 3), "library_p99_ms": round(st.latency_p99_ms, 3),
-                        "kept_up": bool(wall <= n_strides / args.rate * 1.05), "triggers": int(n_trig)}
-        log(f"[bench] serving {compute}: {out[compute]}")
     lloid.lloid_ctx_destroy(ctx)
     m = out[args.compute]
     return {"metric": METRIC, "value": m["value"], "unit": "template-samples/s", "n_gpus": 1,
@@ -278,7 +301,7 @@ def bench_serving(args):
                        "banks": nb, "templates": sum(b.n_templates for b in banks), "detectors": 2,
                        "strides": n_strides, "rate_x_real_time": args.rate, "f0": f0},
             "p50_stride_latency_ms": m["p50_stride_latency_ms"], "p99_stride_latency_ms": m["p99_stride_latency_ms"],
-            "paths": out}
+            "paths": out, "rate_sweep": sweep}
 
 
 def main():
@@ -295,6 +318,8 @@ def main():
                          "serving_c4 (128 banks streamed in 1 s strides)")
     ap.add_argument("--banks", type=int, default=0, help="banks for batched_c3 / serving_c4 (0: 64 / 128)")
     ap.add_argument("--rate", type=float, default=16.0, help="serving_c4: strides per second (x real time)")
+    ap.add_argument("--rates", default="", help="serving_c4: also sweep these rates (e.g. 1,4,16,64), "
+                                                "min(1000, 60 x rate) strides each, operand type only")
     ap.add_argument("--strides", type=int, default=120, help="serving_c4: timed 1 s strides")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC byte-counter calibration)")
@@ -388,6 +413,9 @@ def main():
     if args.cpu_sample_s > 0:
         log(f"[bench] cpu baseline: oracle on {args.cpu_sample_s:g} s")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_s)
+        one = cpu_baseline_1thread(wl, min(args.cpu_sample_s, 4.0))
+        if one:
+            out["cpu_baseline_1_thread"] = one
     lloid.lloid_ctx_destroy(ctx)
     print(json.dumps(out), flush=True)
 

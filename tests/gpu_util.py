@@ -87,6 +87,24 @@ def compare_series(z_gpu, z_oracle, compute, label=""):
     return {"max_abs": float(d.max()), "max_rel_at6": rel}
 
 
+def record_precision(case: str, compute: str, **stats):
+    """Merge measured errors into the JSON file named by LLOID_PRECISION_OUT
+    (if set): {compute: {case: stats}}.  The benchmark prints these next to
+    its throughput as the stated SNR error of each precision."""
+    import json
+    import os
+    path = os.environ.get("LLOID_PRECISION_OUT")
+    if not path:
+        return
+    data = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            data = json.load(f)
+    data.setdefault(compute, {})[case] = stats
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+
+
 def gpu_complex(res):
     s = res.snr
     return s[..., 0].astype(np.float64) + 1j * s[..., 1].astype(np.float64)

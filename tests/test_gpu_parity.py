@@ -16,7 +16,7 @@ import oracle
 from workloads import configs
 from workloads.strain import Injection, inject
 
-from gpu_util import EPS_ABS, compare_peaks, compare_series, gpu_complex, log, run_filter, ctx
+from gpu_util import EPS_ABS, compare_peaks, compare_series, ctx, gpu_complex, log, record_precision, run_filter
 
 pytestmark = pytest.mark.gpu
 PRECISIONS = ["f32", "f16", "bf16"]
@@ -199,6 +199,7 @@ def test_c1_bank_short_block(compute):
     res.peak_snr, res.peak_sample = res.peak_snr[tsel], res.peak_sample[tsel]
     p = compare_peaks(res, np.abs(z), pa, ps, compute, label=f"c1short/{compute}")
     log(f"  series {s} peaks {p}")
+    record_precision(f"multirate_c1 bank, 36 s block, {len(tsel)} templates, every sample", compute, **s, **p)
     for inj in injs:
         r = int(np.nonzero(tsel == inj.template)[0][0])
         w = inj.t0 // 2048
