@@ -246,10 +246,10 @@ def bench_serving(args):
     torch.cuda.init()
     ctx = lloid.lloid_ctx_create(0)
     out = {}
-    def serve(hs, compute, rate, n_str):
+    def serve(hs, compute, rate, n_str, use_graph=False):
         """Push n_str strides (after `warm` untimed ones) at `rate` x real time."""
         s = lloid.lloid_stream_create(ctx, f0, compute, n_detectors=2, min_rate_hz=128, window=(1, 1),
-                                      max_filter_s=66.0, max_windows_per_tick=2)
+                                      max_filter_s=66.0, max_windows_per_tick=2, use_graph=use_graph)
         for h in hs:
             lloid.lloid_stream_admit(s, h)
         n_trig = 0
@@ -278,13 +278,18 @@ def bench_serving(args):
                 "p50_stride_latency_ms": round(float(np.percentile(lat, 50)), 3),
                 "p99_stride_latency_ms": round(float(np.percentile(lat, 99)), 3),
                 "library_p50_ms": round(st.latency_p50_ms, 3), "library_p99_ms": round(st.latency_p99_ms, 3),
-                "kept_up": bool(wall <= n_str / rate * 1.05), "triggers": int(n_trig)}
+                "kept_up": bool(wall <= n_str / rate * 1.05), "triggers": int(n_trig),
+                "hip_graph": bool(use_graph), "graph_captures": int(st.graph_captures),
+                "graph_replays": int(st.graph_replays)}
 
     sweep = []
     for compute in [args.compute] + (["f32"] if args.f32_steps and args.compute != "f32" else []):
         hs = [lloid.bank_from_svd(ctx, b, compute) for b in banks]
         out[compute] = serve(hs, compute, args.rate, n_strides)
         log(f"[bench] serving {compute}: {out[compute]}")
+        if compute == args.compute:
+            out[compute + "_hip_graph"] = serve(hs, compute, args.rate, n_strides, use_graph=True)
+            log(f"[bench] serving {compute} (HIP graph ticks): {out[compute + '_hip_graph']}")
         if compute == args.compute and args.rates:
             for r in [float(v) for v in args.rates.split(",") if v]:
                 sweep.append(serve(hs, compute, r, min(1000, int(60 * r))))

@@ -239,7 +239,10 @@ typedef struct {
   int32_t n_detectors;          /* 1..16 */
   int32_t min_rate_hz;          /* lowest slice rate an admitted bank may use */
   int32_t max_windows_per_tick; /* windows filtered by one tick at most; 0 means 8 */
-  int32_t reserved;
+  int32_t use_graph;            /* nonzero: each tick's device work (table upload, every stage,
+                                   trigger count) runs as a captured HIP graph, replayed while the
+                                   tick's shape (slots, windows, buffers) is unchanged and captured
+                                   again when it changes; results are those of the direct launches */
   double max_filter_s;          /* longest slice span (J_s / f0 + N_s / r_s) an admitted bank may
                                    have, in seconds; sets the history kept; 0 means 66 */
   int64_t hbm_budget;           /* device bytes for admitted banks (arrays + per-tick scratch);
@@ -258,6 +261,8 @@ typedef struct {
   int32_t active_slots;
   int32_t queued_banks;
   int64_t bytes_in_use;         /* budget taken by active slots */
+  int64_t graph_captures;       /* with use_graph: ticks that captured a new graph */
+  int64_t graph_replays;        /* with use_graph: ticks that replayed the previous one */
 } lloid_stream_stats;
 
 lloid_status lloid_stream_create(lloid_ctx *ctx, int32_t full_rate_hz, lloid_dtype compute,

@@ -60,6 +60,14 @@ struct lloid_stream {
   float *level_mem = nullptr;
   void *staging = nullptr;
   int *bad = nullptr;
+  // captured tick (use_graph): replayed while the key (everything the
+  // launches take as arguments or sizes) is unchanged
+  bool use_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int64_t> graph_key;
+  int64_t *hsmall = nullptr;       // pinned: [0] trigger count, [1] low 4 bytes: non-finite flag
+  int64_t graph_captures = 0, graph_replays = 0;
   // results and statistics
   std::deque<lloid_trigger> out;
   std::vector<double> lat_ms;
@@ -270,16 +278,55 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
   to.n_fir = (int)fj.size();
   to.n_mix = (int)mj.size();
   const size_t trig_off = put(tj.data(), tj.size() * sizeof(TrigJob));
-  HIP_TRY(hipMemcpyAsync(dtab, htab, off, hipMemcpyHostToDevice, st));
-  rs = launch_stages(ctx, s->ct, dtab, to, items, false, s->thr, nullptr);
-  if (rs != LLOID_OK) return rs;
-  HIP_TRY(launch_trigger_jobs((const TrigJob *)(dtab + trig_off), (int)tj.size(), rows, s->thr, counts, total, cap,
-                              dtrig, st));
-  int64_t h_total = 0;
-  int h_bad = 0;
-  HIP_TRY(hipMemcpyAsync(&h_total, total, sizeof h_total, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(&h_bad, s->bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
+  // the tick's device work: table upload, every stage, trigger count and the
+  // two small results into pinned host memory
+  auto enqueue = [&]() -> lloid_status {
+    HIP_TRY(hipMemcpyAsync(dtab, htab, off, hipMemcpyHostToDevice, st));
+    const lloid_status r = launch_stages(ctx, s->ct, dtab, to, items, false, s->thr, nullptr);
+    if (r != LLOID_OK) return r;
+    HIP_TRY(launch_trigger_jobs((const TrigJob *)(dtab + trig_off), (int)tj.size(), rows, s->thr, counts, total, cap,
+                                dtrig, st));
+    HIP_TRY(hipMemcpyAsync(s->hsmall, total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(s->hsmall + 1, s->bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    return LLOID_OK;
+  };
+  if (s->use_graph) {
+    std::vector<int64_t> key = {(int64_t)(uintptr_t)dtab, (int64_t)(uintptr_t)htab, (int64_t)off, (int64_t)trig_off,
+                                (int64_t)tj.size(), rows, cap, (int64_t)(uintptr_t)counts, (int64_t)(uintptr_t)dtrig,
+                                items.fir, items.mix, items.entries, (int64_t)to.fir, (int64_t)to.mix, to.n_fir,
+                                to.n_mix};
+    for (int h = 0; h < kMaxHops; ++h) {
+      key.push_back(items.up[h]);
+      key.push_back((int64_t)to.up[h]);
+      key.push_back(to.n_up[h]);
+    }
+    if (!s->exec || key != s->graph_key) {
+      if (s->exec) (void)hipGraphExecDestroy(s->exec), s->exec = nullptr;
+      if (s->graph) (void)hipGraphDestroy(s->graph), s->graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      const lloid_status r = enqueue();
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(st, &g);
+      if (r != LLOID_OK) {
+        if (ec == hipSuccess && g) (void)hipGraphDestroy(g);
+        return r;
+      }
+      HIP_TRY(ec);
+      s->graph = g;
+      HIP_TRY(hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0));
+      s->graph_key = key;
+      ++s->graph_captures;
+    } else {
+      ++s->graph_replays;
+    }
+    HIP_TRY(hipGraphLaunch(s->exec, st));
+  } else {
+    rs = enqueue();
+    if (rs != LLOID_OK) return rs;
+  }
   HIP_TRY(hipStreamSynchronize(st));
+  const int64_t h_total = s->hsmall[0];
+  const int h_bad = *(const int *)(s->hsmall + 1);
   if (h_total > 0) {
     const size_t at = s->out.size();
     s->out.resize(at + (size_t)h_total);
@@ -371,6 +418,7 @@ extern "C" lloid_status lloid_stream_create(lloid_ctx *ctx, int32_t full_rate_hz
   s->sscale = sscale;
   s->budget = opts->hbm_budget;
   s->max_w = opts->max_windows_per_tick > 0 ? opts->max_windows_per_tick : 8;
+  s->use_graph = opts->use_graph != 0;
   int L = 1;
   while ((full_rate_hz >> (L - 1)) > opts->min_rate_hz) ++L;
   s->n_levels = L;
@@ -389,7 +437,8 @@ extern "C" lloid_status lloid_stream_create(lloid_ctx *ctx, int32_t full_rate_hz
   }
   const size_t lbytes = total * 4 * s->n_det;
   if (hipMalloc((void **)&s->level_mem, lbytes) != hipSuccess ||
-      hipMalloc(&s->staging, (size_t)s->push_max * 8) != hipSuccess || hipMalloc((void **)&s->bad, 256) != hipSuccess) {
+      hipMalloc(&s->staging, (size_t)s->push_max * 8) != hipSuccess || hipMalloc((void **)&s->bad, 256) != hipSuccess ||
+      hipHostMalloc((void **)&s->hsmall, 2 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     lloid_stream_destroy(s);
     return fail(LLOID_ENOMEM, "stream buffers do not fit on the device");
@@ -517,6 +566,8 @@ extern "C" lloid_status lloid_stream_stats_get(const lloid_stream *s, lloid_stre
   for (const auto &sl : s->slots)
     if (sl.bank) (sl.active ? out->active_slots : out->queued_banks) += 1;
   out->bytes_in_use = s->used;
+  out->graph_captures = s->graph_captures;
+  out->graph_replays = s->graph_replays;
   return LLOID_OK;
 }
 
@@ -527,6 +578,9 @@ extern "C" lloid_status lloid_stream_destroy(lloid_stream *s) {
   if (s->level_mem) (void)hipFree(s->level_mem);
   if (s->staging) (void)hipFree(s->staging);
   if (s->bad) (void)hipFree(s->bad);
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->hsmall) (void)hipHostFree(s->hsmall);
   if (s->ws.base) (void)hipFree(s->ws.base);
   if (s->pinned) (void)hipHostFree(s->pinned);
   delete s;

@@ -65,7 +65,7 @@ class lloid_peaks(ctypes.Structure):
 
 class lloid_stream_opts(ctypes.Structure):
     _fields_ = [("n_detectors", ctypes.c_int32), ("min_rate_hz", ctypes.c_int32),
-                ("max_windows_per_tick", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_windows_per_tick", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("max_filter_s", ctypes.c_double), ("hbm_budget", ctypes.c_int64),
                 ("trig", lloid_trigger_opts)]
 
@@ -75,7 +75,8 @@ class lloid_stream_stats(ctypes.Structure):
                 ("next_window", ctypes.c_int64), ("latency_p50_ms", ctypes.c_double),
                 ("latency_p99_ms", ctypes.c_double), ("latency_max_ms", ctypes.c_double),
                 ("active_slots", ctypes.c_int32), ("queued_banks", ctypes.c_int32),
-                ("bytes_in_use", ctypes.c_int64)]
+                ("bytes_in_use", ctypes.c_int64), ("graph_captures", ctypes.c_int64),
+                ("graph_replays", ctypes.c_int64)]
 
 
 TRIGGER_DTYPE = np.dtype([("bank", np.int32), ("detector", np.int32), ("template_id", np.int32),
@@ -356,9 +357,10 @@ def bank_from_svd(ctx, svd_bank, compute: str = "f16"):
 def lloid_stream_create(ctx, full_rate_hz: int, compute: str = "f16", n_detectors: int = 1,
                         min_rate_hz: int | None = None, window=(1, 1), threshold: float = 4.0,
                         strain_scale: float = 0.0, hbm_budget: int = 0, max_filter_s: float = 0.0,
-                        max_windows_per_tick: int = 0):
+                        max_windows_per_tick: int = 0, use_graph: bool = False):
     opts = lloid_stream_opts(int(n_detectors), int(min_rate_hz or max(1, full_rate_hz // 16)),
-                             int(max_windows_per_tick), 0, float(max_filter_s), int(hbm_budget),
+                             int(max_windows_per_tick), 1 if use_graph else 0, float(max_filter_s),
+                             int(hbm_budget),
                              lloid_trigger_opts(int(window[0]), int(window[1]), float(threshold),
                                                 float(strain_scale)))
     out = ctypes.c_void_p()

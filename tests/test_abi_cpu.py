@@ -54,6 +54,10 @@ int main(void) {
   printf("lloid_trigger %zu\\n", sizeof(lloid_trigger));
   printf("lloid_trigger_opts %zu\\n", sizeof(lloid_trigger_opts));
   printf("lloid_peaks %zu\\n", sizeof(lloid_peaks));
+  printf("lloid_stream_opts %zu\\n", sizeof(lloid_stream_opts));
+  printf("lloid_stream_stats %zu\\n", sizeof(lloid_stream_stats));
+  P(lloid_stream_opts, use_graph) P(lloid_stream_opts, hbm_budget) P(lloid_stream_opts, trig)
+  P(lloid_stream_stats, bytes_in_use) P(lloid_stream_stats, graph_replays)
   P(lloid_slice, start_tap) P(lloid_slice, basis) P(lloid_slice, mixing)
   P(lloid_trigger, window) P(lloid_trigger, sample) P(lloid_trigger, snr) P(lloid_trigger, phase)
   P(lloid_bank_desc, slices) P(lloid_bank_info, device_bytes)
@@ -66,7 +70,8 @@ int main(void) {
                                                         check=True).stdout.splitlines())
     mirror = {"lloid_slice": lloid.lloid_slice, "lloid_bank_desc": lloid.lloid_bank_desc,
               "lloid_bank_info": lloid.lloid_bank_info, "lloid_trigger_opts": lloid.lloid_trigger_opts,
-              "lloid_peaks": lloid.lloid_peaks}
+              "lloid_peaks": lloid.lloid_peaks, "lloid_stream_opts": lloid.lloid_stream_opts,
+              "lloid_stream_stats": lloid.lloid_stream_stats}
     for name, cls in mirror.items():
         assert int(got[name]) == ctypes.sizeof(cls), name
     assert int(got["lloid_trigger"]) == lloid.TRIGGER_DTYPE.itemsize
@@ -76,6 +81,10 @@ int main(void) {
         assert int(got[f"lloid_slice.{f}"]) == getattr(lloid.lloid_slice, f).offset
     assert int(got["lloid_bank_desc.slices"]) == lloid.lloid_bank_desc.slices.offset
     assert int(got["lloid_bank_info.device_bytes"]) == lloid.lloid_bank_info.device_bytes.offset
+    for f in ("use_graph", "hbm_budget", "trig"):
+        assert int(got[f"lloid_stream_opts.{f}"]) == getattr(lloid.lloid_stream_opts, f).offset, f
+    for f in ("bytes_in_use", "graph_replays"):
+        assert int(got[f"lloid_stream_stats.{f}"]) == getattr(lloid.lloid_stream_stats, f).offset, f
 
 
 def test_missing_device_is_an_error_code():

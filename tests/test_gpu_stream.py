@@ -47,30 +47,42 @@ def run_stream(lloid, s, strains, sizes):
     return np.concatenate(got)
 
 
-@pytest.mark.parametrize("sizes", [[1024], [700, 1500, 333]])
-def test_stream_equals_offline(sizes):
+@pytest.mark.parametrize("sizes,use_graph", [([1024], False), ([700, 1500, 333], False),
+                                             ([1024], True), ([700, 1500, 333], True)])
+def test_stream_equals_offline(sizes, use_graph):
+    """With use_graph the ticks replay a captured HIP graph (captured again when
+    a tick's shape changes); every replay must give the offline result."""
     from paper_2410_16416_amd import lloid
     wl = configs.mini_multirate(seconds=12, detectors=2, n_injections=2)
     h = lloid.bank_from_svd(ctx(), wl.bank, "f16")
     s = lloid.lloid_stream_create(ctx(), 1024, "f16", n_detectors=2, min_rate_hz=64, window=(1, 4),
-                                  max_filter_s=8.0)
+                                  max_filter_s=8.0, use_graph=use_graph)
     try:
         slot, active = lloid.lloid_stream_admit(s, h)
         assert active
         got = canon(run_stream(lloid, s, wl.strains, sizes))
         want = offline(lloid, h, wl.strains, (1, 4), slot)
         st = lloid.lloid_stream_stats_get(s)
-        log(f"[stream {sizes}] {len(got)} triggers, ticks {st.ticks}, p50 {st.latency_p50_ms:.2f} ms, "
-            f"p99 {st.latency_p99_ms:.2f} ms")
+        log(f"[stream {sizes} graph={use_graph}] {len(got)} triggers, ticks {st.ticks}, p50 {st.latency_p50_ms:.2f} ms, "
+            f"p99 {st.latency_p99_ms:.2f} ms, graph captures {st.graph_captures} replays {st.graph_replays}")
         assert len(got) == len(want) > 0
         assert np.array_equal(got, want)
         assert st.next_window == 48 and st.triggers == len(got)
+        if use_graph:
+            # regular strides repeat one tick shape (replays); irregular ones may
+            # change it every tick (a capture each time)
+            assert st.graph_captures >= 1 and st.graph_captures + st.graph_replays == st.ticks
+            if len(sizes) == 1:
+                assert st.graph_replays >= 1
+        else:
+            assert st.graph_captures == 0 and st.graph_replays == 0
     finally:
         lloid.lloid_stream_destroy(s)
         lloid.lloid_bank_destroy(h)
 
 
-def test_continuous_batching_admission_and_removal():
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_continuous_batching_admission_and_removal(use_graph):
     """Banks join while others run, one waits for budget and enters when a
     slot is removed; each bank's triggers equal its offline triggers over the
     windows it was active for.  Threshold 3 gives every bank triggers in the
@@ -95,7 +107,7 @@ def test_continuous_batching_admission_and_removal():
     # a + b fit, b + c fit, a + b + c do not
     budget = sizes[1] + max(sizes[0], sizes[2])
     s = lloid.lloid_stream_create(ctx(), f0, "f16", n_detectors=2, min_rate_hz=64, window=(1, 2),
-                                  threshold=3.0, max_filter_s=4.0, hbm_budget=budget)
+                                  threshold=3.0, max_filter_s=4.0, hbm_budget=budget, use_graph=use_graph)
     try:
         a, act_a = lloid.lloid_stream_admit(s, hs[0])
         assert act_a
