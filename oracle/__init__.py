@@ -14,11 +14,11 @@ slicing (not described in the paper) is parity unpinned.
 
 from .lloid import (
     Seq, halfband_taps, decimate2, interpolate2, fir, lloid_snr, direct_snr,
-    window_index, window_starts, peak_table, triggers, sigma2, level_ranges,
+    window_index, window_starts, peak_table, triggers, sigma2, level_ranges, subsample_peak,
 )
 
 __all__ = [
     "Seq", "halfband_taps", "decimate2", "interpolate2", "fir", "lloid_snr",
     "direct_snr", "window_index", "window_starts", "peak_table", "triggers",
-    "sigma2", "level_ranges",
+    "sigma2", "level_ranges", "subsample_peak",
 ]

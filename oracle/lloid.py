@@ -250,6 +250,26 @@ def triggers(z: np.ndarray, n_lo: int, f0: int, num: int, den: int, threshold: f
     return out
 
 
+def subsample_peak(a_prev, a_peak, a_next):
+    """Sub-sample refinement of a sampled maximum (Sec. III.B names sub-sample
+    interpolation at the SNR peak as the feature behind the port's slightly
+    lower network SNRs).  The parabola through (-1, a_prev), (0, a_peak),
+    (+1, a_next) has its vertex at
+
+        dt = (a_prev - a_next) / (2 (a_prev - 2 a_peak + a_next)),
+
+    with value a_peak - (a_prev - a_next) dt / 4.  dt is clipped to
+    [-1/2, 1/2]; a flat or convex triple (curvature >= 0) keeps dt = 0 and
+    the sampled value.  Applied to |z|.  Arrays broadcast; returns (dt, value)."""
+    a_prev, a_peak, a_next = (np.asarray(v, dtype=np.float64) for v in (a_prev, a_peak, a_next))
+    curv = a_prev - 2.0 * a_peak + a_next
+    ok = curv < 0.0
+    dt = np.where(ok, (a_prev - a_next) / np.where(ok, 2.0 * curv, 1.0), 0.0)
+    dt = np.clip(dt, -0.5, 0.5)
+    value = np.where(ok, a_peak - 0.25 * (a_prev - a_next) * dt, a_peak)
+    return dt, value
+
+
 def sigma2(bank) -> np.ndarray:
     """Squared full-rate norm of each reconstructed template (cos + sin).
 

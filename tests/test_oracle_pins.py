@@ -397,3 +397,53 @@ def test_c0_injection_recovered_in_window_40():
         assert ps[inj.template, 40] == 4146
         assert 8.0 < pa[inj.template, 40] < 12.0
     assert abs(np.abs(zs[inj.template, 4146]) - np.abs(zd[inj.template, 4146])) < 0.2
+
+
+def test_subsample_peak_recovers_a_sampled_parabola():
+    """Closed form: three samples of c - k (t - t0)^2 give back t0 and c."""
+    rng = np.random.default_rng(4)
+    t0 = rng.uniform(-0.49, 0.49, 200)
+    c = rng.uniform(4.0, 30.0, 200)
+    k = rng.uniform(0.01, 3.0, 200)
+
+    def a(t):
+        return c - k * (t - t0) ** 2
+
+    dt, v = oracle.subsample_peak(a(-1.0), a(0.0), a(1.0))
+    assert np.allclose(dt, t0, rtol=0, atol=1e-12)
+    assert np.allclose(v, c, rtol=0, atol=1e-12)
+
+
+def test_subsample_peak_degenerate_and_clipped_cases():
+    # flat and convex triples keep the sampled value
+    assert oracle.subsample_peak(5.0, 5.0, 5.0) == (0.0, 5.0)
+    assert oracle.subsample_peak(6.0, 5.0, 6.0) == (0.0, 5.0)
+    # a vertex beyond the bracket is clipped to half a sample
+    dt, v = oracle.subsample_peak(1.0, 5.0, 6.0)
+    assert dt == 0.5 and v == pytest.approx(5.0 + 0.25 * 5.0 * 0.5, abs=1e-15)
+    # symmetric neighbours: the sample is the peak
+    dt, v = oracle.subsample_peak(3.0, 7.0, 3.0)
+    assert dt == 0.0 and v == 7.0
+
+
+def test_subsample_peak_recovers_a_fractional_arrival():
+    """A noise-free chirp arriving between samples (band-limited fractional
+    delay by an FFT phase ramp): the exact matched filter's sampled peak is
+    low by the sampling loss; the parabola brings back the arrival time and
+    most of the lost SNR."""
+    from workloads.chirp import mass_chirps
+    f0, n, t_c, amp = 1024, 8192, 5000, 10.0
+    fam = mass_chirps(1, f0, 1.0, 20.0, 1.2, 1.2, np.random.default_rng(0))
+    h = fam.full_rate_filters()                        # [2, 1024] cos, sin; unit norm
+    x = np.zeros(n)
+    j = np.arange(h.shape[1])
+    x[t_c - j] = amp * h[0]                            # the cos filter, coalescing at t_c
+    f = np.fft.rfftfreq(n)
+    for tau in (0.25, 0.5, -0.4):
+        xs = np.fft.irfft(np.fft.rfft(x) * np.exp(-2j * np.pi * f * tau), n)
+        a = np.abs(oracle.direct_snr(h, xs, 0, n)[0])
+        k = int(np.argmax(a))
+        dt, v = oracle.subsample_peak(a[k - 1], a[k], a[k + 1])
+        peak_true = np.abs(oracle.direct_snr(h, x, t_c, t_c + 1)[0, 0])   # the aligned peak
+        assert abs((k + dt) - (t_c + tau)) < 0.05, tau
+        assert abs(v - peak_true) < 0.35 * abs(a[k] - peak_true), tau
