@@ -94,7 +94,9 @@ typedef struct {
   const lloid_slice *slices;
 } lloid_bank_desc;
 
-/* A trigger: the SNR peak of one template in one window with |z| >= threshold. */
+/* A trigger: the SNR peak of one template in one window with |z| >= threshold,
+ * with its sub-sample refinement (Sec. III.B: the interpolation at the SNR
+ * peak that the paper's port leaves out). */
 typedef struct {
   int32_t bank;          /* bank index in a batched call / stream slot; 0 for lloid_filter */
   int32_t detector;      /* as passed by the caller */
@@ -104,6 +106,9 @@ typedef struct {
   int64_t sample;        /* peak sample n* */
   float snr;             /* |z_i[n*]| */
   float phase;           /* atan2(Im z_i[n*], Re z_i[n*]) in (-pi, pi] */
+  float snr_interp;      /* sub-sample peak: vertex of the parabola through |z_i| at n* - 1, n*, n* + 1 */
+  float dt;              /* its offset from n* in samples, in [-1/2, 1/2] (0 when the triple is not
+                            concave); the refined peak time is (sample + dt) / f0 */
 } lloid_trigger;
 
 typedef struct {

@@ -463,6 +463,9 @@ void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, 
                           int64_t wb, const Windows &win, const BankBufs &bb, float inv_scale, float *snr,
                           int64_t snr_ld, const TileShapes &ts, std::vector<FirJob> &fj, std::vector<UpJob> *uj,
                           std::vector<MixJob> &mj) {
+  // the operand holds one extra sample on each side, for the sub-sample
+  // refinement of peaks at the chunk's first and last samples
+  const int64_t e0 = t0 - 1, e1 = t1 + 1;
   const size_t lsz = low_esz(b->compute);
   const int ti = b->compute == LLOID_F16 ? 1 : 0;   // BF16 interpolates FP32 buffers
   for (size_t s = 0; s < b->slices.size(); ++s) {
@@ -478,16 +481,16 @@ void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, 
     j.n_rtiles = (int)ceil_div(sl.lrows, ts.fbm);
     j.col_limit = sl.lp;
     if (sl.level == 0) {
-      j.k_lo = t0;
-      j.k_hi = t1;
+      j.k_lo = e0;
+      j.k_hi = e1;
       j.out = bb.ocat;
-      j.out_lo = t0;
+      j.out_lo = e0;
       j.ldo = b->kcat;
       j.col0 = sl.koff;
     } else {
       // FIR at the slice rate into a channel-major buffer, then the hops up to f0
-      const UpPlan p = up_plan(t0, t1, sl.level);
-      const std::vector<int64_t> ld = low_ld(t1 - t0, sl.level);
+      const UpPlan p = up_plan(e0, e1, sl.level);
+      const std::vector<int64_t> ld = low_ld(e1 - e0, sl.level);
       const int H = (int)p.r.size();
       j.k_lo = p.in[0].lo;
       j.k_hi = p.in[0].hi;
@@ -512,7 +515,7 @@ void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, 
         q.n_rtiles = (int)ceil_div(sl.lp, 32);
         if (h + 1 == H) {
           q.dst = bb.ocat;
-          q.dst_abs0 = t0;
+          q.dst_abs0 = e0;
           q.ld_dst = b->kcat;
           q.col0 = sl.koff;
           q.dst_tm = 1;
@@ -534,8 +537,11 @@ void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, 
   m.peak_snr = bb.psnr;
   m.peak_n = bb.pn;
   m.peak_phase = bb.pphase;
+  m.peak_dt = bb.pdt;
+  m.peak_si = bb.psi;
   m.snr = snr;
-  m.ocat_abs0 = t0;
+  m.ocat_abs0 = e0;
+  m.snr_abs0 = t0;
   m.n_end = n_end;
   m.w0 = wa;
   m.nw = wb - wa;
@@ -668,9 +674,9 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   wpc = std::min(wpc, W);
   // every buffer a kernel addresses through a buffer resource stays under 2 GiB
   for (int i = 0; i < nb; ++i)
-    while (wpc > 1 && !operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1))) wpc = (wpc + 1) / 2;
+    while (wpc > 1 && !operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1) + 2)) wpc = (wpc + 1) / 2;
   for (int i = 0; i < nb; ++i)
-    if (!operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1)))
+    if (!operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1) + 2))
       return fail(LLOID_EINVAL, "one trigger window of bank %d needs buffers over 2 GiB", i);
   const int64_t n_chunks = ceil_div(W, wpc);
   const int64_t chunk_n = std::min<int64_t>(n, win.start(wpc) + 1);   // samples of the longest chunk
@@ -701,10 +707,12 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     add(tab, 4);
     add(tab, 8);
     add(tab, 4);
-    add((size_t)chunk_n * banks[i]->kcat, esz);
+    add(tab, 4);
+    add(tab, 4);
+    add((size_t)(chunk_n + 2) * banks[i]->kcat, esz);
     for (const auto &sl : banks[i]->slices)
       if (sl.level > 0)
-        for (int64_t ld : low_ld(chunk_n, sl.level)) add((size_t)sl.lp * ld, low_esz(ct));
+        for (int64_t ld : low_ld(chunk_n + 2, sl.level)) add((size_t)sl.lp * ld, low_esz(ct));
   }
   add((size_t)total_rows + 2, 8);
   add(1, 4);
@@ -731,14 +739,16 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     bw[i].psnr = cv.take<float>(tab);
     bw[i].pn = cv.take<int64_t>(tab);
     bw[i].pphase = cv.take<float>(tab);
+    bw[i].pdt = cv.take<float>(tab);
+    bw[i].psi = cv.take<float>(tab);
     bw[i].ld_peak = W;
     bw[i].w_base = 0;
-    bw[i].ocat = cv.take<char>((size_t)chunk_n * banks[i]->kcat * esz);
+    bw[i].ocat = cv.take<char>((size_t)(chunk_n + 2) * banks[i]->kcat * esz);
     bw[i].low.assign(banks[i]->slices.size(), {});
     for (size_t s = 0; s < banks[i]->slices.size(); ++s) {
       const auto &sl = banks[i]->slices[s];
       if (sl.level > 0)
-        for (int64_t ld : low_ld(chunk_n, sl.level))
+        for (int64_t ld : low_ld(chunk_n + 2, sl.level))
           bw[i].low[s].push_back(cv.take<char>((size_t)sl.lp * ld * low_esz(ct)));
     }
   }
@@ -788,7 +798,8 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   {
     int64_t row = 0;
     for (int i = 0; i < nb; ++i) {
-      tj[i] = TrigJob{bw[i].psnr, bw[i].pn, bw[i].pphase, W, 0, W, row, banks[i]->n_templates, i, detector, 0};
+      tj[i] = TrigJob{bw[i].psnr, bw[i].pn, bw[i].pphase, bw[i].pdt, bw[i].psi, W, 0, W, row, banks[i]->n_templates,
+                      i, detector, 0};
       row += banks[i]->n_templates;
     }
   }

@@ -91,8 +91,9 @@ struct MixJob {
   float *peak_snr;       // [F][ld_peak], column w - w_base
   int64_t *peak_n;
   float *peak_phase;
-  float *snr;            // optional [F][snr_ld][2], column n - ocat_abs0
-  int64_t ocat_abs0, n_end, w0, nw, win_p, win_q, ld_peak, w_base, snr_ld, item0, e0;
+  float *peak_dt, *peak_si;   // sub-sample peak offset and value (triggers only)
+  float *snr;            // optional [F][snr_ld][2], column n - snr_abs0
+  int64_t ocat_abs0, n_end, w0, nw, win_p, win_q, ld_peak, w_base, snr_ld, snr_abs0, item0, e0;
   float inv_scale;
   int rows, kcat, n_templates, n_rtiles, pad;
 };
@@ -101,7 +102,7 @@ struct MixJob {
 struct TrigJob {
   const float *snr;
   const int64_t *peak_n;
-  const float *phase;
+  const float *phase, *dt, *si;
   int64_t ld, w_base, nw, row0;   // row0: first (bank, template) row of this job
   int n_templates, bank_id, detector, pad;
 };
@@ -237,7 +238,7 @@ struct BankBufs {
   void *ocat = nullptr;            // [chunk samples][kcat]
   std::vector<std::vector<void *>> low;  // per slice at level > 0: FIR output, then each
                                          // interpolation hop's output except the last
-  float *psnr = nullptr, *pphase = nullptr;
+  float *psnr = nullptr, *pphase = nullptr, *pdt = nullptr, *psi = nullptr;
   int64_t *pn = nullptr;
   int64_t ld_peak = 0, w_base = 0; // peak tables [F][ld_peak], column w - w_base
 };

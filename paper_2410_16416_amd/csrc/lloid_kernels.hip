@@ -529,7 +529,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mix_peak(const MixJob *__restr
           if (SNR && ok) {
             const int64_t i = (r0 + wm * 32 * MT + mt * 32 + 8 * (p >> 1) + 4 * (lane >> 5) + 2 * (p & 1)) >> 1;
             if (i < n_templates)
-              *(float2 *)(jb.snr + (i * jb.snr_ld + (col - jb.ocat_abs0)) * 2) = make_float2(re * inv_scale, im * inv_scale);
+              *(float2 *)(jb.snr + (i * jb.snr_ld + (col - jb.snr_abs0)) * 2) = make_float2(re * inv_scale, im * inv_scale);
           }
         }
       }
@@ -565,11 +565,15 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mix_peak(const MixJob *__restr
   }
 }
 
-// Phase at each reported window peak: z_i[n*] recomputed as the dot products
-// of mixing rows 2i, 2i+1 with the operand row at n* (FP32 accumulation), one
-// thread per (template, window) entry reading 16-byte vectors.  Peaks below
-// `thr` get phase 0 (not reported), so only the entries that become triggers
-// do the work.
+// Phase and sub-sample refinement at each reported window peak: z_i at n* - 1,
+// n*, n* + 1 recomputed as the dot products of mixing rows 2i, 2i+1 with those
+// operand rows (FP32 accumulation; the operand holds one extra sample on each
+// side of a chunk), one thread per (template, window) entry reading 16-byte
+// vectors; a team of 8 lanes shares an entry (strided over K, then reduced
+// with lane shuffles).  The refinement is the vertex of the parabola through
+// the three |z| values (offset clipped to half a sample; none when the triple
+// is not concave).  Peaks below `thr` get zeros (not reported), so only the
+// entries that become triggers do the work.
 template <typename T> struct Vec16 {
   T v[16 / sizeof(T)];
 };
@@ -577,8 +581,10 @@ template <typename T> struct Vec16 {
 template <typename T>
 __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ jobs, int n_jobs, int64_t entries,
                                                     float thr) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= entries) return;
+  constexpr int TEAM = 8;
+  const int64_t e = (int64_t)blockIdx.x * (256 / TEAM) + threadIdx.x / TEAM;
+  const int sub = threadIdx.x % TEAM;
+  if (e >= entries) return;   // uniform within a team
   // job owning entry e: last job with e0 <= e
   int lo = 0, hi = n_jobs - 1;
   while (lo < hi) {
@@ -591,27 +597,53 @@ __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ j
   const int64_t i = le / jb.nw, wl = le - i * jb.nw;
   const int64_t o = i * jb.ld_peak + (jb.w0 + wl - jb.w_base);
   if (!(jb.peak_snr[o] >= thr)) {
-    jb.peak_phase[o] = 0.f;
+    if (sub == 0) {
+      jb.peak_phase[o] = 0.f;
+      jb.peak_dt[o] = 0.f;
+      jb.peak_si[o] = 0.f;
+    }
     return;
   }
   constexpr int EPV = 16 / (int)sizeof(T);
   const int kcat = jb.kcat;   // a multiple of 32: rows are whole 16-byte vectors
-  const uint4 *orow = (const uint4 *)((const T *)jb.ocat + (jb.peak_n[o] - jb.ocat_abs0) * (int64_t)kcat);
+  const uint4 *o0 = (const uint4 *)((const T *)jb.ocat + (jb.peak_n[o] - 1 - jb.ocat_abs0) * (int64_t)kcat);
   const uint4 *mc = (const uint4 *)((const T *)jb.mix + (2 * i) * (int64_t)kcat);
   const uint4 *ms = mc + kcat / EPV;
-  float re = 0.f, im = 0.f;
-  for (int k = 0; k < kcat / EPV; ++k) {
-    const Vec16<T> a = __builtin_bit_cast(Vec16<T>, orow[k]);
+  float re[3] = {0.f, 0.f, 0.f}, im[3] = {0.f, 0.f, 0.f};
+  for (int k = sub; k < kcat / EPV; k += TEAM) {
     const Vec16<T> c = __builtin_bit_cast(Vec16<T>, mc[k]);
     const Vec16<T> d = __builtin_bit_cast(Vec16<T>, ms[k]);
 #pragma unroll
-    for (int j = 0; j < EPV; ++j) {
-      const float ov = Op<T>::tof(a.v[j]);
-      re += Op<T>::tof(c.v[j]) * ov;
-      im += Op<T>::tof(d.v[j]) * ov;
+    for (int q = 0; q < 3; ++q) {
+      const Vec16<T> a = __builtin_bit_cast(Vec16<T>, o0[q * (kcat / EPV) + k]);
+#pragma unroll
+      for (int j = 0; j < EPV; ++j) {
+        const float ov = Op<T>::tof(a.v[j]);
+        re[q] += Op<T>::tof(c.v[j]) * ov;
+        im[q] += Op<T>::tof(d.v[j]) * ov;
+      }
     }
   }
-  jb.peak_phase[o] = atan2f(im, re);
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int off = 1; off < TEAM; off <<= 1) {
+      re[q] += __shfl_xor(re[q], off);
+      im[q] += __shfl_xor(im[q], off);
+    }
+  if (sub != 0) return;
+  float amp[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) amp[q] = sqrtf(re[q] * re[q] + im[q] * im[q]) * jb.inv_scale;
+  const float curv = amp[0] - 2.f * amp[1] + amp[2];
+  float dt = 0.f, v = amp[1];
+  if (curv < 0.f) {
+    dt = fminf(0.5f, fmaxf(-0.5f, (amp[0] - amp[2]) / (2.f * curv)));
+    v = amp[1] - 0.25f * (amp[0] - amp[2]) * dt;
+  }
+  jb.peak_phase[o] = atan2f(im[1], re[1]);
+  jb.peak_dt[o] = dt;
+  jb.peak_si[o] = v;
 }
 
 // ---------------------------------------------------------- trigger compaction
@@ -700,6 +732,8 @@ __global__ void k_trigger_write(const TrigJob *__restrict__ jobs, int n_jobs, fl
       t.sample = jb.peak_n[i * jb.ld + w];
       t.snr = row[w];
       t.phase = jb.phase[i * jb.ld + w];
+      t.snr_interp = jb.si[i * jb.ld + w];
+      t.dt = jb.dt[i * jb.ld + w];
       out[pos] = t;
     }
     const int blk = sh[blockDim.x - 1];
@@ -827,7 +861,7 @@ hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_
 hipError_t launch_peak_phase(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float phase_thr,
                              hipStream_t s) {
   if (n_entries <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((n_entries + 255) / 256);
+  const unsigned blocks = (unsigned)((n_entries + 31) / 32);   // 32 entries of 8 lanes per workgroup
   switch (t) {
     case LLOID_F16: k_peak_phase<_Float16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, phase_thr); break;
     case LLOID_BF16: k_peak_phase<__bf16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, phase_thr); break;

@@ -81,12 +81,12 @@ int64_t tick_samples(const lloid_stream *s) { return s->max_w * s->win_len + 1; 
 
 // device bytes one active bank needs beyond its own arrays: per-tick scratch of every detector
 int64_t scratch_bytes(const lloid_stream *s, const lloid_bank *b) {
-  const int64_t ts = tick_samples(s);
+  const int64_t ts = tick_samples(s) + 2;
   int64_t per = (int64_t)ts * b->kcat * (int64_t)dtype_size(b->compute);
   for (const auto &sl : b->slices)
     if (sl.level > 0)
       for (int64_t ld : low_ld(ts, sl.level)) per += (int64_t)sl.lp * ld * (int64_t)low_esz(b->compute) + 256;
-  per += (int64_t)b->n_templates * s->max_w * (16 + (int64_t)sizeof(lloid_trigger)) + 4096;
+  per += (int64_t)b->n_templates * s->max_w * (24 + (int64_t)sizeof(lloid_trigger)) + 4096;
   return per * s->n_det;
 }
 
@@ -96,7 +96,7 @@ lloid_status check_bank(const lloid_stream *s, const lloid_bank *b) {
   if (b->f0 != s->f0) return fail(LLOID_EINVAL, "the bank's full rate differs from the stream's");
   if (b->compute != s->ct) return fail(LLOID_EINVAL, "the bank's compute type differs from the stream's");
   if (b->n_levels > s->n_levels) return fail(LLOID_EINVAL, "the bank's lowest rate is below the stream's");
-  if (!operands_fit(b, tick_samples(s))) return fail(LLOID_EINVAL, "the bank's per-tick buffers exceed 2 GiB");
+  if (!operands_fit(b, tick_samples(s) + 2)) return fail(LLOID_EINVAL, "the bank's per-tick buffers exceed 2 GiB");
   for (const auto &sl : b->slices) {
     const int64_t span = sl.start_tap / sl.dec + sl.n_taps + 4 * kHalfQ;
     if (span > s->hist[sl.level]) return fail(LLOID_EINVAL, "a slice spans more than the stream's history");
@@ -163,7 +163,8 @@ int64_t ready_until(const lloid_stream *s) {
     for (const auto &sl : s->slots) {
       if (!sl.active || !ok) continue;
       for (const auto &sd : sl.bank->slices) {
-        const Range r = need_ranges(t0, t1, sd.level + 1)[sd.level];
+        // outputs [t0 - 1, t1 + 1): the peaks' sub-sample refinement reads one sample past t1
+        const Range r = need_ranges(t0 - 1, t1 + 1, sd.level + 1)[sd.level];
         for (const auto &d : s->det)
           if (r.hi - sd.start_tap / sd.dec > d.avail[sd.level]) ok = false;
       }
@@ -201,14 +202,16 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
   for (int i : act) {
     const lloid_bank *b = s->slots[i].bank;
     for (int d = 0; d < s->n_det; ++d) {
-      add((size_t)tlen * b->kcat, esz);
+      add((size_t)(tlen + 2) * b->kcat, esz);
       for (const auto &sl : b->slices) {
         ++n_fir;
         if (sl.level > 0)
-          for (int64_t ld : low_ld(tlen, sl.level)) add((size_t)sl.lp * ld, low_esz(s->ct)), ++n_up;
+          for (int64_t ld : low_ld(tlen + 2, sl.level)) add((size_t)sl.lp * ld, low_esz(s->ct)), ++n_up;
       }
       add((size_t)b->n_templates * nw, 4);
       add((size_t)b->n_templates * nw, 8);
+      add((size_t)b->n_templates * nw, 4);
+      add((size_t)b->n_templates * nw, 4);
       add((size_t)b->n_templates * nw, 4);
     }
     rows += (int64_t)b->n_templates * s->n_det;
@@ -232,15 +235,17 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
     const lloid_bank *b = s->slots[i].bank;
     for (int d = 0; d < s->n_det; ++d) {
       BankBufs bb;
-      bb.ocat = cv.take<char>((size_t)tlen * b->kcat * esz);
+      bb.ocat = cv.take<char>((size_t)(tlen + 2) * b->kcat * esz);
       bb.low.assign(b->slices.size(), {});
       for (size_t k = 0; k < b->slices.size(); ++k)
         if (b->slices[k].level > 0)
-          for (int64_t ld : low_ld(tlen, b->slices[k].level))
+          for (int64_t ld : low_ld(tlen + 2, b->slices[k].level))
             bb.low[k].push_back(cv.take<char>((size_t)b->slices[k].lp * ld * low_esz(s->ct)));
       bb.psnr = cv.take<float>((size_t)b->n_templates * nw);
       bb.pn = cv.take<int64_t>((size_t)b->n_templates * nw);
       bb.pphase = cv.take<float>((size_t)b->n_templates * nw);
+      bb.pdt = cv.take<float>((size_t)b->n_templates * nw);
+      bb.psi = cv.take<float>((size_t)b->n_templates * nw);
       bb.ld_peak = nw;
       bb.w_base = wa;
       std::vector<LevelView> lv(s->n_levels);
@@ -248,7 +253,8 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
       for (int k = 0; k < s->n_levels; ++k) lv[k] = LevelView{ds.x[k], ds.lo[k], ds.avail[k] - ds.lo[k]};
       add_bank_jobs(b, lv.data(), t0, t1, n_end, wa, wb, s->win, bb, 1.f / (b->mix_scale * s->sscale), nullptr, 0, ts,
                     fj, uj, mj);
-      tj.push_back(TrigJob{bb.psnr, bb.pn, bb.pphase, nw, wa, nw, row, b->n_templates, s->slots[i].id, d, 0});
+      tj.push_back(TrigJob{bb.psnr, bb.pn, bb.pphase, bb.pdt, bb.psi, nw, wa, nw, row, b->n_templates, s->slots[i].id,
+                           d, 0});
       row += b->n_templates;
     }
   }

@@ -81,8 +81,9 @@ class lloid_stream_stats(ctypes.Structure):
 
 TRIGGER_DTYPE = np.dtype([("bank", np.int32), ("detector", np.int32), ("template_id", np.int32),
                           ("reserved", np.int32), ("window", np.int64), ("sample", np.int64),
-                          ("snr", np.float32), ("phase", np.float32)])
-assert TRIGGER_DTYPE.itemsize == 40
+                          ("snr", np.float32), ("phase", np.float32),
+                          ("snr_interp", np.float32), ("dt", np.float32)])
+assert TRIGGER_DTYPE.itemsize == 48
 
 
 def _load():
@@ -236,7 +237,7 @@ def lloid_filter(bank, detector: int, strain, window=(1, 1), threshold: float = 
     """strain: float64/float32 numpy array (host) or torch tensor (host or device).
 
     triggers_out: optional preallocated host buffer (numpy TRIGGER_DTYPE array or a
-    pinned torch uint8 tensor of 40*cap bytes).  snr_out: optional [F, n, 2] float32
+    pinned torch uint8 tensor of 48*cap bytes).  snr_out: optional [F, n, 2] float32
     numpy array or torch tensor receiving the complex SNR.
     """
     if isinstance(strain, np.ndarray):

@@ -60,6 +60,7 @@ int main(void) {
   P(lloid_stream_stats, bytes_in_use) P(lloid_stream_stats, graph_replays)
   P(lloid_slice, start_tap) P(lloid_slice, basis) P(lloid_slice, mixing)
   P(lloid_trigger, window) P(lloid_trigger, sample) P(lloid_trigger, snr) P(lloid_trigger, phase)
+  P(lloid_trigger, snr_interp) P(lloid_trigger, dt)
   P(lloid_bank_desc, slices) P(lloid_bank_info, device_bytes)
   return 0;
 }
@@ -75,7 +76,7 @@ int main(void) {
     for name, cls in mirror.items():
         assert int(got[name]) == ctypes.sizeof(cls), name
     assert int(got["lloid_trigger"]) == lloid.TRIGGER_DTYPE.itemsize
-    for f in ("window", "sample", "snr", "phase"):
+    for f in ("window", "sample", "snr", "phase", "snr_interp", "dt"):
         assert int(got[f"lloid_trigger.{f}"]) == lloid.TRIGGER_DTYPE.fields[f][1]
     for f in ("start_tap", "basis", "mixing"):
         assert int(got[f"lloid_slice.{f}"]) == getattr(lloid.lloid_slice, f).offset

@@ -247,3 +247,48 @@ def test_c1_full_size_sampled_windows(compute):
             log(f"  det {det}: {res.n_triggers} triggers, windows checked {sample}")
     finally:
         lloid.lloid_bank_destroy(b)
+
+
+@pytest.mark.parametrize("compute", PRECISIONS)
+def test_subsample_peaks_match_oracle(compute):
+    """Every trigger's sub-sample refinement equals the oracle's parabola through
+    the oracle's |z| at the peak sample and its neighbours (where the peak sample
+    agrees, i.e. outside near ties), and does not depend on chunking: forcing
+    chunks of a few windows gives bit-identical records."""
+    from paper_2410_16416_amd import lloid
+    log(f"[subsample] compute={compute}")
+    wl, x, _, _, _, _ = mini_case()
+    n = x.shape[0]
+    z = oracle.lloid_snr(wl.bank, x, -1, n + 1)          # one sample of margin on each side
+    a = np.abs(z)
+    b = lloid.bank_from_svd(ctx(), wl.bank, compute)
+    try:
+        res = lloid.lloid_filter(b, 0, x, window=(1, 4), threshold=3.0)
+        lloid.lloid_ctx_set_chunk_bytes(ctx(), 400000)
+        try:
+            chunked = lloid.lloid_filter(b, 0, x, window=(1, 4), threshold=3.0)
+        finally:
+            lloid.lloid_ctx_set_chunk_bytes(ctx(), 6 << 30)
+    finally:
+        lloid.lloid_bank_destroy(b)
+    t = res.triggers
+    assert t.shape[0] > 20
+    assert np.array_equal(t, chunked.triggers)
+    eps = EPS_ABS[compute]
+    i, s = t["template_id"].astype(np.int64), t["sample"].astype(np.int64)
+    dt_o, v_o = oracle.subsample_peak(a[i, s], a[i, s + 1], a[i, s + 2])    # a[:, k] is sample k - 1
+    curv = a[i, s] - 2.0 * a[i, s + 1] + a[i, s + 2]
+    # compare where the oracle has the same peak sample (outside near ties)
+    wins = t["window"].astype(np.int64)
+    starts = oracle.window_starts(int(wins.max()) + 2, 1024, 1, 4)
+    same = np.array([a[ii, 1 + starts[w]:1 + min(starts[w + 1], n)].argmax() + starts[w] == ss
+                     for ii, w, ss in zip(i, wins, s)])
+    assert same.mean() > 0.8
+    assert np.all(np.abs(t["snr_interp"][same] - v_o[same]) <= 2 * eps)
+    # dt is ill-conditioned where the peak is flat: a perturbation eps of the
+    # three values moves the vertex by about 2 eps / |curvature|
+    tol = np.minimum(1.0, 4 * eps / np.maximum(np.abs(curv[same]), 1e-12)) + 1e-6
+    assert np.all(np.abs(t["dt"][same] - dt_o[same]) <= tol)
+    assert np.all(np.abs(t["dt"]) <= 0.5) and np.all(t["snr_interp"] >= t["snr"] - 2 * eps)
+    log(f"  {t.shape[0]} triggers, {int(same.sum())} compared, max |d snr_interp| "
+        f"{float(np.abs(t['snr_interp'][same] - v_o[same]).max()):.2e}")
