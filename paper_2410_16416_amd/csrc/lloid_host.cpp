@@ -575,7 +575,9 @@ void lloid::number_jobs(std::vector<FirJob> &fj, std::vector<UpJob> *uj, std::ve
   int64_t e = 0;
   for (auto &m : mj) {
     m.item0 = it;
-    it += ceil_div(m.nw, 8) * 8 * m.n_rtiles;
+    // windows in runs of 8 (one per XCD) per row tile; fewer than 8 windows
+    // run window-major over the row tiles, padded to a multiple of 8
+    it += m.nw >= 8 ? ceil_div(m.nw, 8) * 8 * m.n_rtiles : round_up(m.nw * m.n_rtiles, 8);
     m.e0 = e;
     e += (int64_t)m.n_templates * m.nw;
   }
@@ -714,7 +716,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
       if (sl.level > 0)
         for (int64_t ld : low_ld(chunk_n + 2, sl.level)) add((size_t)sl.lp * ld, low_esz(ct));
   }
-  add((size_t)total_rows + 2, 8);
+  add((size_t)trig_blocks(total_rows * W) + 2, 8);
   add(1, 4);
   add((size_t)std::max<int64_t>(dev_cap, 1), sizeof(lloid_trigger));
   if (host_snr) add((size_t)n * 2 * banks[0]->n_templates, 4);
@@ -752,8 +754,9 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
           bw[i].low[s].push_back(cv.take<char>((size_t)sl.lp * ld * low_esz(ct)));
     }
   }
-  int64_t *counts = cv.take<int64_t>((size_t)total_rows + 2);
-  int64_t *total = counts + total_rows;
+  const int64_t n_blk = trig_blocks(total_rows * W);
+  int64_t *counts = cv.take<int64_t>((size_t)n_blk + 2);
+  int64_t *total = counts + n_blk;
   int *bad = cv.take<int>(1);
   lloid_trigger *dtrig = cv.take<lloid_trigger>((size_t)std::max<int64_t>(dev_cap, 1));
   float *dsnr = snr ? (host_snr ? cv.take<float>((size_t)n * 2 * banks[0]->n_templates) : snr) : nullptr;
@@ -796,11 +799,11 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   }
   std::vector<TrigJob> tj(nb);
   {
-    int64_t row = 0;
+    int64_t e = 0;
     for (int i = 0; i < nb; ++i) {
-      tj[i] = TrigJob{bw[i].psnr, bw[i].pn, bw[i].pphase, bw[i].pdt, bw[i].psi, W, 0, W, row, banks[i]->n_templates,
+      tj[i] = TrigJob{bw[i].psnr, bw[i].pn, bw[i].pphase, bw[i].pdt, bw[i].psi, 0, W, e, banks[i]->n_templates,
                       i, detector, 0};
-      row += banks[i]->n_templates;
+      e += (int64_t)banks[i]->n_templates * W;
     }
   }
   const size_t trig_off = put(tj.data(), tj.size() * sizeof(TrigJob));
@@ -838,8 +841,8 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     if (r2 != LLOID_OK) return r2;
   }
   HIP_TRY(mark(LLOID_STAGE_TRIGGER, 0));
-  HIP_TRY(launch_trigger_jobs((const TrigJob *)(dtab + trig_off), nb, total_rows, thr, counts, total, dev_cap, dtrig,
-                              st));
+  HIP_TRY(launch_trigger_jobs((const TrigJob *)(dtab + trig_off), nb, total_rows * W, thr, counts, total, dev_cap,
+                              dtrig, st));
   HIP_TRY(mark(LLOID_STAGE_TRIGGER, 1));
   HIP_TRY(mark(LLOID_STAGE_D2H, 0));
   int64_t h_total = 0;

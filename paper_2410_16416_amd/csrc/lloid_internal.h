@@ -98,14 +98,21 @@ struct MixJob {
   int rows, kcat, n_templates, n_rtiles, pad;
 };
 
-// Trigger compaction over the peak table of one bank, windows [w_base, w_base + nw).
+// Trigger compaction over the peak table of one bank, windows [w_base, w_base + nw):
+// dense [n_templates][nw] tables whose entries are numbered elem0, elem0 + 1, ...
+// in the flat order of the batch.
 struct TrigJob {
   const float *snr;
   const int64_t *peak_n;
   const float *phase, *dt, *si;
-  int64_t ld, w_base, nw, row0;   // row0: first (bank, template) row of this job
+  int64_t w_base, nw, elem0;
   int n_templates, bank_id, detector, pad;
 };
+
+// Entries per trigger-compaction block, and the per-block count slots that
+// n_elems entries need (the scan also keeps the total after them).
+constexpr int kTrigPerBlock = 1024;
+inline int64_t trig_blocks(int64_t n_elems) { return (n_elems + kTrigPerBlock - 1) / kTrigPerBlock; }
 
 }  // namespace lloid
 
@@ -162,8 +169,9 @@ hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_
                            hipStream_t s);
 hipError_t launch_peak_phase(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float phase_thr,
                              hipStream_t s);
-// Trigger compaction: counts, offsets and records (job-major, template, window).
-hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_rows, float thr, int64_t *counts,
+// Trigger compaction: counts, offsets and records (job-major, template, window);
+// counts holds trig_blocks(n_elems) slots.
+hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems, float thr, int64_t *counts,
                                int64_t *total, int64_t cap, lloid_trigger *out, hipStream_t s);
 hipError_t launch_sigma2(const double *mix64, int n_templates, int lsum, const double *inv_dec_per_col,
                          double *out, hipStream_t s);

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "lloid_internal.h"
 
@@ -236,6 +237,10 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
   // lane's shifted copy: its column offset within a fragment is constant mod VEC
   const int lr = (lane & 31) % O::VEC;
   const T *bl = Bc + lr * WC + (wave * NT * 32 + (lane & 31) + (lane >> 5) * O::VEC - lr);
+  // 32-column fragments of this wave that start before k_hi: past the end of
+  // a ragged last tile a wave skips their MFMAs (it still loads and syncs)
+  const int64_t wcol = i0 + wave * NT * 32;
+  const int live = (int)(jb.k_hi <= wcol ? 0 : std::min<int64_t>(NT, (jb.k_hi - wcol + 31) / 32));
   int ksup = 0;
   for (int c = 0; c < nchunks; ++c) {
     const int cur = c & 1, kc = c * BK;
@@ -254,20 +259,27 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
     la.store(As[cur]);
     __syncthreads();
     if (c + 1 < nchunks) la.load(ra, (kc + BK) * (int)sizeof(T));
+    auto ksteps = [&](auto all) __attribute__((always_inline)) {
 #pragma unroll
-    for (int ks = 0; ks < BK / O::KS; ++ks) {
-      if (BK > kBK && kc + ks * O::KS >= np) break;
-      typename O::vec af[MT], bf[NT];
+      for (int ks = 0; ks < BK / O::KS; ++ks) {
+        if (BK > kBK && kc + ks * O::KS >= np) break;
+        typename O::vec af[MT], bf[NT];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-        af[mt] = *(const typename O::vec *)(As[cur] + (mt * 32 + (lane & 31)) * P + ks * O::KS + (lane >> 5) * O::VEC);
+        for (int mt = 0; mt < MT; ++mt)
+          af[mt] = *(const typename O::vec *)(As[cur] + (mt * 32 + (lane & 31)) * P + ks * O::KS + (lane >> 5) * O::VEC);
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) bf[nt] = *(const typename O::vec *)(bl + (kc - ksup) + nt * 32 + ks * O::KS);
+        for (int nt = 0; nt < NT; ++nt)
+          if (decltype(all)::value || nt < live)
+            bf[nt] = *(const typename O::vec *)(bl + (kc - ksup) + nt * 32 + ks * O::KS);
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = O::mfma(af[mt], bf[nt], acc[mt][nt]);
-    }
+          for (int nt = 0; nt < NT; ++nt)
+            if (decltype(all)::value || nt < live) acc[mt][nt] = O::mfma(af[mt], bf[nt], acc[mt][nt]);
+      }
+    };
+    if (live == NT) ksteps(std::true_type{});
+    else if (live > 0) ksteps(std::false_type{});
   }
 
   // store: lane holds column i, rows rb..rb+3 for each group of four; level-0
@@ -432,13 +444,21 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mix_peak(const MixJob *__restr
   const MixJob &jb = jobs[find_job(jobs, n_jobs, blockIdx.x)];
   // XCD-aware order: the 8 XCDs take workgroups round-robin (every job's items
   // start at a multiple of 8), so give all row tiles of one window the same
-  // XCD and neighbouring slots (shared operand rows in that XCD's L2).
+  // XCD and neighbouring slots (shared operand rows in that XCD's L2).  A job
+  // of fewer than 8 windows would leave XCDs idle that way: its items run
+  // window-major over the row tiles instead, spread over all XCDs.
   const int64_t b = (int64_t)blockIdx.x - jb.item0;
-  const int xcd = (int)(b & 7);
-  const int64_t slot = b >> 3;
   const int n_rtiles = jb.n_rtiles;
-  const int rt = (int)(slot % n_rtiles);
-  const int64_t wl = (slot / n_rtiles) * 8 + xcd;   // window within the job
+  int rt;
+  int64_t wl;   // window within the job
+  if (jb.nw >= 8) {
+    const int64_t slot = b >> 3;
+    rt = (int)(slot % n_rtiles);
+    wl = (slot / n_rtiles) * 8 + (b & 7);
+  } else {
+    rt = (int)(b % n_rtiles);
+    wl = b / n_rtiles;
+  }
   if (wl >= jb.nw) return;
   const int64_t w = jb.w0 + wl;
   const T *mix = (const T *)jb.mix;
@@ -647,98 +667,136 @@ __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ j
 }
 
 // ---------------------------------------------------------- trigger compaction
+// Stream compaction over the flat (job, template, window) order of every peak
+// table: per-block flag counts, an exclusive scan of the block counts, then a
+// rewrite of each block's flagged entries at its scanned offset.  A block
+// covers kTrigPerBlock consecutive entries in kTrigPerBlock / 256 rounds of
+// 256, so the cost follows the number of entries whatever the row shape.
 
-__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *sh) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  int64_t tot = 0;
-  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) tot += sh[q];
-  __syncthreads();
-  return tot;
-}
+constexpr int kTrigThreads = 256;
 
-// Row r of the batch is template (r - row0) of the job owning it.
-__device__ __forceinline__ int find_trig_job(const TrigJob *__restrict__ jobs, int n_jobs, int64_t row) {
+// Job owning flat entry e: the last job with elem0 <= e.
+__device__ __forceinline__ int find_trig_job(const TrigJob *__restrict__ jobs, int n_jobs, int64_t e) {
   int lo = 0, hi = n_jobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].row0 <= row) lo = mid;
+    if (jobs[mid].elem0 <= e) lo = mid;
     else hi = mid - 1;
   }
   return lo;
 }
 
-__global__ void k_trigger_count(const TrigJob *__restrict__ jobs, int n_jobs, float thr, int64_t *__restrict__ counts) {
-  __shared__ int64_t sh[16];
-  const TrigJob &jb = jobs[find_trig_job(jobs, n_jobs, blockIdx.x)];
-  const int64_t i = (int64_t)blockIdx.x - jb.row0;
-  const float *row = jb.snr + i * jb.ld;
-  int64_t c = 0;
-  for (int64_t w = threadIdx.x; w < jb.nw; w += blockDim.x) c += row[w] >= thr ? 1 : 0;
-  c = block_sum(c, sh);
-  if (threadIdx.x == 0) counts[blockIdx.x] = c;
+__device__ __forceinline__ uint64_t lanes_below() {
+  const int lane = (int)(threadIdx.x & 63);
+  return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
-// exclusive prefix sum of counts[0..n) in place; total in *total (one block)
-__global__ void k_trigger_scan(int64_t *counts, int64_t n, int64_t *total) {
-  __shared__ int64_t sh[1024];
-  int64_t carry = 0;
-  for (int64_t base = 0; base < n; base += blockDim.x) {
-    const int64_t i = base + threadIdx.x;
-    const int64_t v = i < n ? counts[i] : 0;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-      const int64_t add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
-      __syncthreads();
-      sh[threadIdx.x] += add;
-      __syncthreads();
+__global__ __launch_bounds__(kTrigThreads) void k_trigger_count(const TrigJob *__restrict__ jobs, int n_jobs,
+                                                                int64_t n_elems, float thr,
+                                                                int64_t *__restrict__ counts) {
+  __shared__ int sh[kTrigThreads / 64];
+  int c = 0;
+  for (int k = 0; k < kTrigPerBlock / kTrigThreads; ++k) {
+    const int64_t e = (int64_t)blockIdx.x * kTrigPerBlock + k * kTrigThreads + threadIdx.x;
+    bool f = false;
+    if (e < n_elems) {
+      const TrigJob &jb = jobs[find_trig_job(jobs, n_jobs, e)];
+      f = jb.snr[e - jb.elem0] >= thr;
     }
-    if (i < n) counts[i] = carry + sh[threadIdx.x] - v;
-    const int64_t blk = sh[blockDim.x - 1];
+    c += __popcll(__ballot(f));
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int q = 0; q < kTrigThreads / 64; ++q) t += sh[q];
+    counts[blockIdx.x] = t;
+  }
+}
+
+// Exclusive prefix sum of counts[0..n) in place, total in *total; one block of
+// 1024 threads, each taking 8 consecutive values per pass.
+__global__ __launch_bounds__(1024) void k_trigger_scan(int64_t *counts, int64_t n, int64_t *total) {
+  constexpr int V = 8, TPB = 1024;
+  __shared__ int64_t wsum[TPB / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += (int64_t)TPB * V) {
+    const int64_t i0 = base + (int64_t)threadIdx.x * V;
+    int64_t v[V];
+    int64_t own = 0;
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      v[q] = i0 + q < n ? counts[i0 + q] : 0;
+      own += v[q];
+    }
+    // inclusive scan of the per-thread sums across the wave, then across waves
+    int64_t inc = own;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t u = __shfl_up(inc, off);
+      if (lane >= off) inc += u;
+    }
+    if (lane == 63) wsum[wave] = inc;
     __syncthreads();
-    carry += blk;
+    int64_t before = carry, pass = 0;
+    for (int q = 0; q < TPB / 64; ++q) {
+      if (q < wave) before += wsum[q];
+      pass += wsum[q];
+    }
+    int64_t run = before + inc - own;
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      if (i0 + q < n) counts[i0 + q] = run;
+      run += v[q];
+    }
+    carry += pass;
+    __syncthreads();
   }
   if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ void k_trigger_write(const TrigJob *__restrict__ jobs, int n_jobs, float thr,
-                                const int64_t *__restrict__ offsets, int64_t cap, lloid_trigger *__restrict__ out) {
-  __shared__ int sh[1024];
-  const TrigJob &jb = jobs[find_trig_job(jobs, n_jobs, blockIdx.x)];
-  const int64_t i = (int64_t)blockIdx.x - jb.row0;
-  const float *row = jb.snr + i * jb.ld;
+__global__ __launch_bounds__(kTrigThreads) void k_trigger_write(const TrigJob *__restrict__ jobs, int n_jobs,
+                                                                int64_t n_elems, float thr,
+                                                                const int64_t *__restrict__ offsets, int64_t cap,
+                                                                lloid_trigger *__restrict__ out) {
+  __shared__ int sh[kTrigThreads / 64];
+  const int wave = threadIdx.x >> 6;
   int64_t run = offsets[blockIdx.x];
-  for (int64_t base = 0; base < jb.nw; base += blockDim.x) {
-    const int64_t w = base + threadIdx.x;
-    const int f = (w < jb.nw && row[w] >= thr) ? 1 : 0;
-    sh[threadIdx.x] = f;
-    __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-      const int add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
-      __syncthreads();
-      sh[threadIdx.x] += add;
-      __syncthreads();
+  for (int k = 0; k < kTrigPerBlock / kTrigThreads; ++k) {
+    const int64_t e = (int64_t)blockIdx.x * kTrigPerBlock + k * kTrigThreads + threadIdx.x;
+    int j = 0;
+    bool f = false;
+    if (e < n_elems) {
+      j = find_trig_job(jobs, n_jobs, e);
+      f = jobs[j].snr[e - jobs[j].elem0] >= thr;
     }
-    const int64_t pos = run + sh[threadIdx.x] - f;
+    const uint64_t m = __ballot(f);
+    if ((threadIdx.x & 63) == 0) sh[wave] = __popcll(m);
+    __syncthreads();
+    int64_t pos = run + __popcll(m & lanes_below());
+    int blk = 0;
+    for (int q = 0; q < kTrigThreads / 64; ++q) {
+      if (q < wave) pos += sh[q];
+      blk += sh[q];
+    }
     if (f && pos < cap) {
+      const TrigJob &jb = jobs[j];
+      const int64_t o = e - jb.elem0;   // template o / nw, window o % nw of this table
       lloid_trigger t;
       t.bank = jb.bank_id;
       t.detector = jb.detector;
-      t.template_id = (int32_t)i;
+      t.template_id = (int32_t)(o / jb.nw);
       t.reserved = 0;
-      t.window = jb.w_base + w;
-      t.sample = jb.peak_n[i * jb.ld + w];
-      t.snr = row[w];
-      t.phase = jb.phase[i * jb.ld + w];
-      t.snr_interp = jb.si[i * jb.ld + w];
-      t.dt = jb.dt[i * jb.ld + w];
+      t.window = jb.w_base + o % jb.nw;
+      t.sample = jb.peak_n[o];
+      t.snr = jb.snr[o];
+      t.phase = jb.phase[o];
+      t.snr_interp = jb.si[o];
+      t.dt = jb.dt[o];
       out[pos] = t;
     }
-    const int blk = sh[blockDim.x - 1];
-    __syncthreads();
     run += blk;
+    __syncthreads();
   }
 }
 
@@ -871,15 +929,13 @@ hipError_t launch_peak_phase(lloid_dtype t, const MixJob *jobs, int n_jobs, int6
   return hipGetLastError();
 }
 
-hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_rows, float thr, int64_t *counts,
+hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems, float thr, int64_t *counts,
                                int64_t *total, int64_t cap, lloid_trigger *out, hipStream_t s) {
-  if (n_rows <= 0) {
-    k_trigger_scan<<<1, 1024, 0, s>>>(counts, 0, total);
-    return hipGetLastError();
-  }
-  k_trigger_count<<<(unsigned)n_rows, 256, 0, s>>>(jobs, n_jobs, thr, counts);
-  k_trigger_scan<<<1, 1024, 0, s>>>(counts, n_rows, total);
-  k_trigger_write<<<(unsigned)n_rows, 1024, 0, s>>>(jobs, n_jobs, thr, counts, cap, out);
+  const int64_t nblk = n_elems > 0 ? trig_blocks(n_elems) : 0;
+  if (nblk > 0) k_trigger_count<<<(unsigned)nblk, kTrigThreads, 0, s>>>(jobs, n_jobs, n_elems, thr, counts);
+  k_trigger_scan<<<1, 1024, 0, s>>>(counts, nblk, total);
+  if (nblk > 0)
+    k_trigger_write<<<(unsigned)nblk, kTrigThreads, 0, s>>>(jobs, n_jobs, n_elems, thr, counts, cap, out);
   return hipGetLastError();
 }
 

@@ -216,7 +216,7 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
     }
     rows += (int64_t)b->n_templates * s->n_det;
   }
-  add((size_t)rows + 2, 8);
+  add((size_t)trig_blocks(rows * nw) + 2, 8);
   add((size_t)rows * nw, sizeof(lloid_trigger));
   const size_t tab_bytes = n_fir * sizeof(FirJob) + n_up * sizeof(UpJob) +
                            act.size() * s->n_det * (sizeof(MixJob) + sizeof(TrigJob)) + 64 * (4 + kMaxHops);
@@ -253,13 +253,14 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
       for (int k = 0; k < s->n_levels; ++k) lv[k] = LevelView{ds.x[k], ds.lo[k], ds.avail[k] - ds.lo[k]};
       add_bank_jobs(b, lv.data(), t0, t1, n_end, wa, wb, s->win, bb, 1.f / (b->mix_scale * s->sscale), nullptr, 0, ts,
                     fj, uj, mj);
-      tj.push_back(TrigJob{bb.psnr, bb.pn, bb.pphase, bb.pdt, bb.psi, nw, wa, nw, row, b->n_templates, s->slots[i].id,
-                           d, 0});
+      tj.push_back(TrigJob{bb.psnr, bb.pn, bb.pphase, bb.pdt, bb.psi, wa, nw, row * nw, b->n_templates,
+                           s->slots[i].id, d, 0});
       row += b->n_templates;
     }
   }
-  int64_t *counts = cv.take<int64_t>((size_t)rows + 2);
-  int64_t *total = counts + rows;
+  const int64_t n_blk = trig_blocks(rows * nw);
+  int64_t *counts = cv.take<int64_t>((size_t)n_blk + 2);
+  int64_t *total = counts + n_blk;
   const int64_t cap = rows * nw;
   lloid_trigger *dtrig = cv.take<lloid_trigger>((size_t)std::max<int64_t>(cap, 1));
   char *dtab = cv.take<char>(tab_bytes);
@@ -290,8 +291,8 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
     HIP_TRY(hipMemcpyAsync(dtab, htab, off, hipMemcpyHostToDevice, st));
     const lloid_status r = launch_stages(ctx, s->ct, dtab, to, items, false, s->thr, nullptr);
     if (r != LLOID_OK) return r;
-    HIP_TRY(launch_trigger_jobs((const TrigJob *)(dtab + trig_off), (int)tj.size(), rows, s->thr, counts, total, cap,
-                                dtrig, st));
+    HIP_TRY(launch_trigger_jobs((const TrigJob *)(dtab + trig_off), (int)tj.size(), rows * nw, s->thr, counts, total,
+                                cap, dtrig, st));
     HIP_TRY(hipMemcpyAsync(s->hsmall, total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(s->hsmall + 1, s->bad, sizeof(int), hipMemcpyDeviceToHost, st));
     return LLOID_OK;
