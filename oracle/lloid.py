@@ -270,6 +270,34 @@ def subsample_peak(a_prev, a_peak, a_next):
     return dt, value
 
 
+def xi2(z: np.ndarray, n_lo: int, n_end: int, n_star: int, acorr: np.ndarray) -> float:
+    """Signal-consistency value of one peak (Sec. II.A computes it, with the
+    phase, for every trigger, citing the autocorrelation test of the GstLAL
+    papers).  Restated: with the template's normalised complex
+    autocorrelation R[k], k = -K..K (R[0] = 1), a signal matching the template
+    makes the SNR around the peak follow z[n* + k] = z[n*] R[k], so
+
+        xi2 = sum_k |z[n* + k] - z[n*] R[k]|^2 / sum_k (2 - 2 |R[k]|^2),
+
+    the denominator being the expected numerator in unit white noise (E|z|^2
+    = 2 for unit-norm cos and sin filters), so that xi2 averages 1 on noise.
+    Both sums run over the lags with 0 <= n* + k < n_end (the samples the SNR
+    series has); a zero denominator gives 0.
+
+    z: complex SNR of the template on samples n_lo .. n_lo + len - 1, covering
+    the lags used; acorr: complex [2K + 1], index K + k for lag k."""
+    half = (acorr.shape[0] - 1) // 2
+    lag = np.arange(-half, half + 1)
+    n = n_star + lag
+    ok = (n >= 0) & (n < n_end)
+    zk = z[n[ok] - n_lo]
+    r = acorr[ok]
+    zs = z[n_star - n_lo]
+    num = float(np.sum(np.abs(zk - zs * r) ** 2))
+    den = float(np.sum(2.0 - 2.0 * np.abs(r) ** 2))
+    return num / den if den > 0.0 else 0.0
+
+
 def sigma2(bank) -> np.ndarray:
     """Squared full-rate norm of each reconstructed template (cos + sin).
 

@@ -447,3 +447,94 @@ def test_subsample_peak_recovers_a_fractional_arrival():
         peak_true = np.abs(oracle.direct_snr(h, x, t_c, t_c + 1)[0, 0])   # the aligned peak
         assert abs((k + dt) - (t_c + tau)) < 0.05, tau
         assert abs(v - peak_true) < 0.35 * abs(a[k] - peak_true), tau
+
+
+# ------------------------------------------------- signal consistency (xi^2)
+
+def _rand_acorr(rng, half):
+    """A Hermitian lag table with R[0] = 1 and |R| < 1 elsewhere."""
+    r = np.zeros(2 * half + 1, dtype=np.complex128)
+    r[half] = 1.0
+    for k in range(1, half + 1):
+        v = 0.8 ** k * np.exp(1j * rng.uniform(0, 2 * np.pi))
+        r[half + k] = v
+        r[half - k] = np.conj(v)
+    return r
+
+
+def test_autocorrelation_input_matches_numpy_correlate():
+    """The bank's lag table (setup stage) against the library correlation:
+    np.correlate(h, h, 'full')[N - 1 + k] = sum_j h[j] conj(h[j - k])."""
+    from workloads import autocorrelation
+    rng = np.random.default_rng(11)
+    f = rng.standard_normal((6, 29))
+    r = autocorrelation(f, 7)
+    for i in range(3):
+        h = f[2 * i] + 1j * f[2 * i + 1]
+        c = np.correlate(h, h, "full") / np.sum(np.abs(h) ** 2)
+        assert np.allclose(r[i], c[28 - 7:28 + 8], atol=1e-14)
+        assert abs(r[i, 7] - 1.0) < 1e-14
+        assert np.allclose(r[i, ::-1], np.conj(r[i]), atol=1e-14)
+
+
+def test_xi2_vanishes_on_a_pure_template_response_and_counts_a_defect():
+    """Closed form: if z[n* + k] = c R[k] on every lag, each numerator term is
+    zero; adding e at one in-range lag k0 != 0 gives |e|^2 / sum (2 - 2|R|^2);
+    a defect outside the lag range, or outside [0, n_end), changes nothing.
+    A transposed lag (R[-k]) or a missing conjugate fails the first case."""
+    rng = np.random.default_rng(12)
+    half = 5
+    r = _rand_acorr(rng, half)
+    c = 7.0 * np.exp(0.7j)
+    n_star, n_lo = 40, 30
+    z = np.zeros(30, dtype=np.complex128)
+    z[n_star - half - n_lo:n_star + half + 1 - n_lo] = c * r
+    den = np.sum(2.0 - 2.0 * np.abs(r) ** 2)
+    assert oracle.xi2(z, n_lo, 1000, n_star, r) < 1e-24
+    z2 = z.copy()
+    e = 0.3 - 0.2j
+    z2[n_star + 3 - n_lo] += e
+    assert abs(oracle.xi2(z2, n_lo, 1000, n_star, r) - abs(e) ** 2 / den) < 1e-14
+    z3 = z.copy()
+    z3[n_star + half + 2 - n_lo] += 5.0                  # beyond the lag range
+    assert oracle.xi2(z3, n_lo, 1000, n_star, r) < 1e-24
+    # the series ends at n_end = n* + 2: lags 3..5 drop out of both sums
+    den_c = np.sum(2.0 - 2.0 * np.abs(r[:half + 3]) ** 2)
+    assert abs(oracle.xi2(z2, n_lo, n_star + 3, n_star, r) - 0.0) < 1e-24
+    z4 = z.copy()
+    z4[n_star - 2 - n_lo] += e
+    assert abs(oracle.xi2(z4, n_lo, n_star + 3, n_star, r) - abs(e) ** 2 / den_c) < 1e-14
+    # the start of the data clips the negative lags the same way
+    z5 = np.zeros(12, dtype=np.complex128)
+    z5[:1 + half] = c * r[half - 0:]
+    z5[1] += e
+    den_s = np.sum(2.0 - 2.0 * np.abs(r[half:]) ** 2)
+    assert abs(oracle.xi2(z5, 0, 1000, 0, r) - abs(e) ** 2 / den_s) < 1e-14
+    # a transposed lag table is caught by the pure response
+    assert oracle.xi2(z, n_lo, 1000, n_star, r[::-1]) > 1e-3
+
+
+def test_xi2_averages_one_in_white_noise():
+    """Closed-form expectation: with z the exact matched filter of unit-norm
+    cos/sin filters in unit white noise and R their autocorrelation,
+    E|z[n+k] - z[n] R[k]|^2 = 2 - 2|R[k]|^2 at any fixed n, so xi2 averages 1
+    (Sec. II.A's consistency value, normalised as restated in the oracle).
+    Dropping the conjugate in the lag table gives 2 + 2|R|^2 - 4 Re R^2
+    instead, caught below."""
+    from workloads import autocorrelation
+    from workloads.chirp import mass_chirps
+    f0, n = 1024, 1 << 17
+    fam = mass_chirps(2, f0, 0.5, 20.0, 1.2, 2.0, np.random.default_rng(3))
+    h = fam.full_rate_filters()
+    half = 24
+    r = autocorrelation(h, half)
+    x = np.random.default_rng(4).standard_normal(n)
+    z = oracle.direct_snr(h, x, 0, n)
+    pos = np.arange(2000, n - 2000, 37)
+    for i in range(2):
+        v = np.array([oracle.xi2(z[i], 0, n, int(p), r[i]) for p in pos])
+        # neighbouring positions are nearly independent at this spacing
+        se = np.std(v) / np.sqrt(len(v))
+        assert abs(np.mean(v) - 1.0) < 5 * se + 0.01, (i, np.mean(v), se)
+        w = np.array([oracle.xi2(z[i], 0, n, int(p), np.conj(r[i])) for p in pos[:400]])
+        assert np.max(np.abs(r[i].imag)) > 0.3 and np.mean(w) > 1.5

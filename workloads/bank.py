@@ -56,6 +56,9 @@ class SvdBank:
     n_templates: int
     slices: list = field(default_factory=list)
     family: ChirpFamily | None = None
+    # normalised complex autocorrelation of each template, [F, 2K + 1] (column
+    # K + k holds lag k), or None; the input of the signal-consistency value
+    autocorr: np.ndarray | None = None
 
     def decimation(self, s: int) -> int:
         return self.f0 // self.slices[s].rate
@@ -110,3 +113,46 @@ def build_svd_bank(family: ChirpFamily, f0: int, specs: list) -> SvdBank:
             mixing=np.ascontiguousarray(a[:, :l] * sv[None, :l]),
             singular_values=sv.copy()))
     return bank
+
+
+def autocorrelation(filters: np.ndarray, half: int) -> np.ndarray:
+    """Normalised complex autocorrelation of the templates in `filters`.
+
+    Rows 2i and 2i+1 are the cos and sin filters of template i at taps
+    j = 0..N-1 before coalescence; h_i = h_2i + i h_2i+1.  For lags
+    k = -half..half,
+
+        R_i[k] = sum_j h_i[j] conj(h_i[j - k]) / sum_j |h_i[j]|^2,
+
+    so R_i[0] = 1 and R_i[-k] = conj(R_i[k]).  This is the covariance
+    E[z_i[n + k] conj(z_i[n])] / E|z_i[n]|^2 of the complex SNR in white
+    noise.  Returns complex128 [F, 2 half + 1], column half + k for lag k.
+    """
+    h = filters[0::2] + 1j * filters[1::2]
+    n = h.shape[1]
+    size = 1 << int(np.ceil(np.log2(n + half + 1)))
+    spec = np.fft.fft(h, size, axis=1)
+    circ = np.fft.ifft(spec * np.conj(spec), axis=1)     # circ[k] = sum_j h[j] conj(h[j - k])
+    lags = np.arange(-half, half + 1) % size
+    r = circ[:, lags]
+    return r / np.sum(np.abs(h) ** 2, axis=1)[:, None]
+
+
+def bank_autocorrelation(bank: SvdBank, half: int, batch: int = 64) -> np.ndarray:
+    """Autocorrelation input of a bank: from the full-rate chirp templates when
+    the bank was built from a family, else (banks with random bases) from the
+    reconstruction M U of its full-rate slice, which stands in for templates."""
+    if bank.family is not None:
+        out = np.empty((bank.n_templates, 2 * half + 1), dtype=np.complex128)
+        for a in range(0, bank.n_templates, batch):
+            rows = np.arange(a, min(a + batch, bank.n_templates))
+            out[rows] = autocorrelation(bank.family.full_rate_filters(rows), half)
+        return out
+    top = bank.slices[0]
+    if top.rate != bank.f0:
+        raise ValueError("a bank without a family needs a full-rate first slice")
+    out = np.empty((bank.n_templates, 2 * half + 1), dtype=np.complex128)
+    for a in range(0, bank.n_templates, batch):
+        b = min(a + batch, bank.n_templates)
+        out[a:b] = autocorrelation(top.mixing[2 * a:2 * b] @ top.basis, half)
+    return out
