@@ -92,16 +92,24 @@ typedef struct {
   lloid_dtype compute;   /* operand type of both GEMMs: LLOID_F32, LLOID_F16 or LLOID_BF16;
                             accumulation is always FP32 */
   const lloid_slice *slices;
+  int32_t autocorr_half; /* K, 0..512: lags of the signal-consistency value; 0 = not computed */
+  int32_t reserved;
+  const double *autocorr; /* host, [n_templates][2K + 1][2]: (Re, Im) of template i's normalised
+                             complex autocorrelation R_i[k] at lag k = -K..K (index K + k; R_i[0] = 1);
+                             NULL when K = 0 */
 } lloid_bank_desc;
 
 /* A trigger: the SNR peak of one template in one window with |z| >= threshold,
  * with its sub-sample refinement (Sec. III.B: the interpolation at the SNR
- * peak that the paper's port leaves out). */
+ * peak that the paper's port leaves out) and its signal-consistency value
+ * (Sec. II.A: phase and xi^2 are computed for every trigger). */
 typedef struct {
   int32_t bank;          /* bank index in a batched call / stream slot; 0 for lloid_filter */
   int32_t detector;      /* as passed by the caller */
   int32_t template_id;   /* i */
-  int32_t reserved;
+  float xi2;             /* sum_k |z_i[n*+k] - z_i[n*] R_i[k]|^2 / sum_k (2 - 2 |R_i[k]|^2) over the lags
+                            k = -K..K with 0 <= n*+k < end of the data (1 on average in unit white
+                            noise, 0 for a signal matching the template); 0 when the bank has K = 0 */
   int64_t window;        /* w */
   int64_t sample;        /* peak sample n* */
   float snr;             /* |z_i[n*]| */
@@ -145,7 +153,7 @@ typedef enum {
   LLOID_STAGE_FIR = 2,       /* basis-filter correlation, all slices */
   LLOID_STAGE_INTERP = 3,    /* interpolation of low-rate orthogonal SNR to f0 */
   LLOID_STAGE_MIX = 4,       /* mixing GEMM + complex SNR + window peaks */
-  LLOID_STAGE_PHASE = 5,     /* phase of the complex SNR at each window peak */
+  LLOID_STAGE_PHASE = 5,     /* phase, sub-sample peak and xi^2 at each trigger peak */
   LLOID_STAGE_TRIGGER = 6,   /* trigger compaction */
   LLOID_STAGE_D2H = 7,       /* results to the caller's buffers */
   LLOID_N_STAGES = 8
@@ -163,10 +171,12 @@ lloid_status lloid_ctx_stage_times(lloid_ctx *ctx, double *ms, int64_t *calls, i
 
 /* Upload one SVD bank (Sec. II.A "SVD bank").  Validates every slice (EINVAL
  * on a rate that is not f0 / 2^k with k <= 7, a start tap that is not a multiple of
- * f0 / r_s, L_s > N_s, a NULL array), scales each slice's basis and the
- * mixing matrices by exact powers of two, converts them to the compute
- * type, lays them out for the kernels and computes sigma^2 in FP64.  The
- * descriptor and its arrays are not referenced after the call returns. */
+ * f0 / r_s, L_s > N_s, a NULL array, autocorr_half outside 0..512 or a NULL
+ * autocorr with K > 0, a non-finite autocorrelation value), scales each
+ * slice's basis and the mixing matrices by exact powers of two, converts them
+ * to the compute type, lays them out for the kernels, stores the
+ * autocorrelations in FP32 and computes sigma^2 in FP64.  The descriptor and
+ * its arrays are not referenced after the call returns. */
 lloid_status lloid_bank_create(lloid_ctx *ctx, const lloid_bank_desc *desc, lloid_bank **out);
 
 /* sigma2[i] = sum_s (1/D_s) sum_l (mixing_s[2i][l]^2 + mixing_s[2i+1][l]^2), the

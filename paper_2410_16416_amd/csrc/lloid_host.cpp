@@ -186,6 +186,7 @@ static void free_bank_device(lloid_bank *b) {
   for (auto &s : b->slices)
     if (s.basis) (void)hipFree(s.basis), s.basis = nullptr;
   if (b->mix) (void)hipFree(b->mix), b->mix = nullptr;
+  if (b->acorr) (void)hipFree(b->acorr), b->acorr = nullptr;
 }
 
 extern "C" lloid_status lloid_bank_destroy(lloid_bank *bank) {
@@ -222,6 +223,12 @@ extern "C" lloid_status lloid_bank_create(lloid_ctx *ctx, const lloid_bank_desc 
       return fail(LLOID_EINVAL, "slice %d: n_basis %d must be in [1, n_taps = %d]", s, sl.n_basis, sl.n_taps);
     if (!sl.basis || !sl.mixing) return fail(LLOID_EINVAL, "slice %d: NULL basis or mixing", s);
   }
+  const int K = d->autocorr_half;
+  if (K < 0 || K > kMaxAutocorrHalf)
+    return fail(LLOID_EINVAL, "autocorr_half %d is outside [0, %d]", K, kMaxAutocorrHalf);
+  if (K > 0 && !d->autocorr) return fail(LLOID_EINVAL, "NULL autocorr with autocorr_half %d", K);
+  for (int64_t q = 0; K > 0 && q < (int64_t)F * (2 * K + 1) * 2; ++q)
+    if (!std::isfinite(d->autocorr[q])) return fail(LLOID_EINVAL, "non-finite autocorrelation value");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
 
@@ -231,6 +238,7 @@ extern "C" lloid_status lloid_bank_create(lloid_ctx *ctx, const lloid_bank_desc 
   b->n_templates = F;
   b->compute = d->compute;
   b->rows = (int)round_up(2 * (int64_t)F, kMixBM);
+  b->acorr_half = K;
   const size_t esz = dtype_size(d->compute);
   int koff = 0, lsum = 0;
   double max_mix = 0.0;
@@ -312,6 +320,18 @@ extern "C" lloid_status lloid_bank_create(lloid_ctx *ctx, const lloid_bank_desc 
       launch_cast_f64(dtmp, b->compute, b->mix, (int64_t)host.size(), st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return cleanup(fail(LLOID_EDEVICE, "mixing upload failed"));
+
+  // autocorrelations as FP32 (re, im) pairs, [F][2K + 1]
+  if (K > 0) {
+    const size_t na = (size_t)F * (2 * K + 1) * 2;
+    std::vector<float> fa(na);
+    for (size_t q = 0; q < na; ++q) fa[q] = (float)d->autocorr[q];
+    if (hipMalloc(&b->acorr, na * sizeof(float)) != hipSuccess) return cleanup(fail(LLOID_ENOMEM, "autocorr alloc"));
+    b->device_bytes += (int64_t)(na * sizeof(float));
+    if (hipMemcpyAsync(b->acorr, fa.data(), na * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return cleanup(fail(LLOID_EDEVICE, "autocorr upload failed"));
+  }
 
   // sigma^2 in FP64 from the unscaled mixing matrices
   host.assign((size_t)2 * F * lsum + lsum, 0.0);
@@ -463,9 +483,11 @@ void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, 
                           int64_t wb, const Windows &win, const BankBufs &bb, float inv_scale, float *snr,
                           int64_t snr_ld, const TileShapes &ts, std::vector<FirJob> &fj, std::vector<UpJob> *uj,
                           std::vector<MixJob> &mj) {
-  // the operand holds one extra sample on each side, for the sub-sample
-  // refinement of peaks at the chunk's first and last samples
-  const int64_t e0 = t0 - 1, e1 = t1 + 1;
+  // the operand holds operand_margin(b) extra samples on each side: one for
+  // the sub-sample refinement of peaks at the chunk's first and last samples,
+  // K for the signal-consistency lags
+  const int64_t mg = operand_margin(b);
+  const int64_t e0 = t0 - mg, e1 = t1 + mg;
   const size_t lsz = low_esz(b->compute);
   const int ti = b->compute == LLOID_F16 ? 1 : 0;   // BF16 interpolates FP32 buffers
   for (size_t s = 0; s < b->slices.size(); ++s) {
@@ -539,6 +561,9 @@ void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, 
   m.peak_phase = bb.pphase;
   m.peak_dt = bb.pdt;
   m.peak_si = bb.psi;
+  m.peak_xi = bb.pxi;
+  m.acorr = b->acorr;
+  m.acorr_half = b->acorr_half;
   m.snr = snr;
   m.ocat_abs0 = e0;
   m.snr_abs0 = t0;
@@ -580,13 +605,15 @@ void lloid::number_jobs(std::vector<FirJob> &fj, std::vector<UpJob> *uj, std::ve
     it += m.nw >= 8 ? ceil_div(m.nw, 8) * 8 * m.n_rtiles : round_up(m.nw * m.n_rtiles, 8);
     m.e0 = e;
     e += (int64_t)m.n_templates * m.nw;
+    if (m.acorr) n.xi2 = true;
   }
   n.mix = it;
   n.entries = e;
 }
 
 lloid_status lloid::launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dtab, const TabOffsets &to,
-                                  const StageItems &n, bool with_snr, float phase_thr, hipEvent_t *ev) {
+                                  const StageItems &n, bool with_snr, float phase_thr, float trig_thr,
+                                  hipEvent_t *ev) {
   hipStream_t st = ctx->stream;
   auto mark = [&](int stage, int end) -> hipError_t {
     return ev ? hipEventRecord(ev[2 * (stage - LLOID_STAGE_FIR) + end], st) : hipSuccess;
@@ -603,6 +630,7 @@ lloid_status lloid::launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dt
   HIP_TRY(mark(LLOID_STAGE_MIX, 1));
   HIP_TRY(mark(LLOID_STAGE_PHASE, 0));
   HIP_TRY(launch_peak_phase(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.entries, phase_thr, st));
+  if (n.xi2) HIP_TRY(launch_xi2(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.entries, trig_thr, st));
   HIP_TRY(mark(LLOID_STAGE_PHASE, 1));
   return LLOID_OK;
 }
@@ -676,9 +704,10 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   wpc = std::min(wpc, W);
   // every buffer a kernel addresses through a buffer resource stays under 2 GiB
   for (int i = 0; i < nb; ++i)
-    while (wpc > 1 && !operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1) + 2)) wpc = (wpc + 1) / 2;
+    while (wpc > 1 && !operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1) + 2 * operand_margin(banks[i])))
+      wpc = (wpc + 1) / 2;
   for (int i = 0; i < nb; ++i)
-    if (!operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1) + 2))
+    if (!operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1) + 2 * operand_margin(banks[i])))
       return fail(LLOID_EINVAL, "one trigger window of bank %d needs buffers over 2 GiB", i);
   const int64_t n_chunks = ceil_div(W, wpc);
   const int64_t chunk_n = std::min<int64_t>(n, win.start(wpc) + 1);   // samples of the longest chunk
@@ -711,10 +740,12 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     add(tab, 4);
     add(tab, 4);
     add(tab, 4);
-    add((size_t)(chunk_n + 2) * banks[i]->kcat, esz);
+    add(tab, 4);
+    const int64_t ops = chunk_n + 2 * operand_margin(banks[i]);
+    add((size_t)ops * banks[i]->kcat, esz);
     for (const auto &sl : banks[i]->slices)
       if (sl.level > 0)
-        for (int64_t ld : low_ld(chunk_n + 2, sl.level)) add((size_t)sl.lp * ld, low_esz(ct));
+        for (int64_t ld : low_ld(ops, sl.level)) add((size_t)sl.lp * ld, low_esz(ct));
   }
   add((size_t)trig_blocks(total_rows * W) + 2, 8);
   add(1, 4);
@@ -743,14 +774,16 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     bw[i].pphase = cv.take<float>(tab);
     bw[i].pdt = cv.take<float>(tab);
     bw[i].psi = cv.take<float>(tab);
+    bw[i].pxi = cv.take<float>(tab);
     bw[i].ld_peak = W;
     bw[i].w_base = 0;
-    bw[i].ocat = cv.take<char>((size_t)(chunk_n + 2) * banks[i]->kcat * esz);
+    const int64_t ops = chunk_n + 2 * operand_margin(banks[i]);
+    bw[i].ocat = cv.take<char>((size_t)ops * banks[i]->kcat * esz);
     bw[i].low.assign(banks[i]->slices.size(), {});
     for (size_t s = 0; s < banks[i]->slices.size(); ++s) {
       const auto &sl = banks[i]->slices[s];
       if (sl.level > 0)
-        for (int64_t ld : low_ld(chunk_n + 2, sl.level))
+        for (int64_t ld : low_ld(ops, sl.level))
           bw[i].low[s].push_back(cv.take<char>((size_t)sl.lp * ld * low_esz(ct)));
     }
   }
@@ -801,8 +834,8 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   {
     int64_t e = 0;
     for (int i = 0; i < nb; ++i) {
-      tj[i] = TrigJob{bw[i].psnr, bw[i].pn, bw[i].pphase, bw[i].pdt, bw[i].psi, 0, W, e, banks[i]->n_templates,
-                      i, detector, 0};
+      tj[i] = TrigJob{bw[i].psnr, bw[i].pn, bw[i].pphase, bw[i].pdt, bw[i].psi,
+                      banks[i]->acorr ? bw[i].pxi : nullptr, 0, W, e, banks[i]->n_templates, i, detector, 0};
       e += (int64_t)banks[i]->n_templates * W;
     }
   }
@@ -837,7 +870,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     }
   for (int64_t c = 0; c < n_chunks; ++c) {
     const lloid_status r2 = launch_stages(ctx, ct, dtab, chunks[c].to, chunks[c].items, snr != nullptr, phase_thr,
-                                          ctx->profile ? &ctx->cev[(size_t)2 * kChunkStages * c] : nullptr);
+                                          thr, ctx->profile ? &ctx->cev[(size_t)2 * kChunkStages * c] : nullptr);
     if (r2 != LLOID_OK) return r2;
   }
   HIP_TRY(mark(LLOID_STAGE_TRIGGER, 0));

@@ -92,10 +92,12 @@ struct MixJob {
   int64_t *peak_n;
   float *peak_phase;
   float *peak_dt, *peak_si;   // sub-sample peak offset and value (triggers only)
+  float *peak_xi;             // signal-consistency value (triggers only; banks with lags)
+  const float *acorr;         // [n_templates][2 acorr_half + 1] (re, im) autocorrelation, or NULL
   float *snr;            // optional [F][snr_ld][2], column n - snr_abs0
   int64_t ocat_abs0, n_end, w0, nw, win_p, win_q, ld_peak, w_base, snr_ld, snr_abs0, item0, e0;
   float inv_scale;
-  int rows, kcat, n_templates, n_rtiles, pad;
+  int rows, kcat, n_templates, n_rtiles, acorr_half;
 };
 
 // Trigger compaction over the peak table of one bank, windows [w_base, w_base + nw):
@@ -105,6 +107,7 @@ struct TrigJob {
   const float *snr;
   const int64_t *peak_n;
   const float *phase, *dt, *si;
+  const float *xi;                 // NULL: the bank computes no signal-consistency value
   int64_t w_base, nw, elem0;
   int n_templates, bank_id, detector, pad;
 };
@@ -138,6 +141,8 @@ struct lloid_ctx {
 
 struct lloid_bank {
   lloid_ctx *ctx = nullptr;
+  int acorr_half = 0;       // K: lags of the signal-consistency value (0: none)
+  float *acorr = nullptr;   // [n_templates][2K + 1] (re, im)
   int f0 = 0, n_templates = 0, n_levels = 1;
   lloid_dtype compute = LLOID_F16;
   std::vector<lloid::SliceDev> slices;
@@ -169,6 +174,9 @@ hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_
                            hipStream_t s);
 hipError_t launch_peak_phase(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float phase_thr,
                              hipStream_t s);
+// Signal-consistency value at the peaks with |z| >= thr of the jobs that carry
+// autocorrelations.
+hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float thr, hipStream_t s);
 // Trigger compaction: counts, offsets and records (job-major, template, window);
 // counts holds trig_blocks(n_elems) slots.
 hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems, float thr, int64_t *counts,
@@ -246,7 +254,7 @@ struct BankBufs {
   void *ocat = nullptr;            // [chunk samples][kcat]
   std::vector<std::vector<void *>> low;  // per slice at level > 0: FIR output, then each
                                          // interpolation hop's output except the last
-  float *psnr = nullptr, *pphase = nullptr, *pdt = nullptr, *psi = nullptr;
+  float *psnr = nullptr, *pphase = nullptr, *pdt = nullptr, *psi = nullptr, *pxi = nullptr;
   int64_t *pn = nullptr;
   int64_t ld_peak = 0, w_base = 0; // peak tables [F][ld_peak], column w - w_base
 };
@@ -260,10 +268,12 @@ struct TileShapes {
 };
 
 constexpr int kMaxLevel = 7;       // lowest slice rate f0 / 128
+constexpr int kMaxAutocorrHalf = 512;
 constexpr int kMaxHops = 4;        // interpolation hops of a level-7 slice: x2, x4, x4, x4
 
 struct StageItems {
   int64_t fir = 0, mix = 0, entries = 0;
+  bool xi2 = false;                // some mixing job carries autocorrelations
   int64_t up[kMaxHops] = {};       // items of each interpolation hop
 };
 
@@ -308,7 +318,11 @@ void number_jobs(std::vector<FirJob> &fj, std::vector<UpJob> *uj, std::vector<Mi
 // NULL, or 8 events bracketing those four stages.
 constexpr int kChunkStages = 4;    // LLOID_STAGE_FIR .. LLOID_STAGE_PHASE
 lloid_status launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dtab, const TabOffsets &to,
-                           const StageItems &n, bool with_snr, float phase_thr, hipEvent_t *ev);
+                           const StageItems &n, bool with_snr, float phase_thr, float trig_thr, hipEvent_t *ev);
+
+// Samples of the mixing operand beyond each end of a chunk's outputs: one for
+// the sub-sample refinement, K for the signal-consistency lags.
+inline int64_t operand_margin(const lloid_bank *b) { return std::max(1, b->acorr_half); }
 
 }  // namespace lloid
 

@@ -666,6 +666,100 @@ __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ j
   jb.peak_si[o] = v;
 }
 
+// Signal-consistency value at each trigger peak (Sec. II.A computes phase and
+// xi^2 for every trigger):
+//   xi2 = sum_k |z[n* + k] - z[n*] R[k]|^2 / sum_k (2 - 2 |R[k]|^2)
+// over the lags k = -K..K with 0 <= n* + k < n_end, z recomputed like the
+// phase (mixing rows 2i, 2i+1 against operand rows; a chunk's operand holds K
+// extra samples on each side).  A wave takes 64 consecutive (template,
+// window) entries; those at or above the threshold in jobs with
+// autocorrelations are then handled one at a time by the whole wave: first
+// z[n*] over all 64 lanes, then 8 teams of 8 lanes, one lag per team and
+// pass, each team's lanes splitting K into 16-byte reads and reducing by
+// shuffles.
+template <typename T>
+__device__ __forceinline__ float2 z_team(const uint4 *__restrict__ mc, const uint4 *__restrict__ ms,
+                                         const uint4 *__restrict__ row, int nvec, int sub, int stride) {
+  float re = 0.f, im = 0.f;
+  for (int k = sub; k < nvec; k += stride) {
+    const Vec16<T> c = __builtin_bit_cast(Vec16<T>, mc[k]);
+    const Vec16<T> d = __builtin_bit_cast(Vec16<T>, ms[k]);
+    const Vec16<T> a = __builtin_bit_cast(Vec16<T>, row[k]);
+#pragma unroll
+    for (int j = 0; j < (int)(16 / sizeof(T)); ++j) {
+      const float ov = Op<T>::tof(a.v[j]);
+      re += Op<T>::tof(c.v[j]) * ov;
+      im += Op<T>::tof(d.v[j]) * ov;
+    }
+  }
+  for (int off = 1; off < stride; off <<= 1) {
+    re += __shfl_xor(re, off);
+    im += __shfl_xor(im, off);
+  }
+  return make_float2(re, im);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_xi2(const MixJob *__restrict__ jobs, int n_jobs, int64_t entries,
+                                             float thr) {
+  constexpr int TEAM = 8, EPV = 16 / (int)sizeof(T);
+  const int lane = threadIdx.x & 63, team = lane / TEAM, sub = lane % TEAM;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int j = 0;
+  int64_t o = 0, i = 0;
+  bool f = false;
+  if (e < entries) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].e0 <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    j = lo;
+    const MixJob &jb = jobs[j];
+    const int64_t le = e - jb.e0;
+    i = le / jb.nw;
+    o = i * jb.ld_peak + (jb.w0 + le - i * jb.nw - jb.w_base);
+    f = jb.acorr != nullptr && jb.peak_snr[o] >= thr;
+  }
+  uint64_t pending = __ballot(f);
+  while (pending) {
+    const int src = __builtin_ctzll(pending);
+    pending &= pending - 1;
+    const int jj = __shfl(j, src);
+    const int64_t oo = __shfl(o, src), ii = __shfl(i, src);
+    const MixJob &jb = jobs[jj];
+    const int K = jb.acorr_half, kcat = jb.kcat, nvec = kcat / EPV;
+    const int64_t ns = jb.peak_n[oo];
+    const uint4 *mc = (const uint4 *)((const T *)jb.mix + (2 * ii) * (int64_t)kcat);
+    const uint4 *ms = mc + nvec;
+    const uint4 *base = (const uint4 *)((const T *)jb.ocat + (ns - jb.ocat_abs0) * (int64_t)kcat);
+    const float2 *R = (const float2 *)jb.acorr + ii * (2 * K + 1);
+    const float sc = jb.inv_scale;
+    float2 zs = z_team<T>(mc, ms, base, nvec, lane, 64);
+    zs.x *= sc;
+    zs.y *= sc;
+    float num = 0.f, den = 0.f;
+    for (int kk = team; kk < 2 * K + 1; kk += 64 / TEAM) {
+      const int64_t n = ns + kk - K;
+      if (n < 0 || n >= jb.n_end) continue;   // uniform within a team
+      const float2 z = z_team<T>(mc, ms, base + (int64_t)(kk - K) * nvec, nvec, sub, TEAM);
+      const float2 r = R[kk];
+      const float dr = z.x * sc - (zs.x * r.x - zs.y * r.y);
+      const float di = z.y * sc - (zs.x * r.y + zs.y * r.x);
+      if (sub == 0) {
+        num += dr * dr + di * di;
+        den += 2.f - 2.f * (r.x * r.x + r.y * r.y);
+      }
+    }
+    for (int off = 1; off < 64; off <<= 1) {
+      num += __shfl_xor(num, off);
+      den += __shfl_xor(den, off);
+    }
+    if (lane == src) jb.peak_xi[oo] = den > 0.f ? num / den : 0.f;
+  }
+}
+
 // ---------------------------------------------------------- trigger compaction
 // Stream compaction over the flat (job, template, window) order of every peak
 // table: per-block flag counts, an exclusive scan of the block counts, then a
@@ -786,7 +880,7 @@ __global__ __launch_bounds__(kTrigThreads) void k_trigger_write(const TrigJob *_
       t.bank = jb.bank_id;
       t.detector = jb.detector;
       t.template_id = (int32_t)(o / jb.nw);
-      t.reserved = 0;
+      t.xi2 = jb.xi ? jb.xi[o] : 0.f;
       t.window = jb.w_base + o % jb.nw;
       t.sample = jb.peak_n[o];
       t.snr = jb.snr[o];
@@ -936,6 +1030,18 @@ hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems,
   k_trigger_scan<<<1, 1024, 0, s>>>(counts, nblk, total);
   if (nblk > 0)
     k_trigger_write<<<(unsigned)nblk, kTrigThreads, 0, s>>>(jobs, n_jobs, n_elems, thr, counts, cap, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float thr, hipStream_t s) {
+  if (n_entries <= 0) return hipSuccess;
+  const unsigned blocks = blocks_for(n_entries, 256);   // one entry per thread
+  switch (t) {
+    case LLOID_F16: k_xi2<_Float16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, thr); break;
+    case LLOID_BF16: k_xi2<__bf16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, thr); break;
+    case LLOID_F32: k_xi2<float><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, thr); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -79,14 +79,18 @@ namespace {
 
 int64_t tick_samples(const lloid_stream *s) { return s->max_w * s->win_len + 1; }
 
+// Samples at level k that a tick's operand margins (up to kMaxAutocorrHalf
+// on each side) reach beyond the tick and the filter span.
+int64_t margin_at(int k) { return ((2 * (int64_t)kMaxAutocorrHalf + 2) >> k) + 1; }
+
 // device bytes one active bank needs beyond its own arrays: per-tick scratch of every detector
 int64_t scratch_bytes(const lloid_stream *s, const lloid_bank *b) {
-  const int64_t ts = tick_samples(s) + 2;
+  const int64_t ts = tick_samples(s) + 2 * operand_margin(b);
   int64_t per = (int64_t)ts * b->kcat * (int64_t)dtype_size(b->compute);
   for (const auto &sl : b->slices)
     if (sl.level > 0)
       for (int64_t ld : low_ld(ts, sl.level)) per += (int64_t)sl.lp * ld * (int64_t)low_esz(b->compute) + 256;
-  per += (int64_t)b->n_templates * s->max_w * (24 + (int64_t)sizeof(lloid_trigger)) + 4096;
+  per += (int64_t)b->n_templates * s->max_w * (28 + (int64_t)sizeof(lloid_trigger)) + 4096;
   return per * s->n_det;
 }
 
@@ -96,7 +100,8 @@ lloid_status check_bank(const lloid_stream *s, const lloid_bank *b) {
   if (b->f0 != s->f0) return fail(LLOID_EINVAL, "the bank's full rate differs from the stream's");
   if (b->compute != s->ct) return fail(LLOID_EINVAL, "the bank's compute type differs from the stream's");
   if (b->n_levels > s->n_levels) return fail(LLOID_EINVAL, "the bank's lowest rate is below the stream's");
-  if (!operands_fit(b, tick_samples(s) + 2)) return fail(LLOID_EINVAL, "the bank's per-tick buffers exceed 2 GiB");
+  if (!operands_fit(b, tick_samples(s) + 2 * operand_margin(b)))
+    return fail(LLOID_EINVAL, "the bank's per-tick buffers exceed 2 GiB");
   for (const auto &sl : b->slices) {
     const int64_t span = sl.start_tap / sl.dec + sl.n_taps + 4 * kHalfQ;
     if (span > s->hist[sl.level]) return fail(LLOID_EINVAL, "a slice spans more than the stream's history");
@@ -119,7 +124,8 @@ void admit_queued(lloid_stream *s) {
 lloid_status make_room(lloid_stream *s, DetState &d, int k, int64_t add) {
   const int64_t end = d.avail[k] + add;
   if (end - d.lo[k] <= s->cap[k]) return LLOID_OK;
-  const int64_t keep_from = d.avail[k] - s->hist[k] - tick_samples(s) / (int64_t(1) << k) - 4 * kHalfQ;
+  const int64_t keep_from =
+      d.avail[k] - s->hist[k] - tick_samples(s) / (int64_t(1) << k) - 4 * kHalfQ - margin_at(k);
   const int64_t shift = keep_from - d.lo[k];
   const int64_t keep = d.avail[k] - keep_from;
   if (shift < keep || end - keep_from > s->cap[k])
@@ -162,9 +168,11 @@ int64_t ready_until(const lloid_stream *s) {
     bool ok = true;
     for (const auto &sl : s->slots) {
       if (!sl.active || !ok) continue;
+      const int64_t mg = operand_margin(sl.bank);
       for (const auto &sd : sl.bank->slices) {
-        // outputs [t0 - 1, t1 + 1): the peaks' sub-sample refinement reads one sample past t1
-        const Range r = need_ranges(t0 - 1, t1 + 1, sd.level + 1)[sd.level];
+        // outputs [t0 - mg, t1 + mg): the peaks' sub-sample refinement and
+        // signal-consistency lags read up to mg samples past t1
+        const Range r = need_ranges(t0 - mg, t1 + mg, sd.level + 1)[sd.level];
         for (const auto &d : s->det)
           if (r.hi - sd.start_tap / sd.dec > d.avail[sd.level]) ok = false;
       }
@@ -202,12 +210,14 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
   for (int i : act) {
     const lloid_bank *b = s->slots[i].bank;
     for (int d = 0; d < s->n_det; ++d) {
-      add((size_t)(tlen + 2) * b->kcat, esz);
+      const int64_t ops = tlen + 2 * operand_margin(b);
+      add((size_t)ops * b->kcat, esz);
       for (const auto &sl : b->slices) {
         ++n_fir;
         if (sl.level > 0)
-          for (int64_t ld : low_ld(tlen + 2, sl.level)) add((size_t)sl.lp * ld, low_esz(s->ct)), ++n_up;
+          for (int64_t ld : low_ld(ops, sl.level)) add((size_t)sl.lp * ld, low_esz(s->ct)), ++n_up;
       }
+      add((size_t)b->n_templates * nw, 4);
       add((size_t)b->n_templates * nw, 4);
       add((size_t)b->n_templates * nw, 8);
       add((size_t)b->n_templates * nw, 4);
@@ -235,17 +245,19 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
     const lloid_bank *b = s->slots[i].bank;
     for (int d = 0; d < s->n_det; ++d) {
       BankBufs bb;
-      bb.ocat = cv.take<char>((size_t)(tlen + 2) * b->kcat * esz);
+      const int64_t ops = tlen + 2 * operand_margin(b);
+      bb.ocat = cv.take<char>((size_t)ops * b->kcat * esz);
       bb.low.assign(b->slices.size(), {});
       for (size_t k = 0; k < b->slices.size(); ++k)
         if (b->slices[k].level > 0)
-          for (int64_t ld : low_ld(tlen + 2, b->slices[k].level))
+          for (int64_t ld : low_ld(ops, b->slices[k].level))
             bb.low[k].push_back(cv.take<char>((size_t)b->slices[k].lp * ld * low_esz(s->ct)));
       bb.psnr = cv.take<float>((size_t)b->n_templates * nw);
       bb.pn = cv.take<int64_t>((size_t)b->n_templates * nw);
       bb.pphase = cv.take<float>((size_t)b->n_templates * nw);
       bb.pdt = cv.take<float>((size_t)b->n_templates * nw);
       bb.psi = cv.take<float>((size_t)b->n_templates * nw);
+      bb.pxi = cv.take<float>((size_t)b->n_templates * nw);
       bb.ld_peak = nw;
       bb.w_base = wa;
       std::vector<LevelView> lv(s->n_levels);
@@ -253,8 +265,8 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
       for (int k = 0; k < s->n_levels; ++k) lv[k] = LevelView{ds.x[k], ds.lo[k], ds.avail[k] - ds.lo[k]};
       add_bank_jobs(b, lv.data(), t0, t1, n_end, wa, wb, s->win, bb, 1.f / (b->mix_scale * s->sscale), nullptr, 0, ts,
                     fj, uj, mj);
-      tj.push_back(TrigJob{bb.psnr, bb.pn, bb.pphase, bb.pdt, bb.psi, wa, nw, row * nw, b->n_templates,
-                           s->slots[i].id, d, 0});
+      tj.push_back(TrigJob{bb.psnr, bb.pn, bb.pphase, bb.pdt, bb.psi, b->acorr ? bb.pxi : nullptr, wa, nw, row * nw,
+                           b->n_templates, s->slots[i].id, d, 0});
       row += b->n_templates;
     }
   }
@@ -289,7 +301,7 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
   // two small results into pinned host memory
   auto enqueue = [&]() -> lloid_status {
     HIP_TRY(hipMemcpyAsync(dtab, htab, off, hipMemcpyHostToDevice, st));
-    const lloid_status r = launch_stages(ctx, s->ct, dtab, to, items, false, s->thr, nullptr);
+    const lloid_status r = launch_stages(ctx, s->ct, dtab, to, items, false, s->thr, s->thr, nullptr);
     if (r != LLOID_OK) return r;
     HIP_TRY(launch_trigger_jobs((const TrigJob *)(dtab + trig_off), (int)tj.size(), rows * nw, s->thr, counts, total,
                                 cap, dtrig, st));
@@ -302,6 +314,7 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
                                 (int64_t)tj.size(), rows, cap, (int64_t)(uintptr_t)counts, (int64_t)(uintptr_t)dtrig,
                                 items.fir, items.mix, items.entries, (int64_t)to.fir, (int64_t)to.mix, to.n_fir,
                                 to.n_mix};
+    key.push_back(items.xi2 ? 1 : 0);
     for (int h = 0; h < kMaxHops; ++h) {
       key.push_back(items.up[h]);
       key.push_back((int64_t)to.up[h]);
@@ -437,7 +450,7 @@ extern "C" lloid_status lloid_stream_create(lloid_ctx *ctx, int32_t full_rate_hz
   for (int k = 0; k < L; ++k) {
     const int64_t rate = full_rate_hz >> k;
     s->hist[k] = (int64_t)std::ceil(span_s * rate) + 8 * kHalfQ;
-    const int64_t tick_k = tick_samples(s) / (int64_t(1) << k) + 8 * kHalfQ;
+    const int64_t tick_k = tick_samples(s) / (int64_t(1) << k) + 8 * kHalfQ + margin_at(k);
     const int64_t push_k = s->push_max / (int64_t(1) << k) + 8 * kHalfQ;
     s->cap[k] = 2 * (s->hist[k] + tick_k) + push_k;
     total += (size_t)s->cap[k];
@@ -462,7 +475,7 @@ extern "C" lloid_status lloid_stream_create(lloid_ctx *ctx, int32_t full_rate_hz
       p += s->cap[k];
       if (k > 0) sup_lo = ceil_div(sup_lo - kHalfQ, 2);
       // before its support a level is exactly zero: the history starts as zeros
-      d.lo[k] = sup_lo - s->hist[k] - 8 * kHalfQ;
+      d.lo[k] = sup_lo - s->hist[k] - 8 * kHalfQ - margin_at(k);
       d.avail[k] = sup_lo;
     }
   }

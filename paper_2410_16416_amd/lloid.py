@@ -43,7 +43,9 @@ class lloid_slice(ctypes.Structure):
 class lloid_bank_desc(ctypes.Structure):
     _fields_ = [("full_rate_hz", ctypes.c_int32), ("n_templates", ctypes.c_int32),
                 ("n_slices", ctypes.c_int32), ("compute", ctypes.c_int32),
-                ("slices", ctypes.POINTER(lloid_slice))]
+                ("slices", ctypes.POINTER(lloid_slice)),
+                ("autocorr_half", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("autocorr", ctypes.POINTER(ctypes.c_double))]
 
 
 class lloid_bank_info(ctypes.Structure):
@@ -80,7 +82,7 @@ class lloid_stream_stats(ctypes.Structure):
 
 
 TRIGGER_DTYPE = np.dtype([("bank", np.int32), ("detector", np.int32), ("template_id", np.int32),
-                          ("reserved", np.int32), ("window", np.int64), ("sample", np.int64),
+                          ("xi2", np.float32), ("window", np.int64), ("sample", np.int64),
                           ("snr", np.float32), ("phase", np.float32),
                           ("snr_interp", np.float32), ("dt", np.float32)])
 assert TRIGGER_DTYPE.itemsize == 48
@@ -185,8 +187,11 @@ def lloid_ctx_set_chunk_bytes(ctx, nbytes: int):
     _check(_lib.lloid_ctx_set_chunk_bytes(ctx, int(nbytes)))
 
 
-def lloid_bank_create(ctx, full_rate_hz: int, n_templates: int, slices, compute: str = "f16"):
-    """slices: objects with rate, start_tap, n_taps, basis [L, N], mixing [2F, L] (float64)."""
+def lloid_bank_create(ctx, full_rate_hz: int, n_templates: int, slices, compute: str = "f16",
+                      autocorr=None):
+    """slices: objects with rate, start_tap, n_taps, basis [L, N], mixing [2F, L] (float64).
+    autocorr: None, or complex [F, 2K + 1] normalised template autocorrelations
+    (column K + k for lag k), the input of each trigger's xi2."""
     keep = []
     arr = (lloid_slice * len(slices))()
     for k, s in enumerate(slices):
@@ -200,6 +205,14 @@ def lloid_bank_create(ctx, full_rate_hz: int, n_templates: int, slices, compute:
         arr[k].basis = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         arr[k].mixing = m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     desc = lloid_bank_desc(int(full_rate_hz), int(n_templates), len(slices), DTYPES[compute], arr)
+    if autocorr is not None:
+        ac = np.asarray(autocorr)
+        if ac.ndim != 2 or ac.shape[0] != int(n_templates) or ac.shape[1] % 2 != 1:
+            raise ValueError("autocorr must be [n_templates, 2K + 1]")
+        pairs = np.ascontiguousarray(np.stack([ac.real, ac.imag], axis=-1), dtype=np.float64)
+        keep.append(pairs)
+        desc.autocorr_half = (ac.shape[1] - 1) // 2
+        desc.autocorr = pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     out = ctypes.c_void_p()
     _check(_lib.lloid_bank_create(ctx, ctypes.byref(desc), ctypes.byref(out)))
     return out
@@ -349,8 +362,10 @@ def lloid_filter_batch(banks, detector: int, strain, window=(1, 1), threshold: f
 
 
 def bank_from_svd(ctx, svd_bank, compute: str = "f16"):
-    """Upload an SVD bank object (attributes f0, n_templates, slices)."""
-    return lloid_bank_create(ctx, svd_bank.f0, svd_bank.n_templates, svd_bank.slices, compute)
+    """Upload an SVD bank object (attributes f0, n_templates, slices and,
+    optionally, autocorr)."""
+    return lloid_bank_create(ctx, svd_bank.f0, svd_bank.n_templates, svd_bank.slices, compute,
+                             autocorr=getattr(svd_bank, "autocorr", None))
 
 
 # ------------------------------------------------------------------ streaming

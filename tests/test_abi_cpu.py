@@ -60,8 +60,9 @@ int main(void) {
   P(lloid_stream_stats, bytes_in_use) P(lloid_stream_stats, graph_replays)
   P(lloid_slice, start_tap) P(lloid_slice, basis) P(lloid_slice, mixing)
   P(lloid_trigger, window) P(lloid_trigger, sample) P(lloid_trigger, snr) P(lloid_trigger, phase)
-  P(lloid_trigger, snr_interp) P(lloid_trigger, dt)
-  P(lloid_bank_desc, slices) P(lloid_bank_info, device_bytes)
+  P(lloid_trigger, snr_interp) P(lloid_trigger, dt) P(lloid_trigger, xi2)
+  P(lloid_bank_desc, slices) P(lloid_bank_desc, autocorr_half) P(lloid_bank_desc, autocorr)
+  P(lloid_bank_info, device_bytes)
   return 0;
 }
 """)
@@ -76,11 +77,12 @@ int main(void) {
     for name, cls in mirror.items():
         assert int(got[name]) == ctypes.sizeof(cls), name
     assert int(got["lloid_trigger"]) == lloid.TRIGGER_DTYPE.itemsize
-    for f in ("window", "sample", "snr", "phase", "snr_interp", "dt"):
+    for f in ("xi2", "window", "sample", "snr", "phase", "snr_interp", "dt"):
         assert int(got[f"lloid_trigger.{f}"]) == lloid.TRIGGER_DTYPE.fields[f][1]
     for f in ("start_tap", "basis", "mixing"):
         assert int(got[f"lloid_slice.{f}"]) == getattr(lloid.lloid_slice, f).offset
-    assert int(got["lloid_bank_desc.slices"]) == lloid.lloid_bank_desc.slices.offset
+    for f in ("slices", "autocorr_half", "autocorr"):
+        assert int(got[f"lloid_bank_desc.{f}"]) == getattr(lloid.lloid_bank_desc, f).offset, f
     assert int(got["lloid_bank_info.device_bytes"]) == lloid.lloid_bank_info.device_bytes.offset
     for f in ("use_graph", "hbm_budget", "trig"):
         assert int(got[f"lloid_stream_opts.{f}"]) == getattr(lloid.lloid_stream_opts, f).offset, f

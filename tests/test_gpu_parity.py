@@ -249,6 +249,63 @@ def test_c1_full_size_sampled_windows(compute):
         lloid.lloid_bank_destroy(b)
 
 
+XI_HALF = 20
+
+
+@pytest.mark.parametrize("compute", PRECISIONS)
+def test_xi2_matches_oracle(compute):
+    """Every trigger's signal-consistency value equals the oracle's xi2 from the
+    oracle's z at the trigger's peak sample (where that sample agrees with the
+    oracle's, i.e. outside near ties).  Bound: with |dz| <= eps on every lag
+    (eps the stated complex-SNR tolerance), d_k = z_k - z* R_k moves by at most
+    2 eps, so the numerator moves by at most 4 eps sum|d_k| + 4 eps^2 n_lags;
+    divided by the denominator.  Chunking (a few windows per chunk, so lags
+    cross chunk edges) gives bit-identical records; lags before sample 0 and
+    past the data end drop out as in the oracle."""
+    from paper_2410_16416_amd import lloid
+    from workloads import bank_autocorrelation
+    log(f"[xi2] compute={compute}")
+    wl, x, z, _, _, _ = mini_case()
+    n = x.shape[0]
+    r = bank_autocorrelation(wl.bank, XI_HALF)
+    wl.bank.autocorr = r
+    b = lloid.bank_from_svd(ctx(), wl.bank, compute)
+    try:
+        res = lloid.lloid_filter(b, 0, x, window=(1, 4), threshold=3.0)
+        lloid.lloid_ctx_set_chunk_bytes(ctx(), 400000)
+        try:
+            chunked = lloid.lloid_filter(b, 0, x, window=(1, 4), threshold=3.0)
+        finally:
+            lloid.lloid_ctx_set_chunk_bytes(ctx(), 6 << 30)
+    finally:
+        lloid.lloid_bank_destroy(b)
+        wl.bank.autocorr = None
+    t = res.triggers
+    assert t.shape[0] > 20
+    assert np.array_equal(t, chunked.triggers)
+    eps = EPS_ABS[compute]
+    a = np.abs(z)
+    wins = t["window"].astype(np.int64)
+    starts = oracle.window_starts(int(wins.max()) + 2, 1024, 1, 4)
+    lag = np.arange(-XI_HALF, XI_HALF + 1)
+    n_cmp, worst = 0, 0.0
+    for rec in t:
+        i, s, w = int(rec["template_id"]), int(rec["sample"]), int(rec["window"])
+        if a[i, starts[w]:min(starts[w + 1], n)].argmax() + starts[w] != s:
+            continue
+        want = oracle.xi2(z[i], 0, n, s, r[i])
+        ok = (s + lag >= 0) & (s + lag < n)
+        d = z[i, (s + lag)[ok]] - z[i, s] * r[i, ok]
+        den = np.sum(2.0 - 2.0 * np.abs(r[i, ok]) ** 2)
+        tol = (4 * eps * np.sum(np.abs(d)) + 4 * eps ** 2 * ok.sum()) / den + 1e-5 * want
+        assert abs(float(rec["xi2"]) - want) <= tol, (i, s, float(rec["xi2"]), want, tol)
+        worst = max(worst, abs(float(rec["xi2"]) - want))
+        n_cmp += 1
+    assert n_cmp > 0.8 * t.shape[0]
+    assert np.all(t["xi2"] >= 0)
+    log(f"  {t.shape[0]} triggers, {n_cmp} compared, max |d xi2| {worst:.2e}")
+
+
 @pytest.mark.parametrize("compute", PRECISIONS)
 def test_subsample_peaks_match_oracle(compute):
     """Every trigger's sub-sample refinement equals the oracle's parabola through

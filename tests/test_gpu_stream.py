@@ -5,7 +5,7 @@ call gives for the whole stream, alone or in the mix."""
 import numpy as np
 import pytest
 
-from workloads import configs
+from workloads import bank_autocorrelation, configs
 
 from gpu_util import ctx, log
 
@@ -54,6 +54,7 @@ def test_stream_equals_offline(sizes, use_graph):
     a tick's shape changes); every replay must give the offline result."""
     from paper_2410_16416_amd import lloid
     wl = configs.mini_multirate(seconds=12, detectors=2, n_injections=2)
+    wl.bank.autocorr = bank_autocorrelation(wl.bank, 20)   # xi2 lags reach across ticks
     h = lloid.bank_from_svd(ctx(), wl.bank, "f16")
     s = lloid.lloid_stream_create(ctx(), 1024, "f16", n_detectors=2, min_rate_hz=64, window=(1, 4),
                                   max_filter_s=8.0, use_graph=use_graph)
