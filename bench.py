@@ -12,8 +12,10 @@ resident in HBM to triggers in pinned host memory, through the C ABI.
 
 Prints one JSON line: whole-job template-samples of SNR per second, the
 roofline of the dominant kernel (device time from HIP events on the
-library's stream over the timed steps), the plain FP32 path beside it, and
-the FP64 oracle timed on the host cores on a bounded sample.
+library's stream over the timed steps), the plain FP32 path beside it, the
+same path with every trigger's xi2 signal-consistency value (bank
+autocorrelations over 2K + 1 lags), and the FP64 oracle timed on the host
+cores on a bounded sample.
 """
 
 from __future__ import annotations
@@ -326,6 +328,9 @@ def main():
     ap.add_argument("--rates", default="", help="serving_c4: also sweep these rates (e.g. 1,4,16,64), "
                                                 "min(1000, 60 x rate) strides each, operand type only")
     ap.add_argument("--strides", type=int, default=120, help="serving_c4: timed 1 s strides")
+    ap.add_argument("--xi2-half", type=int, default=175,
+                    help="multirate_c1: lags K on each side of the signal-consistency path (2K + 1 samples)")
+    ap.add_argument("--xi2-steps", type=int, default=3, help="timed steps of the path with xi2 (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -405,6 +410,18 @@ def main():
         out["f32_path"] = {"value": round(v32, 1), "ms_per_step": round(w32 / args.f32_steps * 1e3, 3),
                            "speedup_of_headline": round(value / v32, 2),
                            "roofline_mix": roofline_entry("mfma", work["mix"][1], ms / max(calls, 1), "f32")}
+    if args.xi2_steps and args.xi2_half > 0:
+        from workloads import bank_autocorrelation
+        log(f"[bench] {args.compute} with xi2 over {2 * args.xi2_half + 1} lags: steps {args.xi2_steps}")
+        wl.bank.autocorr = bank_autocorrelation(wl.bank, args.xi2_half)
+        try:
+            wx, ntx, stx = run_path(lloid, ctx, wl, xs, args.compute, args.xi2_steps, 1, tbufs)
+        finally:
+            wl.bank.autocorr = None
+        out["xi2_path"] = {"lags": 2 * args.xi2_half + 1, "value": round(samples_per_step / (wx / args.xi2_steps), 1),
+                           "ms_per_step": round(wx / args.xi2_steps * 1e3, 3),
+                           "phase_stage_ms_per_step": round(stx["phase"][0] / args.xi2_steps, 3),
+                           "triggers_per_step": int(ntx)}
     if args.copy_calibration_mib:
         nbytes = args.copy_calibration_mib << 20
         a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")

@@ -671,26 +671,50 @@ __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ j
 //   xi2 = sum_k |z[n* + k] - z[n*] R[k]|^2 / sum_k (2 - 2 |R[k]|^2)
 // over the lags k = -K..K with 0 <= n* + k < n_end, z recomputed like the
 // phase (mixing rows 2i, 2i+1 against operand rows; a chunk's operand holds K
-// extra samples on each side).  A wave takes 64 consecutive (template,
-// window) entries; those at or above the threshold in jobs with
-// autocorrelations are then handled one at a time by the whole wave: first
+// extra samples on each side).  A wave takes kXiPerWave consecutive entries
+// (few, so that the triggers, about one in eight entries, spread evenly over
+// the waves); those at or above the threshold in jobs with autocorrelations
+// are then handled one at a time by the whole wave: first
 // z[n*] over all 64 lanes, then 8 teams of 8 lanes, one lag per team and
 // pass, each team's lanes splitting K into 16-byte reads and reducing by
 // shuffles.
+constexpr int kXiPerWave = 8, kXiPerBlock = 4 * kXiPerWave;
+
+// acc + the dot product of two 16-byte vectors of T, FP32 accumulation: packed
+// two-element dot instructions for the 16-bit types (their products are exact
+// in FP32), FMAs for FP32.
+template <typename T> __device__ __forceinline__ float dot16(uint4 x, uint4 y, float acc);
+template <> __device__ __forceinline__ float dot16<_Float16>(uint4 x, uint4 y, float acc) {
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  const unsigned xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2, xs[q]), __builtin_bit_cast(h2, ys[q]), acc, false);
+  return acc;
+}
+template <> __device__ __forceinline__ float dot16<__bf16>(uint4 x, uint4 y, float acc) {
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+  const unsigned xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(b2, xs[q]), __builtin_bit_cast(b2, ys[q]), acc, false);
+  return acc;
+}
+template <> __device__ __forceinline__ float dot16<float>(uint4 x, uint4 y, float acc) {
+  acc = fmaf(__uint_as_float(x.x), __uint_as_float(y.x), acc);
+  acc = fmaf(__uint_as_float(x.y), __uint_as_float(y.y), acc);
+  acc = fmaf(__uint_as_float(x.z), __uint_as_float(y.z), acc);
+  return fmaf(__uint_as_float(x.w), __uint_as_float(y.w), acc);
+}
+
 template <typename T>
 __device__ __forceinline__ float2 z_team(const uint4 *__restrict__ mc, const uint4 *__restrict__ ms,
                                          const uint4 *__restrict__ row, int nvec, int sub, int stride) {
   float re = 0.f, im = 0.f;
   for (int k = sub; k < nvec; k += stride) {
-    const Vec16<T> c = __builtin_bit_cast(Vec16<T>, mc[k]);
-    const Vec16<T> d = __builtin_bit_cast(Vec16<T>, ms[k]);
-    const Vec16<T> a = __builtin_bit_cast(Vec16<T>, row[k]);
-#pragma unroll
-    for (int j = 0; j < (int)(16 / sizeof(T)); ++j) {
-      const float ov = Op<T>::tof(a.v[j]);
-      re += Op<T>::tof(c.v[j]) * ov;
-      im += Op<T>::tof(d.v[j]) * ov;
-    }
+    const uint4 a = row[k];
+    re = dot16<T>(mc[k], a, re);
+    im = dot16<T>(ms[k], a, im);
   }
   for (int off = 1; off < stride; off <<= 1) {
     re += __shfl_xor(re, off);
@@ -704,11 +728,17 @@ __global__ __launch_bounds__(256) void k_xi2(const MixJob *__restrict__ jobs, in
                                              float thr) {
   constexpr int TEAM = 8, EPV = 16 / (int)sizeof(T);
   const int lane = threadIdx.x & 63, team = lane / TEAM, sub = lane % TEAM;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  // XCD-contiguous blocks: XCD x (= blockIdx % 8) takes one run of blocks,
+  // so a window's triggers (window-major entries) share that XCD's L2
+  const int64_t n_blk = (entries + kXiPerBlock - 1) / kXiPerBlock;
+  const int64_t per_xcd = (n_blk + 7) / 8;
+  const int64_t lb = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (lb >= n_blk) return;
+  const int64_t e = lb * kXiPerBlock + (threadIdx.x >> 6) * kXiPerWave + lane;
   int j = 0;
   int64_t o = 0, i = 0;
   bool f = false;
-  if (e < entries) {
+  if (lane < kXiPerWave && e < entries) {
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -717,9 +747,11 @@ __global__ __launch_bounds__(256) void k_xi2(const MixJob *__restrict__ jobs, in
     }
     j = lo;
     const MixJob &jb = jobs[j];
+    // window-major within the job: consecutive entries are templates of one window
     const int64_t le = e - jb.e0;
-    i = le / jb.nw;
-    o = i * jb.ld_peak + (jb.w0 + le - i * jb.nw - jb.w_base);
+    const int64_t wl = le / jb.n_templates;
+    i = le - wl * jb.n_templates;
+    o = i * jb.ld_peak + (jb.w0 + wl - jb.w_base);
     f = jb.acorr != nullptr && jb.peak_snr[o] >= thr;
   }
   uint64_t pending = __ballot(f);
@@ -1035,7 +1067,7 @@ hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems,
 
 hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float thr, hipStream_t s) {
   if (n_entries <= 0) return hipSuccess;
-  const unsigned blocks = blocks_for(n_entries, 256);   // one entry per thread
+  const unsigned blocks = (unsigned)(8 * ((blocks_for(n_entries, kXiPerBlock) + 7) / 8));
   switch (t) {
     case LLOID_F16: k_xi2<_Float16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, thr); break;
     case LLOID_BF16: k_xi2<__bf16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, thr); break;
