@@ -675,10 +675,12 @@ __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ j
 // (few, so that the triggers, about one in eight entries, spread evenly over
 // the waves); those at or above the threshold in jobs with autocorrelations
 // are then handled one at a time by the whole wave: first
-// z[n*] over all 64 lanes, then 8 teams of 8 lanes, one lag per team and
+// z[n*] over all 64 lanes, then 8 teams of 8 lanes, kXiLags lags per team and
 // pass, each team's lanes splitting K into 16-byte reads and reducing by
-// shuffles.
+// shuffles.  The kernel is bound by the latency of those reads (each trigger
+// reads 2K + 1 operand rows): the lags per pass are the reads in flight.
 constexpr int kXiPerWave = 8, kXiPerBlock = 4 * kXiPerWave;
+constexpr int kXiLags = 8;   // lags per team and pass
 
 // acc + the dot product of two 16-byte vectors of T, FP32 accumulation: packed
 // two-element dot instructions for the 16-bit types (their products are exact
@@ -771,17 +773,47 @@ __global__ __launch_bounds__(256) void k_xi2(const MixJob *__restrict__ jobs, in
     float2 zs = z_team<T>(mc, ms, base, nvec, lane, 64);
     zs.x *= sc;
     zs.y *= sc;
+    // a team takes kXiLags lags per pass (lags team + 8 u), so that the reads of
+    // kXiLags operand rows and one pair of mixing vectors are in flight at once;
+    // lags outside the data read the peak's row and are not counted
     float num = 0.f, den = 0.f;
-    for (int kk = team; kk < 2 * K + 1; kk += 64 / TEAM) {
-      const int64_t n = ns + kk - K;
-      if (n < 0 || n >= jb.n_end) continue;   // uniform within a team
-      const float2 z = z_team<T>(mc, ms, base + (int64_t)(kk - K) * nvec, nvec, sub, TEAM);
-      const float2 r = R[kk];
-      const float dr = z.x * sc - (zs.x * r.x - zs.y * r.y);
-      const float di = z.y * sc - (zs.x * r.y + zs.y * r.x);
-      if (sub == 0) {
-        num += dr * dr + di * di;
-        den += 2.f - 2.f * (r.x * r.x + r.y * r.y);
+    for (int kb = 0; kb < 2 * K + 1; kb += 64 / TEAM * kXiLags) {
+      const uint4 *rows[kXiLags];
+      bool ok[kXiLags];
+#pragma unroll
+      for (int u = 0; u < kXiLags; ++u) {
+        const int kk = kb + team + (64 / TEAM) * u;
+        const int64_t n = ns + kk - K;
+        ok[u] = kk < 2 * K + 1 && n >= 0 && n < jb.n_end;
+        rows[u] = base + (ok[u] ? (int64_t)(kk - K) * nvec : 0);
+      }
+      float re[kXiLags], im[kXiLags];
+#pragma unroll
+      for (int u = 0; u < kXiLags; ++u) re[u] = im[u] = 0.f;
+      for (int k = sub; k < nvec; k += TEAM) {
+        const uint4 c = mc[k], d = ms[k];
+        uint4 a[kXiLags];
+#pragma unroll
+        for (int u = 0; u < kXiLags; ++u) a[u] = rows[u][k];
+#pragma unroll
+        for (int u = 0; u < kXiLags; ++u) {
+          re[u] = dot16<T>(c, a[u], re[u]);
+          im[u] = dot16<T>(d, a[u], im[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kXiLags; ++u) {
+        for (int off = 1; off < TEAM; off <<= 1) {
+          re[u] += __shfl_xor(re[u], off);
+          im[u] += __shfl_xor(im[u], off);
+        }
+        if (ok[u] && sub == 0) {
+          const float2 r = R[kb + team + (64 / TEAM) * u];
+          const float dr = re[u] * sc - (zs.x * r.x - zs.y * r.y);
+          const float di = im[u] * sc - (zs.x * r.y + zs.y * r.x);
+          num += dr * dr + di * di;
+          den += 2.f - 2.f * (r.x * r.x + r.y * r.y);
+        }
       }
     }
     for (int off = 1; off < 64; off <<= 1) {
