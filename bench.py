@@ -14,8 +14,8 @@ Prints one JSON line: whole-job template-samples of SNR per second, the
 roofline of the dominant kernel (device time from HIP events on the
 library's stream over the timed steps), the plain FP32 path beside it, the
 same path with every trigger's xi2 signal-consistency value (bank
-autocorrelations over 2K + 1 lags), and the FP64 oracle timed on the host
-cores on a bounded sample.
+autocorrelations over 2K + 1 lags), the coincidence of the two detectors'
+triggers, and the FP64 oracle timed on the host cores on a bounded sample.
 """
 
 from __future__ import annotations
@@ -331,13 +331,14 @@ def main():
     ap.add_argument("--xi2-half", type=int, default=175,
                     help="multirate_c1: lags K on each side of the signal-consistency path (2K + 1 samples)")
     ap.add_argument("--xi2-steps", type=int, default=3, help="timed steps of the path with xi2 (0: skip)")
+    ap.add_argument("--coinc-reps", type=int, default=5, help="timed coincidence calls on the last triggers (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC byte-counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the filtering path runs on a single MI355X "
-              "(multi-GPU sharding by bank is described in DESIGN.md, not run here)", file=sys.stderr)
+              "(sharding by bank over several GPUs is not run here)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -410,6 +411,25 @@ def main():
         out["f32_path"] = {"value": round(v32, 1), "ms_per_step": round(w32 / args.f32_steps * 1e3, 3),
                            "speedup_of_headline": round(value / v32, 2),
                            "roofline_mix": roofline_entry("mfma", work["mix"][1], ms / max(calls, 1), "f32")}
+    if args.coinc_reps:
+        # coincidence of the two detectors' triggers (same template, within the
+        # light travel time: 10 ms, 21 samples at 2048 Hz), lists resident in HBM
+        bank = lloid.bank_from_svd(ctx, wl.bank, args.compute)
+        try:
+            trig = [lloid.lloid_filter(bank, d, x, window=(1, 1), threshold=4.0).triggers for d, x in enumerate(xs)]
+        finally:
+            lloid.lloid_bank_destroy(bank)
+        dev = [torch.from_numpy(t.view(np.uint8).copy()).to("cuda") for t in trig]
+        pairs = lloid.lloid_coincide(ctx, dev[0], dev[1], 21)
+        torch.cuda.synchronize()
+        t0c = time.perf_counter()
+        for _ in range(args.coinc_reps):
+            pairs = lloid.lloid_coincide(ctx, dev[0], dev[1], 21, cap=pairs.shape[0] + 16)
+        torch.cuda.synchronize()
+        out["coincidence"] = {"max_dt_samples": 21, "triggers": [int(t.shape[0]) for t in trig],
+                              "pairs": int(pairs.shape[0]),
+                              "ms_per_call": round((time.perf_counter() - t0c) / args.coinc_reps * 1e3, 3),
+                              "timing": "host wall time of the call (device lists, host output)"}
     if args.xi2_steps and args.xi2_half > 0:
         from workloads import bank_autocorrelation
         log(f"[bench] {args.compute} with xi2 over {2 * args.xi2_half + 1} lags: steps {args.xi2_steps}")

@@ -303,6 +303,38 @@ lloid_status lloid_stream_flush(lloid_stream *s);
 lloid_status lloid_stream_stats_get(const lloid_stream *s, lloid_stream_stats *out);
 lloid_status lloid_stream_destroy(lloid_stream *s);
 
+/* ---- coincidence across detectors ----
+ * A coincidence pairs the triggers of one template of one bank in two
+ * detectors whose peak samples lie within the light travel time between the
+ * detectors (Sec. II.A: the coincidence generator pairs triggers of the same
+ * template within the light travel time; the non-coincident triggers of
+ * times when several detectors observe are the background). */
+typedef struct {
+  int64_t a, b;          /* indices into the first and the second trigger list */
+  int32_t bank;
+  int32_t template_id;
+  float snr_net;         /* network SNR sqrt(snr_a^2 + snr_b^2) */
+  float dt;              /* (sample_b + dt_b) - (sample_a + dt_a): arrival difference in samples,
+                            with each trigger's sub-sample refinement */
+} lloid_coinc;
+
+/* Every pair (i, j) with a[i].bank == b[j].bank, a[i].template_id ==
+ * b[j].template_id and |a[i].sample - b[j].sample| <= max_dt (samples, for
+ * example the light travel time times f0, rounded up), in order of i, then j.
+ *   a, b:        trigger lists (host or device), each sorted by (bank,
+ *                template_id, sample) as lloid_filter and lloid_filter_batch
+ *                return one detector's triggers; n_a, n_b >= 0.
+ *   out:         cap records (host or device); *n_out = number of pairs.
+ *   background:  NULL, or n_a + n_b bytes (host or device): 1 for each trigger
+ *                of a, then of b, that is in no pair, else 0.
+ * EINVAL on a NULL list with a positive count, a list out of order or
+ * max_dt < 0; ETRUNC when the pairs exceed cap (*n_out is then the number
+ * needed; the first cap pairs are written).  Runs on the context's stream and
+ * returns when the results are in the caller's buffers. */
+lloid_status lloid_coincide(lloid_ctx *ctx, const lloid_trigger *a, int64_t n_a, const lloid_trigger *b,
+                            int64_t n_b, int64_t max_dt, lloid_coinc *out, int64_t cap, int64_t *n_out,
+                            uint8_t *background);
+
 /* Device bytes the filter calls of this context may use for the per-chunk
  * operands (the orthogonal SNR of every bank over a run of whole windows);
  * longer blocks are processed in several chunks.  Default 6 GiB. */

@@ -940,6 +940,67 @@ extern "C" lloid_status lloid_filter_batch(lloid_bank *const *banks, int32_t n_b
   ABI_GUARD_END
 }
 
+extern "C" lloid_status lloid_coincide(lloid_ctx *ctx, const lloid_trigger *a, int64_t n_a, const lloid_trigger *b,
+                                      int64_t n_b, int64_t max_dt, lloid_coinc *out, int64_t cap, int64_t *n_out,
+                                      uint8_t *background) {
+  ABI_GUARD_BEGIN
+  if (!ctx || !n_out) return fail(LLOID_EINVAL, "NULL argument");
+  if (n_a < 0 || n_b < 0 || cap < 0 || max_dt < 0) return fail(LLOID_EINVAL, "negative count, capacity or max_dt");
+  if ((n_a > 0 && !a) || (n_b > 0 && !b)) return fail(LLOID_EINVAL, "NULL trigger list");
+  if (cap > 0 && !out) return fail(LLOID_EINVAL, "NULL output with a positive capacity");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const bool host_a = n_a > 0 && !is_device_ptr(a), host_b = n_b > 0 && !is_device_ptr(b);
+  const bool host_out = cap > 0 && !is_device_ptr(out);
+  const bool host_bg = background && !is_device_ptr(background);
+  size_t bytes = 0;
+  auto add = [&](size_t cnt, size_t sz) { bytes = (size_t)round_up((int64_t)bytes, 256) + cnt * sz; };
+  if (host_a) add((size_t)n_a, sizeof(lloid_trigger));
+  if (host_b) add((size_t)n_b, sizeof(lloid_trigger));
+  add((size_t)n_a + 2, 8);
+  add(1, sizeof(int));
+  if (host_out) add((size_t)cap, sizeof(lloid_coinc));
+  if (host_bg) add((size_t)(n_a + n_b), 1);
+  lloid_status rs = ensure_ws(ctx, ctx->ws, bytes);
+  if (rs != LLOID_OK) return rs;
+  Carve cv{(char *)ctx->ws.base};
+  const lloid_trigger *da = a, *db = b;
+  if (host_a) {
+    lloid_trigger *p = cv.take<lloid_trigger>((size_t)n_a);
+    HIP_TRY(hipMemcpyAsync(p, a, (size_t)n_a * sizeof(lloid_trigger), hipMemcpyHostToDevice, st));
+    da = p;
+  }
+  if (host_b) {
+    lloid_trigger *p = cv.take<lloid_trigger>((size_t)n_b);
+    HIP_TRY(hipMemcpyAsync(p, b, (size_t)n_b * sizeof(lloid_trigger), hipMemcpyHostToDevice, st));
+    db = p;
+  }
+  int64_t *counts = cv.take<int64_t>((size_t)n_a + 2);
+  int64_t *total = counts + n_a;
+  int *bad = cv.take<int>(1);
+  lloid_coinc *dout = host_out ? cv.take<lloid_coinc>((size_t)cap) : out;
+  uint8_t *dbg = host_bg ? cv.take<uint8_t>((size_t)(n_a + n_b)) : background;
+  HIP_TRY(launch_fill_u8(bad, sizeof(int), st));
+  HIP_TRY(launch_coincide(da, n_a, db, n_b, max_dt, counts, total, bad, cap, dout, dbg, dbg ? dbg + n_a : nullptr,
+                          st));
+  int64_t h_total = 0;
+  int h_bad = 0;
+  HIP_TRY(hipMemcpyAsync(&h_total, total, sizeof h_total, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&h_bad, bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h_bad) return fail(LLOID_EINVAL, "a trigger list is not sorted by (bank, template_id, sample)");
+  const int64_t ncopy = std::min(h_total, cap);
+  if (host_out && ncopy > 0)
+    HIP_TRY(hipMemcpyAsync(out, dout, (size_t)ncopy * sizeof(lloid_coinc), hipMemcpyDeviceToHost, st));
+  if (host_bg && n_a + n_b > 0)
+    HIP_TRY(hipMemcpyAsync(background, dbg, (size_t)(n_a + n_b), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *n_out = h_total;
+  if (h_total > cap) return fail(LLOID_ETRUNC, "%lld coincidences, capacity %lld", (long long)h_total, (long long)cap);
+  return LLOID_OK;
+  ABI_GUARD_END
+}
+
 extern "C" lloid_status lloid_ctx_set_chunk_bytes(lloid_ctx *ctx, int64_t bytes) {
   if (!ctx || bytes <= 0) return fail(LLOID_EINVAL, "bad argument");
   ctx->chunk_budget = bytes;

@@ -181,6 +181,11 @@ hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_e
 // counts holds trig_blocks(n_elems) slots.
 hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems, float thr, int64_t *counts,
                                int64_t *total, int64_t cap, lloid_trigger *out, hipStream_t s);
+// Coincidences of two sorted trigger lists: per-trigger counts (na slots),
+// their scan, pairs at the scanned offsets; *bad set when a list is out of order.
+hipError_t launch_coincide(const lloid_trigger *a, int64_t na, const lloid_trigger *b, int64_t nb, int64_t max_dt,
+                           int64_t *counts, int64_t *total, int *bad, int64_t cap, lloid_coinc *out, uint8_t *bg_a,
+                           uint8_t *bg_b, hipStream_t s);
 hipError_t launch_sigma2(const double *mix64, int n_templates, int lsum, const double *inv_dec_per_col,
                          double *out, hipStream_t s);
 hipError_t launch_fill_u8(void *p, size_t bytes, hipStream_t s);

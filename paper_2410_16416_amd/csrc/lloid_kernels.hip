@@ -958,6 +958,82 @@ __global__ __launch_bounds__(kTrigThreads) void k_trigger_write(const TrigJob *_
   }
 }
 
+// ---------------------------------------------------------- coincidence
+// Pairs of triggers of two detectors with the same (bank, template) whose
+// peak samples differ by at most max_dt (Sec. II.A, the coincidence
+// generator).  Both lists are sorted by (bank, template, sample), so the
+// partners of a[i] are one contiguous run of b, found by binary search; one
+// thread per trigger of a counts its run, the counts are scanned, and the
+// same threads write their pairs at the scanned offsets (a-major order).
+
+__device__ __forceinline__ bool key_before(const lloid_trigger &x, int32_t bank, int32_t tmpl, int64_t sample) {
+  if (x.bank != bank) return x.bank < bank;
+  if (x.template_id != tmpl) return x.template_id < tmpl;
+  return x.sample < sample;
+}
+
+__device__ __forceinline__ bool out_of_order(const lloid_trigger &x, const lloid_trigger &y) {
+  return key_before(y, x.bank, x.template_id, x.sample);
+}
+
+// first j with b[j] not before (bank, tmpl, sample - max_dt)
+__device__ __forceinline__ int64_t coinc_first(const lloid_trigger *__restrict__ b, int64_t nb,
+                                               const lloid_trigger &t, int64_t max_dt) {
+  int64_t lo = 0, hi = nb;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (key_before(b[mid], t.bank, t.template_id, t.sample - max_dt)) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool coinc_partner(const lloid_trigger &x, const lloid_trigger &t, int64_t max_dt) {
+  return x.bank == t.bank && x.template_id == t.template_id && x.sample <= t.sample + max_dt;
+}
+
+__global__ void k_coinc_count(const lloid_trigger *__restrict__ a, int64_t na, const lloid_trigger *__restrict__ b,
+                              int64_t nb, int64_t max_dt, int64_t *__restrict__ counts, uint8_t *__restrict__ bg_b,
+                              int *__restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) {
+    if (bg_b) bg_b[i] = 1;
+    if (i + 1 < nb && out_of_order(b[i], b[i + 1])) *bad = 1;
+  }
+  if (i >= na) return;
+  const lloid_trigger t = a[i];
+  if (i + 1 < na && out_of_order(t, a[i + 1])) *bad = 1;
+  int64_t c = 0;
+  for (int64_t j = coinc_first(b, nb, t, max_dt); j < nb && coinc_partner(b[j], t, max_dt); ++j) ++c;
+  counts[i] = c;
+}
+
+__global__ void k_coinc_write(const lloid_trigger *__restrict__ a, int64_t na, const lloid_trigger *__restrict__ b,
+                              int64_t nb, int64_t max_dt, const int64_t *__restrict__ offsets, int64_t cap,
+                              lloid_coinc *__restrict__ out, uint8_t *__restrict__ bg_a,
+                              uint8_t *__restrict__ bg_b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= na) return;
+  const lloid_trigger t = a[i];
+  int64_t m = offsets[i];
+  const int64_t m0 = m;
+  for (int64_t j = coinc_first(b, nb, t, max_dt); j < nb && coinc_partner(b[j], t, max_dt); ++j, ++m) {
+    const lloid_trigger u = b[j];
+    if (bg_b) bg_b[j] = 0;
+    if (m < cap) {
+      lloid_coinc c;
+      c.a = i;
+      c.b = j;
+      c.bank = t.bank;
+      c.template_id = t.template_id;
+      c.snr_net = sqrtf(t.snr * t.snr + u.snr * u.snr);
+      c.dt = (float)(u.sample - t.sample) + (u.dt - t.dt);
+      out[m] = c;
+    }
+  }
+  if (bg_a) bg_a[i] = m == m0 ? 1 : 0;
+}
+
 // ------------------------------------------------------------ launchers
 
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -1106,6 +1182,18 @@ hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_e
     case LLOID_F32: k_xi2<float><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, thr); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_coincide(const lloid_trigger *a, int64_t na, const lloid_trigger *b, int64_t nb, int64_t max_dt,
+                           int64_t *counts, int64_t *total, int *bad, int64_t cap, lloid_coinc *out, uint8_t *bg_a,
+                           uint8_t *bg_b, hipStream_t s) {
+  const int64_t nmax = std::max(na, nb);
+  if (nmax > 0)
+    k_coinc_count<<<blocks_for(nmax, 256), 256, 0, s>>>(a, na, b, nb, max_dt, counts, bg_b, bad);
+  k_trigger_scan<<<1, 1024, 0, s>>>(counts, na, total);
+  if (na > 0)
+    k_coinc_write<<<blocks_for(na, 256), 256, 0, s>>>(a, na, b, nb, max_dt, counts, cap, out, bg_a, bg_b);
   return hipGetLastError();
 }
 

@@ -87,6 +87,10 @@ TRIGGER_DTYPE = np.dtype([("bank", np.int32), ("detector", np.int32), ("template
                           ("snr_interp", np.float32), ("dt", np.float32)])
 assert TRIGGER_DTYPE.itemsize == 48
 
+COINC_DTYPE = np.dtype([("a", np.int64), ("b", np.int64), ("bank", np.int32), ("template_id", np.int32),
+                        ("snr_net", np.float32), ("dt", np.float32)])
+assert COINC_DTYPE.itemsize == 32
+
 
 def _load():
     if not os.path.exists(LIB_PATH):
@@ -106,6 +110,7 @@ def _load():
         "lloid_bank_destroy": ([vp], ctypes.c_int),
         "lloid_filter": ([vp, i32, vp, ctypes.c_int, i64, ctypes.POINTER(lloid_trigger_opts), vp, i64,
                           ctypes.POINTER(i64), vp, ctypes.POINTER(lloid_peaks)], ctypes.c_int),
+        "lloid_coincide": ([vp, vp, i64, vp, i64, i64, vp, i64, ctypes.POINTER(i64), vp], ctypes.c_int),
         "lloid_filter_batch": ([ctypes.POINTER(vp), i32, i32, vp, ctypes.c_int, i64,
                                 ctypes.POINTER(lloid_trigger_opts), vp, i64, ctypes.POINTER(i64),
                                 ctypes.POINTER(lloid_peaks)], ctypes.c_int),
@@ -150,7 +155,8 @@ def exported_symbols():
             "lloid_bank_create", "lloid_bank_sigma2", "lloid_bank_query", "lloid_bank_destroy",
             "lloid_filter", "lloid_filter_batch", "lloid_ctx_set_chunk_bytes",
             "lloid_stream_create", "lloid_stream_admit", "lloid_stream_remove", "lloid_stream_push",
-            "lloid_stream_poll", "lloid_stream_flush", "lloid_stream_stats_get", "lloid_stream_destroy"]
+            "lloid_stream_poll", "lloid_stream_flush", "lloid_stream_stats_get", "lloid_stream_destroy",
+            "lloid_coincide"]
 
 
 def lloid_version() -> str:
@@ -242,6 +248,35 @@ class FilterResult:
     peak_sample: np.ndarray | None = None
     peak_phase: np.ndarray | None = None
     snr: object = None
+
+
+def lloid_coincide(ctx, a, b, max_dt: int, cap: int | None = None, background: bool = False):
+    """Coincidences of two trigger lists (numpy TRIGGER_DTYPE arrays, or torch
+    uint8 tensors of 48-byte records on the device), each sorted by (bank,
+    template_id, sample).  Returns the COINC_DTYPE pairs and, with background,
+    a uint8 array of n_a + n_b flags (1: the trigger is in no pair)."""
+    def count(x):
+        return x.shape[0] if isinstance(x, np.ndarray) else x.numel() // TRIGGER_DTYPE.itemsize
+    n_a, n_b = count(a), count(b)
+    if isinstance(a, np.ndarray):
+        a = np.ascontiguousarray(a, dtype=TRIGGER_DTYPE)
+    if isinstance(b, np.ndarray):
+        b = np.ascontiguousarray(b, dtype=TRIGGER_DTYPE)
+    if cap is None:
+        cap = max(16, 4 * max(n_a, n_b))
+    for _ in range(2):
+        out = np.zeros(max(cap, 1), dtype=COINC_DTYPE)
+        bg = np.zeros(n_a + n_b, dtype=np.uint8) if background else None
+        n = ctypes.c_int64(0)
+        st = _lib.lloid_coincide(ctx, _ptr(a) if n_a else None, n_a, _ptr(b) if n_b else None, n_b, int(max_dt),
+                                 out.ctypes.data, cap, ctypes.byref(n), _ptr(bg) if bg is not None and bg.size else None)
+        if st == LLOID_ETRUNC:
+            cap = n.value
+            continue
+        _check(st)
+        break
+    pairs = out[:n.value].copy()
+    return (pairs, bg) if background else pairs
 
 
 def lloid_filter(bank, detector: int, strain, window=(1, 1), threshold: float = 4.0,

@@ -56,6 +56,8 @@ int main(void) {
   printf("lloid_peaks %zu\\n", sizeof(lloid_peaks));
   printf("lloid_stream_opts %zu\\n", sizeof(lloid_stream_opts));
   printf("lloid_stream_stats %zu\\n", sizeof(lloid_stream_stats));
+  printf("lloid_coinc %zu\\n", sizeof(lloid_coinc));
+  P(lloid_coinc, bank) P(lloid_coinc, template_id) P(lloid_coinc, snr_net) P(lloid_coinc, dt)
   P(lloid_stream_opts, use_graph) P(lloid_stream_opts, hbm_budget) P(lloid_stream_opts, trig)
   P(lloid_stream_stats, bytes_in_use) P(lloid_stream_stats, graph_replays)
   P(lloid_slice, start_tap) P(lloid_slice, basis) P(lloid_slice, mixing)
@@ -77,6 +79,11 @@ int main(void) {
     for name, cls in mirror.items():
         assert int(got[name]) == ctypes.sizeof(cls), name
     assert int(got["lloid_trigger"]) == lloid.TRIGGER_DTYPE.itemsize
+    assert int(got["lloid_coinc"]) == lloid.COINC_DTYPE.itemsize
+    from workloads.triggers import TRIGGER_DTYPE as synthetic
+    assert synthetic == lloid.TRIGGER_DTYPE
+    for f in ("bank", "template_id", "snr_net", "dt"):
+        assert int(got[f"lloid_coinc.{f}"]) == lloid.COINC_DTYPE.fields[f][1], f
     for f in ("xi2", "window", "sample", "snr", "phase", "snr_interp", "dt"):
         assert int(got[f"lloid_trigger.{f}"]) == lloid.TRIGGER_DTYPE.fields[f][1]
     for f in ("start_tap", "basis", "mixing"):

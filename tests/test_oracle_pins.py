@@ -538,3 +538,51 @@ def test_xi2_averages_one_in_white_noise():
         assert abs(np.mean(v) - 1.0) < 5 * se + 0.01, (i, np.mean(v), se)
         w = np.array([oracle.xi2(z[i], 0, n, int(p), np.conj(r[i])) for p in pos[:400]])
         assert np.max(np.abs(r[i].imag)) > 0.3 and np.mean(w) > 1.5
+
+
+# --------------------------------------------------- coincidence (Sec. II.A)
+
+def _trig(rows):
+    from workloads.triggers import TRIGGER_DTYPE
+    t = np.zeros(len(rows), dtype=TRIGGER_DTYPE)
+    for k, (bank, tmpl, sample, snr, dt) in enumerate(rows):
+        t[k]["bank"], t[k]["template_id"], t[k]["sample"] = bank, tmpl, sample
+        t[k]["snr"], t[k]["dt"] = snr, dt
+    return t
+
+
+def test_coincidence_hand_example():
+    """Worked by hand: same bank and template within 10 samples (inclusive)."""
+    a = _trig([(0, 5, 100, 6.0, 0.25), (0, 5, 2000, 5.0, 0.0), (0, 6, 100, 4.0, 0.0)])
+    b = _trig([(0, 5, 90, 8.0, -0.25), (0, 5, 111, 4.5, 0.0), (0, 6, 300, 4.0, 0.0), (1, 5, 100, 9.0, 0.0)])
+    pairs, bg = oracle.coincidences(a, b, 10)
+    assert [(p[0], p[1]) for p in pairs] == [(0, 0)]
+    assert abs(pairs[0][4] - 10.0) < 1e-12            # sqrt(6^2 + 8^2)
+    assert abs(pairs[0][5] - (-10.5)) < 1e-12         # (90 - 0.25) - (100 + 0.25)
+    assert bg == [0, 1, 1, 0, 1, 1, 1]
+    pairs11, _ = oracle.coincidences(a, b, 11)
+    assert [(p[0], p[1]) for p in pairs11] == [(0, 0), (0, 1)]
+
+
+def test_coincidence_invariants():
+    """Swapping the detectors swaps the pairs and negates dt; shifting every
+    sample by a constant changes nothing; an unbounded max_dt pairs every
+    trigger with every trigger of its (bank, template) in the other list."""
+    from workloads.triggers import trigger_pair
+    a, b = trigger_pair(5, n_banks=2, n_templates=12, n_windows=10, rate=0.3)
+    p, bg = oracle.coincidences(a, b, 25)
+    q, bgq = oracle.coincidences(b, a, 25)
+    assert sorted((x[1], x[0]) for x in p) == sorted((x[0], x[1]) for x in q)
+    dts = {(x[0], x[1]): x[5] for x in p}
+    assert all(abs(dts[(x[1], x[0])] + x[5]) < 1e-9 for x in q)
+    assert bg[:len(a)] == bgq[len(b):] and bg[len(a):] == bgq[:len(b)]
+    a2, b2 = a.copy(), b.copy()
+    a2["sample"] += 123457
+    b2["sample"] += 123457
+    assert [x[:2] for x in oracle.coincidences(a2, b2, 25)[0]] == [x[:2] for x in p]
+    allp, _ = oracle.coincidences(a, b, 10 ** 9)
+    from collections import Counter
+    ca = Counter(zip(a["bank"].tolist(), a["template_id"].tolist()))
+    cb = Counter(zip(b["bank"].tolist(), b["template_id"].tolist()))
+    assert len(allp) == sum(ca[k] * cb[k] for k in ca)
+    assert len(p) < len(allp)
