@@ -586,3 +586,63 @@ def test_coincidence_invariants():
     cb = Counter(zip(b["bank"].tolist(), b["template_id"].tolist()))
     assert len(allp) == sum(ca[k] * cb[k] for k in ca)
     assert len(p) < len(allp)
+
+
+# ---------------------------------------- conditioning: PSD, whitening, gating
+
+def test_welch_psd_equals_scipy():
+    """Library routine: the block PSD is scipy's Welch average (periodic Hann,
+    half overlap, no detrending, density scaling)."""
+    x = np.random.default_rng(31).standard_normal(40000) * 2.5
+    for L in (256, 1024):
+        _, want = scipy.signal.welch(x, fs=1024, window="hann", nperseg=L, noverlap=L // 2, detrend=False,
+                                     average="mean", scaling="density")
+        assert np.allclose(oracle.welch_psd(x, 1024, L), want, rtol=1e-12, atol=0)
+
+
+def test_whitening_with_a_flat_psd_is_a_scaling():
+    """Closed form: with S = 2 sigma^2 / f0 the gain is 1/sigma on every bin and
+    the half-overlapped Hann windows sum to one, so whitening returns x/sigma
+    exactly (a dropped segment, a wrong hop or window fails it); scaling the
+    PSD by c scales the output by 1/sqrt(c)."""
+    rng = np.random.default_rng(32)
+    x = rng.standard_normal(5000 + 77)
+    for L in (256, 512):
+        flat = np.full(L // 2 + 1, 2.0 * 9.0 / 1024)
+        assert np.allclose(oracle.whiten(x, 1024, L, flat), x / 3.0, atol=1e-12)
+        s = oracle.welch_psd(x, 1024, L)
+        assert np.allclose(oracle.whiten(x, 1024, L, 4.0 * s), oracle.whiten(x, 1024, L, s) / 2.0, atol=1e-12)
+
+
+def test_whitening_flattens_coloured_noise():
+    """AR(1) noise y[n] = a y[n-1] + e[n] has the one-sided density
+    S(f) = (2/f0) / |1 - a e^{-2 pi i f/f0}|^2; whitened with it (or with the
+    block's own estimate), the output has unit variance and a flat PSD."""
+    f0, L, a = 1024, 512, 0.9
+    e = np.random.default_rng(33).standard_normal(1 << 18)
+    y = scipy.signal.lfilter([1.0], [1.0, -a], e)
+    f = np.arange(L // 2 + 1) / L
+    true = (2.0 / f0) / np.abs(1.0 - a * np.exp(-2j * np.pi * f)) ** 2
+    for s in (true, oracle.welch_psd(y, f0, L)):
+        xw = oracle.whiten(y, f0, L, s)[L:-L]
+        assert abs(np.var(xw) - 1.0) < 0.03
+        flat = oracle.welch_psd(xw, f0, L)[4:-4] * f0 / 2.0
+        assert np.all(np.abs(flat - 1.0) < 0.2)
+    assert np.var(y) > 4.0     # the input was far from white
+
+
+def test_gate_zeroes_around_loud_samples():
+    """Closed form: a spike above the threshold zeroes exactly 2G+1 samples
+    around it (clipped at the ends of the data); the rest is unchanged."""
+    rng = np.random.default_rng(34)
+    xw = rng.standard_normal(3000)
+    xw[1000] = 80.0
+    xw[5] = -90.0
+    out, n = oracle.gate(xw, 20.0, 50)
+    assert n == 101 + 56
+    assert np.all(out[950:1051] == 0) and np.all(out[:56] == 0)
+    keep = np.ones(3000, bool)
+    keep[950:1051] = False
+    keep[:56] = False
+    assert np.array_equal(out[keep], xw[keep])
+    assert oracle.gate(xw, 0.0, 50)[1] == 0
