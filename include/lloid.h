@@ -303,6 +303,39 @@ lloid_status lloid_stream_flush(lloid_stream *s);
 lloid_status lloid_stream_stats_get(const lloid_stream *s, lloid_stream_stats *out);
 lloid_status lloid_stream_destroy(lloid_stream *s);
 
+/* ---- conditioning before the filter ----
+ * Sec. II.A conditions the strain before filtering: a PSD estimate, whitening
+ * with it, and gating of large deviations of the whitened data.  Segments of
+ * L samples start every L/2 samples and carry a periodic Hann window
+ * w[n] = sin^2(pi n / L) (w[n] + w[n + L/2] = 1).
+ *   PSD:       the mean over the segments wholly inside the block of the
+ *              one-sided periodogram c_f |DFT(w x_m)[f]|^2 / (f0 sum w^2),
+ *              c_f = 2 except at f = 0 and L/2 (unit-variance white noise has
+ *              S = 2 / f0); or the caller's PSD.
+ *   whitening: every segment (data zero outside the block) is windowed,
+ *              transformed, scaled by G[f] = 1 / sqrt(S[f] f0 / 2) (0 where
+ *              S[f] <= 0), transformed back and overlap-added.
+ *   gating:    every whitened sample above the threshold in magnitude zeroes
+ *              the samples within gate_half_width of it. */
+typedef struct {
+  int32_t seg_len;         /* L: a power of two, 64..4096 */
+  int32_t gate_half_width; /* >= 0 */
+  float gate_threshold;    /* 0: no gating */
+  int32_t reserved;
+  const double *psd;       /* host, [L/2 + 1] one-sided PSD to whiten with; NULL: estimate it from
+                              this block (which then needs n >= L) */
+} lloid_condition_opts;
+
+/* Condition one block of strain (host or device, F64 or F32, n >= 1 samples
+ * at full_rate_hz) into out (n floats, host or device: the whitened and gated
+ * strain, ready for lloid_filter).  psd_out: NULL or host [L/2 + 1], the PSD
+ * used.  n_gated: NULL or the number of samples zeroed by the gate.
+ * EINVAL on a bad length, rate or option, a block shorter than one segment
+ * without a PSD, or a non-finite strain sample or PSD value.  Runs on the
+ * context's stream and returns when the results are in the caller's buffers. */
+lloid_status lloid_condition(lloid_ctx *ctx, int32_t full_rate_hz, const void *strain, lloid_dtype dtype, int64_t n,
+                             const lloid_condition_opts *opts, float *out, double *psd_out, int64_t *n_gated);
+
 /* ---- coincidence across detectors ----
  * A coincidence pairs the triggers of one template of one bank in two
  * detectors whose peak samples lie within the light travel time between the

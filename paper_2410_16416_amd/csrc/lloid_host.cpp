@@ -940,6 +940,82 @@ extern "C" lloid_status lloid_filter_batch(lloid_bank *const *banks, int32_t n_b
   ABI_GUARD_END
 }
 
+extern "C" lloid_status lloid_condition(lloid_ctx *ctx, int32_t full_rate_hz, const void *strain, lloid_dtype dtype,
+                                       int64_t n, const lloid_condition_opts *opts, float *out, double *psd_out,
+                                       int64_t *n_gated) {
+  ABI_GUARD_BEGIN
+  if (!ctx || !strain || !opts || !out) return fail(LLOID_EINVAL, "NULL argument");
+  if (full_rate_hz <= 0) return fail(LLOID_EINVAL, "full_rate_hz must be positive");
+  if (dtype != LLOID_F64 && dtype != LLOID_F32) return fail(LLOID_EINVAL, "strain must be F64 or F32");
+  if (n < 1 || n > kMaxBlock) return fail(LLOID_EINVAL, "n must be in [1, 2^28]");
+  const int L = opts->seg_len;
+  if (L < kCondMinLen || L > kCondMaxLen || (L & (L - 1)))
+    return fail(LLOID_EINVAL, "seg_len %d is not a power of two in [%d, %d]", L, kCondMinLen, kCondMaxLen);
+  if (opts->gate_half_width < 0 || !(opts->gate_threshold >= 0.f) || !std::isfinite(opts->gate_threshold))
+    return fail(LLOID_EINVAL, "bad gate options");
+  const bool estimate = opts->psd == nullptr;
+  if (estimate && n < L) return fail(LLOID_EINVAL, "a block of %lld samples is shorter than one segment", (long long)n);
+  const int nf = L / 2 + 1;
+  if (!estimate)
+    for (int f = 0; f < nf; ++f)
+      if (!std::isfinite(opts->psd[f])) return fail(LLOID_EINVAL, "non-finite PSD value at bin %d", f);
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const bool host_strain = !is_device_ptr(strain), host_out = !is_device_ptr(out);
+  const bool gating = opts->gate_threshold > 0.f;
+  const int64_t nseg_p = estimate ? (n - L) / (L / 2) + 1 : 0;
+  const int64_t nseg_w = (2 * (n - 1)) / L + 2;
+  size_t bytes = 0;
+  auto add = [&](size_t cnt, size_t sz) { bytes = (size_t)round_up((int64_t)bytes, 256) + cnt * sz; };
+  if (host_strain) add((size_t)n, dtype_size(dtype));
+  add((size_t)n, 4);                       // float strain
+  add((size_t)(nseg_p * nf), 4);           // periodograms
+  add((size_t)nf, 8);                      // PSD
+  add((size_t)nf, 4);                      // gain
+  add((size_t)(nseg_w * L), 4);            // whitened segments
+  if (gating) add((size_t)n, 4), add((size_t)n, 1);
+  if (host_out) add((size_t)n, 4);
+  add(1, 8);
+  add(1, sizeof(int));
+  lloid_status rs = ensure_ws(ctx, ctx->ws, bytes);
+  if (rs != LLOID_OK) return rs;
+  Carve cv{(char *)ctx->ws.base};
+  const void *d_strain = strain;
+  if (host_strain) {
+    char *p = cv.take<char>((size_t)n * dtype_size(dtype));
+    HIP_TRY(hipMemcpyAsync(p, strain, (size_t)n * dtype_size(dtype), hipMemcpyHostToDevice, st));
+    d_strain = p;
+  }
+  float *x = cv.take<float>((size_t)n);
+  float *parts = cv.take<float>((size_t)(nseg_p * nf));
+  double *psd = cv.take<double>((size_t)nf);
+  float *gain = cv.take<float>((size_t)nf);
+  float *y = cv.take<float>((size_t)(nseg_w * L));
+  float *xw = gating ? cv.take<float>((size_t)n) : nullptr;
+  uint8_t *mask = gating ? cv.take<uint8_t>((size_t)n) : nullptr;
+  float *dout = host_out ? cv.take<float>((size_t)n) : out;
+  unsigned long long *count = cv.take<unsigned long long>(1);
+  int *bad = cv.take<int>(1);
+  HIP_TRY(launch_fill_u8(bad, sizeof(int), st));
+  HIP_TRY(launch_fill_u8(count, 8, st));
+  if (gating) HIP_TRY(launch_fill_u8(mask, (size_t)n, st));
+  if (!estimate) HIP_TRY(hipMemcpyAsync(psd, opts->psd, (size_t)nf * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_convert(d_strain, dtype, n, x, 0, n, 1.f, bad, st));
+  HIP_TRY(launch_condition(x, n, L, estimate, (double)full_rate_hz, parts, psd, gain, y, xw, opts->gate_threshold,
+                           opts->gate_half_width, mask, dout, count, st));
+  int h_bad = 0;
+  unsigned long long h_count = 0;
+  HIP_TRY(hipMemcpyAsync(&h_bad, bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&h_count, count, sizeof h_count, hipMemcpyDeviceToHost, st));
+  if (psd_out) HIP_TRY(hipMemcpyAsync(psd_out, psd, (size_t)nf * 8, hipMemcpyDeviceToHost, st));
+  if (host_out) HIP_TRY(hipMemcpyAsync(out, dout, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h_bad) return fail(LLOID_EINVAL, "non-finite strain sample");
+  if (n_gated) *n_gated = (int64_t)h_count;
+  return LLOID_OK;
+  ABI_GUARD_END
+}
+
 extern "C" lloid_status lloid_coincide(lloid_ctx *ctx, const lloid_trigger *a, int64_t n_a, const lloid_trigger *b,
                                       int64_t n_b, int64_t max_dt, lloid_coinc *out, int64_t cap, int64_t *n_out,
                                       uint8_t *background) {

@@ -181,6 +181,14 @@ hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_e
 // counts holds trig_blocks(n_elems) slots.
 hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems, float thr, int64_t *counts,
                                int64_t *total, int64_t cap, lloid_trigger *out, hipStream_t s);
+// Conditioning of one block (float strain x[T]): PSD estimate into psd (when
+// estimate; else psd holds the caller's), gain, whitened segments y, overlap-
+// add into xw (or straight into out without gating), gating into out with
+// the gated-sample count added to *count (mask zeroed by the caller).
+constexpr int kCondMinLen = 64, kCondMaxLen = 4096;
+hipError_t launch_condition(const float *x, int64_t T, int L, bool estimate, double f0, float *parts,
+                            double *psd, float *gain, float *y, float *xw, float gate_thr, int gate_half,
+                            uint8_t *mask, float *out, unsigned long long *count, hipStream_t s);
 // Coincidences of two sorted trigger lists: per-trigger counts (na slots),
 // their scan, pairs at the scanned offsets; *bad set when a list is out of order.
 hipError_t launch_coincide(const lloid_trigger *a, int64_t na, const lloid_trigger *b, int64_t nb, int64_t max_dt,

@@ -958,6 +958,122 @@ __global__ __launch_bounds__(kTrigThreads) void k_trigger_write(const TrigJob *_
   }
 }
 
+// ---------------------------------------------------------- conditioning
+// PSD, whitening and gating before the filter (Sec. II.A).  Each segment of L
+// samples (hop L/2, periodic Hann window) is one workgroup: it loads the
+// windowed samples into LDS and runs a radix-2 Stockham FFT there (two LDS
+// buffers, one barrier per stage, output in natural order).  The PSD launch
+// writes each segment's |X[f]|^2; their mean is taken per bin in FP64.  The
+// whitening launch scales the spectrum by the gain, transforms back and
+// writes the segment; the overlap-add sums the two segments over each sample.
+
+// X = DFT(a) over n = 2^lg points with exponent sign * 2 pi i / n; a and b
+// are LDS buffers of n values; returns the one that holds the result.
+__device__ float2 *fft_lds(float2 *a, float2 *b, int n, int lg, float sign) {
+  const int half = n >> 1;
+  for (int st = 0; st < lg; ++st) {
+    const int ns = 1 << st;
+    for (int j = threadIdx.x; j < half; j += blockDim.x) {
+      const int k = j & (ns - 1);
+      const float2 a0 = a[j], a1 = a[j + half];
+      float sn, cs;
+      sincospif(sign * (float)k / (float)ns, &sn, &cs);   // angle sign * 2 pi k / (2 ns)
+      const float tx = a1.x * cs - a1.y * sn, ty = a1.x * sn + a1.y * cs;
+      const int idx = ((j >> st) << (st + 1)) + k;
+      b[idx] = make_float2(a0.x + tx, a0.y + ty);
+      b[idx + ns] = make_float2(a0.x - tx, a0.y - ty);
+    }
+    __syncthreads();
+    float2 *t = a;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// One segment per workgroup: segment m = seg0 + blockIdx.x covers samples
+// [m L/2, m L/2 + L) of x (zero outside [0, T)).  WHITEN = false: |X[f]|^2
+// for f <= L/2 into parts; true: X scaled by gain[min(f, L - f)], inverse
+// transform, real part / L into y.
+template <bool WHITEN>
+__global__ __launch_bounds__(256) void k_cond_segment(const float *__restrict__ x, int64_t T, int L, int lg,
+                                                      int64_t seg0, const float *__restrict__ gain,
+                                                      float *__restrict__ parts, float *__restrict__ y) {
+  extern __shared__ float2 cbuf[];   // 2 L values
+  float2 *a = cbuf, *b = cbuf + L;
+  const int64_t lo = (seg0 + (int64_t)blockIdx.x) * (L / 2);
+  for (int n = threadIdx.x; n < L; n += blockDim.x) {
+    const int64_t t = lo + n;
+    const float v = (t >= 0 && t < T) ? x[t] : 0.f;
+    const float s = sinpif((float)n / (float)L);
+    a[n] = make_float2(v * s * s, 0.f);
+  }
+  __syncthreads();
+  float2 *X = fft_lds(a, b, L, lg, -1.f);
+  if (!WHITEN) {
+    const int nf = L / 2 + 1;
+    for (int f = threadIdx.x; f < nf; f += blockDim.x)
+      parts[(int64_t)blockIdx.x * nf + f] = X[f].x * X[f].x + X[f].y * X[f].y;
+    return;
+  }
+  for (int f = threadIdx.x; f < L; f += blockDim.x) {
+    const float g = gain[f <= L / 2 ? f : L - f];
+    X[f] = make_float2(X[f].x * g, X[f].y * g);
+  }
+  __syncthreads();
+  float2 *Y = fft_lds(X, X == a ? b : a, L, lg, 1.f);
+  const float inv = 1.f / (float)L;
+  for (int n = threadIdx.x; n < L; n += blockDim.x) y[(int64_t)blockIdx.x * L + n] = Y[n].x * inv;
+}
+
+// Per bin f <= L/2: the mean periodogram in FP64, c_f / (nseg f0 sum w^2) times
+// the sum over segments (sum w^2 = 3 L / 8 for the periodic Hann window).
+__global__ void k_psd_mean(const float *__restrict__ parts, int64_t nseg, int L, double f0, double *__restrict__ psd) {
+  const int nf = L / 2 + 1;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  double acc = 0.0;
+  for (int64_t m = 0; m < nseg; ++m) acc += (double)parts[m * nf + f];
+  const double c = (f == 0 || f == L / 2) ? 1.0 : 2.0;
+  psd[f] = c * acc / ((double)nseg * f0 * (3.0 * L / 8.0));
+}
+
+__global__ void k_psd_gain(const double *__restrict__ psd, int nf, double f0, float *__restrict__ gain) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const double s = psd[f];
+  gain[f] = s > 0.0 ? (float)(1.0 / sqrt(s * f0 / 2.0)) : 0.f;
+}
+
+// xw[n] = the two segments' outputs over sample n (segment m starts at m L/2;
+// y holds segments seg0, seg0 + 1, ...)
+__global__ void k_overlap_add(const float *__restrict__ y, int64_t T, int L, int64_t seg0, float *__restrict__ xw) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= T) return;
+  const int64_t h = L / 2;
+  const int64_t mb = n / h, ma = mb - 1;
+  xw[n] = y[(ma - seg0) * L + (n - ma * h)] + y[(mb - seg0) * L + (n - mb * h)];
+}
+
+// mask[k] = 1 for every k within half_width of a sample with |xw| > thr
+__global__ void k_gate_mark(const float *__restrict__ xw, int64_t T, float thr, int half_width,
+                            uint8_t *__restrict__ mask) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= T || !(fabsf(xw[n]) > thr)) return;
+  const int64_t a = n - half_width < 0 ? 0 : n - half_width;
+  const int64_t e = n + half_width + 1 > T ? T : n + half_width + 1;
+  for (int64_t k = a; k < e; ++k) mask[k] = 1;
+}
+
+__global__ void k_gate_apply(const float *__restrict__ xw, const uint8_t *__restrict__ mask, int64_t T,
+                             float *__restrict__ out, unsigned long long *__restrict__ count) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool g = n < T && mask[n];
+  if (n < T) out[n] = g ? 0.f : xw[n];
+  const uint64_t m = __ballot(g);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, (unsigned long long)__popcll(m));
+}
+
 // ---------------------------------------------------------- coincidence
 // Pairs of triggers of two detectors with the same (bank, template) whose
 // peak samples differ by at most max_dt (Sec. II.A, the coincidence
@@ -1181,6 +1297,29 @@ hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_e
     case LLOID_BF16: k_xi2<__bf16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, thr); break;
     case LLOID_F32: k_xi2<float><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, thr); break;
     default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_condition(const float *x, int64_t T, int L, bool estimate, double f0, float *parts,
+                            double *psd, float *gain, float *y, float *xw, float gate_thr, int gate_half,
+                            uint8_t *mask, float *out, unsigned long long *count, hipStream_t s) {
+  int lg = 0;
+  while ((1 << lg) < L) ++lg;
+  const size_t lds = (size_t)2 * L * sizeof(float2);
+  const int nf = L / 2 + 1;
+  if (estimate) {
+    const int64_t nseg = (T - L) / (L / 2) + 1;
+    k_cond_segment<false><<<(unsigned)nseg, 256, lds, s>>>(x, T, L, lg, 0, nullptr, parts, nullptr);
+    k_psd_mean<<<blocks_for(nf, 256), 256, 0, s>>>(parts, nseg, L, f0, psd);
+  }
+  k_psd_gain<<<blocks_for(nf, 256), 256, 0, s>>>(psd, nf, f0, gain);
+  const int64_t nseg_w = (2 * (T - 1)) / L + 2;   // segments -1 .. floor(2 (T - 1) / L)
+  k_cond_segment<true><<<(unsigned)nseg_w, 256, lds, s>>>(x, T, L, lg, -1, gain, nullptr, y);
+  k_overlap_add<<<blocks_for(T, 256), 256, 0, s>>>(y, T, L, -1, gate_thr > 0.f ? xw : out);
+  if (gate_thr > 0.f) {
+    k_gate_mark<<<blocks_for(T, 256), 256, 0, s>>>(xw, T, gate_thr, gate_half, mask);
+    k_gate_apply<<<blocks_for(T, 256), 256, 0, s>>>(xw, mask, T, out, count);
   }
   return hipGetLastError();
 }

@@ -65,6 +65,12 @@ class lloid_peaks(ctypes.Structure):
                 ("phase", ctypes.c_void_p), ("n_windows", ctypes.c_int64)]
 
 
+class lloid_condition_opts(ctypes.Structure):
+    _fields_ = [("seg_len", ctypes.c_int32), ("gate_half_width", ctypes.c_int32),
+                ("gate_threshold", ctypes.c_float), ("reserved", ctypes.c_int32),
+                ("psd", ctypes.POINTER(ctypes.c_double))]
+
+
 class lloid_stream_opts(ctypes.Structure):
     _fields_ = [("n_detectors", ctypes.c_int32), ("min_rate_hz", ctypes.c_int32),
                 ("max_windows_per_tick", ctypes.c_int32), ("use_graph", ctypes.c_int32),
@@ -110,6 +116,8 @@ def _load():
         "lloid_bank_destroy": ([vp], ctypes.c_int),
         "lloid_filter": ([vp, i32, vp, ctypes.c_int, i64, ctypes.POINTER(lloid_trigger_opts), vp, i64,
                           ctypes.POINTER(i64), vp, ctypes.POINTER(lloid_peaks)], ctypes.c_int),
+        "lloid_condition": ([vp, i32, vp, ctypes.c_int, i64, ctypes.POINTER(lloid_condition_opts), vp, vp,
+                             ctypes.POINTER(i64)], ctypes.c_int),
         "lloid_coincide": ([vp, vp, i64, vp, i64, i64, vp, i64, ctypes.POINTER(i64), vp], ctypes.c_int),
         "lloid_filter_batch": ([ctypes.POINTER(vp), i32, i32, vp, ctypes.c_int, i64,
                                 ctypes.POINTER(lloid_trigger_opts), vp, i64, ctypes.POINTER(i64),
@@ -156,7 +164,7 @@ def exported_symbols():
             "lloid_filter", "lloid_filter_batch", "lloid_ctx_set_chunk_bytes",
             "lloid_stream_create", "lloid_stream_admit", "lloid_stream_remove", "lloid_stream_push",
             "lloid_stream_poll", "lloid_stream_flush", "lloid_stream_stats_get", "lloid_stream_destroy",
-            "lloid_coincide"]
+            "lloid_coincide", "lloid_condition"]
 
 
 def lloid_version() -> str:
@@ -248,6 +256,37 @@ class FilterResult:
     peak_sample: np.ndarray | None = None
     peak_phase: np.ndarray | None = None
     snr: object = None
+
+
+def lloid_condition(ctx, full_rate_hz: int, strain, seg_len: int, gate_threshold: float = 0.0,
+                    gate_half_width: int = 0, psd=None, out=None):
+    """Whiten and gate one block of strain (numpy float64/float32, or a torch
+    tensor).  psd: None (estimate it from the block) or [seg_len/2 + 1] float64.
+    Returns (conditioned float32 strain, PSD used, samples gated); out may be a
+    preallocated float32 numpy array or device tensor of n values."""
+    if isinstance(strain, np.ndarray):
+        strain = np.ascontiguousarray(strain)
+        dt = LLOID_F64 if strain.dtype == np.float64 else LLOID_F32 if strain.dtype == np.float32 else None
+    else:
+        import torch
+        dt = {torch.float64: LLOID_F64, torch.float32: LLOID_F32}.get(strain.dtype)
+    if dt is None:
+        raise LloidError(LLOID_EINVAL, "strain must be float64 or float32")
+    n = strain.shape[0]
+    keep = None
+    opts = lloid_condition_opts(int(seg_len), int(gate_half_width), float(gate_threshold), 0, None)
+    if psd is not None:
+        keep = np.ascontiguousarray(psd, dtype=np.float64)
+        if keep.shape != (seg_len // 2 + 1,):
+            raise ValueError("psd must have seg_len / 2 + 1 values")
+        opts.psd = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if out is None:
+        out = np.empty(n, dtype=np.float32)
+    psd_out = np.empty(seg_len // 2 + 1, dtype=np.float64)
+    gated = ctypes.c_int64(0)
+    _check(_lib.lloid_condition(ctx, int(full_rate_hz), _ptr(strain), dt, n, ctypes.byref(opts), _ptr(out),
+                                psd_out.ctypes.data, ctypes.byref(gated)))
+    return out, psd_out, int(gated.value)
 
 
 def lloid_coincide(ctx, a, b, max_dt: int, cap: int | None = None, background: bool = False):

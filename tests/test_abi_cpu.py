@@ -57,6 +57,8 @@ int main(void) {
   printf("lloid_stream_opts %zu\\n", sizeof(lloid_stream_opts));
   printf("lloid_stream_stats %zu\\n", sizeof(lloid_stream_stats));
   printf("lloid_coinc %zu\\n", sizeof(lloid_coinc));
+  printf("lloid_condition_opts %zu\\n", sizeof(lloid_condition_opts));
+  P(lloid_condition_opts, gate_threshold) P(lloid_condition_opts, psd)
   P(lloid_coinc, bank) P(lloid_coinc, template_id) P(lloid_coinc, snr_net) P(lloid_coinc, dt)
   P(lloid_stream_opts, use_graph) P(lloid_stream_opts, hbm_budget) P(lloid_stream_opts, trig)
   P(lloid_stream_stats, bytes_in_use) P(lloid_stream_stats, graph_replays)
@@ -75,7 +77,7 @@ int main(void) {
     mirror = {"lloid_slice": lloid.lloid_slice, "lloid_bank_desc": lloid.lloid_bank_desc,
               "lloid_bank_info": lloid.lloid_bank_info, "lloid_trigger_opts": lloid.lloid_trigger_opts,
               "lloid_peaks": lloid.lloid_peaks, "lloid_stream_opts": lloid.lloid_stream_opts,
-              "lloid_stream_stats": lloid.lloid_stream_stats}
+              "lloid_stream_stats": lloid.lloid_stream_stats, "lloid_condition_opts": lloid.lloid_condition_opts}
     for name, cls in mirror.items():
         assert int(got[name]) == ctypes.sizeof(cls), name
     assert int(got["lloid_trigger"]) == lloid.TRIGGER_DTYPE.itemsize
@@ -93,6 +95,8 @@ int main(void) {
     assert int(got["lloid_bank_info.device_bytes"]) == lloid.lloid_bank_info.device_bytes.offset
     for f in ("use_graph", "hbm_budget", "trig"):
         assert int(got[f"lloid_stream_opts.{f}"]) == getattr(lloid.lloid_stream_opts, f).offset, f
+    for f in ("gate_threshold", "psd"):
+        assert int(got[f"lloid_condition_opts.{f}"]) == getattr(lloid.lloid_condition_opts, f).offset, f
     for f in ("bytes_in_use", "graph_replays"):
         assert int(got[f"lloid_stream_stats.{f}"]) == getattr(lloid.lloid_stream_stats, f).offset, f
 
