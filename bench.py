@@ -14,7 +14,8 @@ Prints one JSON line: whole-job template-samples of SNR per second, the
 roofline of the dominant kernel (device time from HIP events on the
 library's stream over the timed steps), the plain FP32 path beside it, the
 same path with every trigger's xi2 signal-consistency value (bank
-autocorrelations over 2K + 1 lags), the coincidence of the two detectors'
+autocorrelations over 2K + 1 lags), the conditioning of one detector's
+block (PSD, whitening, gating), the coincidence of the two detectors'
 triggers, and the FP64 oracle timed on the host cores on a bounded sample.
 """
 
@@ -332,6 +333,7 @@ def main():
                     help="multirate_c1: lags K on each side of the signal-consistency path (2K + 1 samples)")
     ap.add_argument("--xi2-steps", type=int, default=3, help="timed steps of the path with xi2 (0: skip)")
     ap.add_argument("--coinc-reps", type=int, default=5, help="timed coincidence calls on the last triggers (0: skip)")
+    ap.add_argument("--cond-reps", type=int, default=5, help="timed conditioning calls on one detector (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -411,6 +413,22 @@ def main():
         out["f32_path"] = {"value": round(v32, 1), "ms_per_step": round(w32 / args.f32_steps * 1e3, 3),
                            "speedup_of_headline": round(value / v32, 2),
                            "roofline_mix": roofline_entry("mfma", work["mix"][1], ms / max(calls, 1), "f32")}
+    if args.cond_reps:
+        # conditioning of one detector's block (PSD estimate, whitening, gating)
+        # from and to HBM, 2 s segments
+        L = 4096
+        dout = torch.empty(wl.n_samples, dtype=torch.float32, device="cuda")
+        lloid.lloid_condition(ctx, f0, xs[0], L, gate_threshold=50.0, gate_half_width=512, out=dout)
+        torch.cuda.synchronize()
+        t0c = time.perf_counter()
+        for _ in range(args.cond_reps):
+            _, _, n_gated = lloid.lloid_condition(ctx, f0, xs[0], L, gate_threshold=50.0, gate_half_width=512,
+                                                  out=dout)
+        torch.cuda.synchronize()
+        msc = (time.perf_counter() - t0c) / args.cond_reps * 1e3
+        out["conditioning"] = {"seg_len": L, "samples": wl.n_samples, "ms_per_call": round(msc, 3),
+                               "samples_per_s": round(wl.n_samples / msc * 1e3, 1), "gated": n_gated,
+                               "timing": "host wall time of the call (device strain in and out)"}
     if args.coinc_reps:
         # coincidence of the two detectors' triggers (same template, within the
         # light travel time: 10 ms, 21 samples at 2048 Hz), lists resident in HBM
