@@ -562,6 +562,7 @@ void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, 
   m.peak_dt = bb.pdt;
   m.peak_si = bb.psi;
   m.peak_xi = bb.pxi;
+  m.peak_z = b->acorr ? bb.pz : nullptr;
   m.acorr = b->acorr;
   m.acorr_half = b->acorr_half;
   m.snr = snr;
@@ -605,6 +606,8 @@ void lloid::number_jobs(std::vector<FirJob> &fj, std::vector<UpJob> *uj, std::ve
     it += m.nw >= 8 ? ceil_div(m.nw, 8) * 8 * m.n_rtiles : round_up(m.nw * m.n_rtiles, 8);
     m.e0 = e;
     e += (int64_t)m.n_templates * m.nw;
+    m.x0 = n.windows;
+    n.windows += m.nw;
     if (m.acorr) n.xi2 = true;
   }
   n.mix = it;
@@ -630,7 +633,7 @@ lloid_status lloid::launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dt
   HIP_TRY(mark(LLOID_STAGE_MIX, 1));
   HIP_TRY(mark(LLOID_STAGE_PHASE, 0));
   HIP_TRY(launch_peak_phase(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.entries, phase_thr, st));
-  if (n.xi2) HIP_TRY(launch_xi2(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.entries, trig_thr, st));
+  if (n.xi2) HIP_TRY(launch_xi2(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.windows, trig_thr, st));
   HIP_TRY(mark(LLOID_STAGE_PHASE, 1));
   return LLOID_OK;
 }
@@ -741,6 +744,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     add(tab, 4);
     add(tab, 4);
     add(tab, 4);
+    add(tab, 8);
     const int64_t ops = chunk_n + 2 * operand_margin(banks[i]);
     add((size_t)ops * banks[i]->kcat, esz);
     for (const auto &sl : banks[i]->slices)
@@ -775,6 +779,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     bw[i].pdt = cv.take<float>(tab);
     bw[i].psi = cv.take<float>(tab);
     bw[i].pxi = cv.take<float>(tab);
+    bw[i].pz = cv.take<float2>(tab);
     bw[i].ld_peak = W;
     bw[i].w_base = 0;
     const int64_t ops = chunk_n + 2 * operand_margin(banks[i]);

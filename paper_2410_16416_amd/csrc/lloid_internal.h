@@ -93,9 +93,11 @@ struct MixJob {
   float *peak_phase;
   float *peak_dt, *peak_si;   // sub-sample peak offset and value (triggers only)
   float *peak_xi;             // signal-consistency value (triggers only; banks with lags)
+  float2 *peak_z;             // z at the peak (scaled), written with the phase; banks with lags
   const float *acorr;         // [n_templates][2 acorr_half + 1] (re, im) autocorrelation, or NULL
   float *snr;            // optional [F][snr_ld][2], column n - snr_abs0
   int64_t ocat_abs0, n_end, w0, nw, win_p, win_q, ld_peak, w_base, snr_ld, snr_abs0, item0, e0;
+  int64_t x0;                 // first (job, window) item of this job in the signal-consistency launch
   float inv_scale;
   int rows, kcat, n_templates, n_rtiles, acorr_half;
 };
@@ -175,8 +177,8 @@ hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_
 hipError_t launch_peak_phase(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float phase_thr,
                              hipStream_t s);
 // Signal-consistency value at the peaks with |z| >= thr of the jobs that carry
-// autocorrelations.
-hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float thr, hipStream_t s);
+// autocorrelations; one workgroup per (job, window).
+hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_windows, float thr, hipStream_t s);
 // Trigger compaction: counts, offsets and records (job-major, template, window);
 // counts holds trig_blocks(n_elems) slots.
 hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems, float thr, int64_t *counts,
@@ -268,6 +270,7 @@ struct BankBufs {
   std::vector<std::vector<void *>> low;  // per slice at level > 0: FIR output, then each
                                          // interpolation hop's output except the last
   float *psnr = nullptr, *pphase = nullptr, *pdt = nullptr, *psi = nullptr, *pxi = nullptr;
+  float2 *pz = nullptr;            // z at each peak, for the signal-consistency value
   int64_t *pn = nullptr;
   int64_t ld_peak = 0, w_base = 0; // peak tables [F][ld_peak], column w - w_base
 };
@@ -286,6 +289,7 @@ constexpr int kMaxHops = 4;        // interpolation hops of a level-7 slice: x2,
 
 struct StageItems {
   int64_t fir = 0, mix = 0, entries = 0;
+  int64_t windows = 0;             // (job, window) pairs: workgroups of the signal-consistency launch
   bool xi2 = false;                // some mixing job carries autocorrelations
   int64_t up[kMaxHops] = {};       // items of each interpolation hop
 };

@@ -11,6 +11,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdlib>
 #include <type_traits>
 
@@ -664,163 +665,194 @@ __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ j
   jb.peak_phase[o] = atan2f(im[1], re[1]);
   jb.peak_dt[o] = dt;
   jb.peak_si[o] = v;
+  if (jb.peak_z) jb.peak_z[o] = make_float2(re[1] * jb.inv_scale, im[1] * jb.inv_scale);
 }
 
 // Signal-consistency value at each trigger peak (Sec. II.A computes phase and
 // xi^2 for every trigger):
 //   xi2 = sum_k |z[n* + k] - z[n*] R[k]|^2 / sum_k (2 - 2 |R[k]|^2)
-// over the lags k = -K..K with 0 <= n* + k < n_end, z recomputed like the
-// phase (mixing rows 2i, 2i+1 against operand rows; a chunk's operand holds K
-// extra samples on each side).  A wave takes kXiPerWave consecutive entries
-// (few, so that the triggers, about one in eight entries, spread evenly over
-// the waves); those at or above the threshold in jobs with autocorrelations
-// are then handled one at a time by the whole wave: first
-// z[n*] over all 64 lanes, then 8 teams of 8 lanes, kXiLags lags per team and
-// pass, each team's lanes splitting K into 16-byte reads and reducing by
-// shuffles.  The kernel is bound by the latency of those reads (each trigger
-// reads 2K + 1 operand rows): the lags per pass are the reads in flight.
-constexpr int kXiPerWave = 8, kXiPerBlock = 4 * kXiPerWave;
-constexpr int kXiLags = 8;   // lags per team and pass
+// over the lags k = -K..K with 0 <= n* + k < n_end.  One workgroup per (job,
+// window) lists the window's triggers in LDS and sorts them by peak sample;
+// each wave takes groups of 16 consecutive triggers and recomputes their z
+// (32 mixing rows: cos and sin of 16 templates) over the samples their lags
+// reach, 32 samples at a time, as MFMA tiles Z = M_rows * Ocat^T (a chunk's
+// operand holds K extra samples on each side).  The tile's epilogue adds
+// each lane's lags to its eight triggers' sums; z[n*] comes from the phase
+// kernel.  Sorting keeps a group's lags close together: the samples a group
+// covers are about its spread of peaks plus 2K.
 
-// acc + the dot product of two 16-byte vectors of T, FP32 accumulation: packed
-// two-element dot instructions for the 16-bit types (their products are exact
-// in FP32), FMAs for FP32.
-template <typename T> __device__ __forceinline__ float dot16(uint4 x, uint4 y, float acc);
-template <> __device__ __forceinline__ float dot16<_Float16>(uint4 x, uint4 y, float acc) {
-  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-  const unsigned xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {y.x, y.y, y.z, y.w};
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2, xs[q]), __builtin_bit_cast(h2, ys[q]), acc, false);
-  return acc;
-}
-template <> __device__ __forceinline__ float dot16<__bf16>(uint4 x, uint4 y, float acc) {
-  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
-  const unsigned xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {y.x, y.y, y.z, y.w};
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(b2, xs[q]), __builtin_bit_cast(b2, ys[q]), acc, false);
-  return acc;
-}
-template <> __device__ __forceinline__ float dot16<float>(uint4 x, uint4 y, float acc) {
-  acc = fmaf(__uint_as_float(x.x), __uint_as_float(y.x), acc);
-  acc = fmaf(__uint_as_float(x.y), __uint_as_float(y.y), acc);
-  acc = fmaf(__uint_as_float(x.z), __uint_as_float(y.z), acc);
-  return fmaf(__uint_as_float(x.w), __uint_as_float(y.w), acc);
-}
+constexpr int kXiThreads = 256;
+constexpr int kXiList = 1024;   // triggers listed per pass over a window's templates
+constexpr int kXiGroup = 16;    // triggers per MFMA row tile
 
 template <typename T>
-__device__ __forceinline__ float2 z_team(const uint4 *__restrict__ mc, const uint4 *__restrict__ ms,
-                                         const uint4 *__restrict__ row, int nvec, int sub, int stride) {
-  float re = 0.f, im = 0.f;
-  for (int k = sub; k < nvec; k += stride) {
-    const uint4 a = row[k];
-    re = dot16<T>(mc[k], a, re);
-    im = dot16<T>(ms[k], a, im);
-  }
-  for (int off = 1; off < stride; off <<= 1) {
-    re += __shfl_xor(re, off);
-    im += __shfl_xor(im, off);
-  }
-  return make_float2(re, im);
-}
+__global__ __launch_bounds__(kXiThreads) void k_xi2(const MixJob *__restrict__ jobs, int n_jobs, float thr) {
+  typedef Op<T> O;
+  __shared__ int64_t l_key[kXiList];   // (n* - window start) << 32 | template
+  __shared__ int l_count;
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_xi2(const MixJob *__restrict__ jobs, int n_jobs, int64_t entries,
-                                             float thr) {
-  constexpr int TEAM = 8, EPV = 16 / (int)sizeof(T);
-  const int lane = threadIdx.x & 63, team = lane / TEAM, sub = lane % TEAM;
-  // XCD-contiguous blocks: XCD x (= blockIdx % 8) takes one run of blocks,
-  // so a window's triggers (window-major entries) share that XCD's L2
-  const int64_t n_blk = (entries + kXiPerBlock - 1) / kXiPerBlock;
-  const int64_t per_xcd = (n_blk + 7) / 8;
-  const int64_t lb = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (lb >= n_blk) return;
-  const int64_t e = lb * kXiPerBlock + (threadIdx.x >> 6) * kXiPerWave + lane;
-  int j = 0;
-  int64_t o = 0, i = 0;
-  bool f = false;
-  if (lane < kXiPerWave && e < entries) {
-    int lo = 0, hi = n_jobs - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (jobs[mid].e0 <= e) lo = mid;
-      else hi = mid - 1;
-    }
-    j = lo;
-    const MixJob &jb = jobs[j];
-    // window-major within the job: consecutive entries are templates of one window
-    const int64_t le = e - jb.e0;
-    const int64_t wl = le / jb.n_templates;
-    i = le - wl * jb.n_templates;
-    o = i * jb.ld_peak + (jb.w0 + wl - jb.w_base);
-    f = jb.acorr != nullptr && jb.peak_snr[o] >= thr;
+  // job and window of this workgroup: the last job with x0 <= blockIdx.x
+  const int64_t item = blockIdx.x;
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].x0 <= item) lo = mid;
+    else hi = mid - 1;
   }
-  uint64_t pending = __ballot(f);
-  while (pending) {
-    const int src = __builtin_ctzll(pending);
-    pending &= pending - 1;
-    const int jj = __shfl(j, src);
-    const int64_t oo = __shfl(o, src), ii = __shfl(i, src);
-    const MixJob &jb = jobs[jj];
-    const int K = jb.acorr_half, kcat = jb.kcat, nvec = kcat / EPV;
-    const int64_t ns = jb.peak_n[oo];
-    const uint4 *mc = (const uint4 *)((const T *)jb.mix + (2 * ii) * (int64_t)kcat);
-    const uint4 *ms = mc + nvec;
-    const uint4 *base = (const uint4 *)((const T *)jb.ocat + (ns - jb.ocat_abs0) * (int64_t)kcat);
-    const float2 *R = (const float2 *)jb.acorr + ii * (2 * K + 1);
-    const float sc = jb.inv_scale;
-    float2 zs = z_team<T>(mc, ms, base, nvec, lane, 64);
-    zs.x *= sc;
-    zs.y *= sc;
-    // a team takes kXiLags lags per pass (lags team + 8 u), so that the reads of
-    // kXiLags operand rows and one pair of mixing vectors are in flight at once;
-    // lags outside the data read the peak's row and are not counted
-    float num = 0.f, den = 0.f;
-    for (int kb = 0; kb < 2 * K + 1; kb += 64 / TEAM * kXiLags) {
-      const uint4 *rows[kXiLags];
-      bool ok[kXiLags];
-#pragma unroll
-      for (int u = 0; u < kXiLags; ++u) {
-        const int kk = kb + team + (64 / TEAM) * u;
-        const int64_t n = ns + kk - K;
-        ok[u] = kk < 2 * K + 1 && n >= 0 && n < jb.n_end;
-        rows[u] = base + (ok[u] ? (int64_t)(kk - K) * nvec : 0);
+  const MixJob &jb = jobs[lo];
+  const int64_t wl = item - jb.x0;
+  if (!jb.acorr || wl >= jb.nw) return;   // uniform over the workgroup
+  const int64_t w = jb.w0 + wl;
+  const int64_t ws = (w * jb.win_p) / jb.win_q;
+  const int K = jb.acorr_half, kcat = jb.kcat, F = jb.n_templates;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const T *mix = (const T *)jb.mix;
+  const T *ocat = (const T *)jb.ocat;
+  const float2 *acorr = (const float2 *)jb.acorr;
+  const float sc = jb.inv_scale;
+  const int nks = kcat / O::KS;
+
+  for (int i0 = 0; i0 < F;) {
+    // ---- list the triggers among templates [i0, ...), at most kXiList
+    if (threadIdx.x == 0) l_count = 0;
+    __syncthreads();
+    int i_next = F;
+    for (int ib = i0; ib < F; ib += kXiThreads) {
+      const int i = ib + (int)threadIdx.x;
+      const int64_t o = (int64_t)i * jb.ld_peak + (w - jb.w_base);
+      const bool f = i < F && jb.peak_snr[o] >= thr;
+      const uint64_t m = __ballot(f);
+      int base = 0;
+      if (lane == 0 && m) base = atomicAdd(&l_count, (int)__popcll(m));
+      base = __shfl(base, 0);
+      if (f) {
+        const int at = base + (int)__popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull));
+        if (at < kXiList) l_key[at] = ((jb.peak_n[o] - ws) << 32) | (int64_t)i;
       }
-      float re[kXiLags], im[kXiLags];
+      __syncthreads();
+      const int cnt = l_count;
+      __syncthreads();
+      if (cnt > kXiList) {   // full: this block's triggers wait for the next pass
+        i_next = ib;
+        break;
+      }
+    }
+    int n_list = min(l_count, kXiList);
+    if (i_next < F) {
+      // keep the triggers of templates below i_next (every one of them fits)
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int k = 0;
+        for (int t = 0; t < n_list; ++t)
+          if ((int)(l_key[t] & 0xffffffff) < i_next) l_key[k++] = l_key[t];
+        l_count = k;
+      }
+      __syncthreads();
+      n_list = l_count;
+    }
+    // ---- bitonic sort of the keys by peak sample (padding sorts last)
+    int np2 = 1;
+    while (np2 < n_list) np2 <<= 1;
+    for (int t = n_list + (int)threadIdx.x; t < np2; t += kXiThreads) l_key[t] = INT64_MAX;
+    __syncthreads();
+    for (int size = 2; size <= np2; size <<= 1)
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int t = threadIdx.x; t < np2 / 2; t += kXiThreads) {
+          const int a = 2 * stride * (t / stride) + (t % stride), b2 = a + stride;
+          const bool up = (a & size) == 0;
+          const int64_t x = l_key[a], y = l_key[b2];
+          if ((x > y) == up) {
+            l_key[a] = y;
+            l_key[b2] = x;
+          }
+        }
+        __syncthreads();
+      }
+
+    // ---- groups of kXiGroup triggers, one wave each
+    const int n_groups = (n_list + kXiGroup - 1) / kXiGroup;
+    for (int g = wave; g < n_groups; g += kXiThreads / 64) {
+      const int t0 = g * kXiGroup, nt = min(kXiGroup, n_list - t0);
+      // A rows: lane row rr = lane % 32 is cos (even) or sin (odd) of trigger rr / 2
+      const int tr = (lane & 31) >> 1;
+      const int64_t ir = l_key[t0 + (tr < nt ? tr : 0)] & 0xffffffff;
+      const T *arow = mix + (2 * ir + (lane & 1)) * (int64_t)kcat + (lane >> 5) * O::VEC;
+      // the eight triggers of this lane's accumulator pairs: rows 8 (e/4) + 4 (lane/32) + e%4
+      int64_t ns[8], ii[8];
+      float2 zs[8];
+      float num[8], den[8];
 #pragma unroll
-      for (int u = 0; u < kXiLags; ++u) re[u] = im[u] = 0.f;
-      for (int k = sub; k < nvec; k += TEAM) {
-        const uint4 c = mc[k], d = ms[k];
-        uint4 a[kXiLags];
+      for (int p = 0; p < 8; ++p) {
+        const int tq = 4 * (p >> 1) + 2 * (lane >> 5) + (p & 1);
+        const int64_t key = l_key[t0 + (tq < nt ? tq : 0)];
+        ns[p] = tq < nt ? ws + (key >> 32) : INT64_MIN / 4;   // absent triggers reach no lag
+        ii[p] = key & 0xffffffff;
+        const float2 z = jb.peak_z[ii[p] * jb.ld_peak + (w - jb.w_base)];
+        zs[p] = z;
+        num[p] = 0.f;
+        den[p] = 0.f;
+      }
+      // samples the group's lags reach, inside the data
+      int64_t a0 = ws + (l_key[t0] >> 32) - K, a1 = ws + (l_key[t0 + nt - 1] >> 32) + K + 1;
+      if (a0 < 0) a0 = 0;
+      if (a1 > jb.n_end) a1 = jb.n_end;
+      for (int64_t s0 = a0; s0 < a1; s0 += 32) {
+        const int64_t n = s0 + (lane & 31);
+        const int64_t nb = n < a1 ? n : a1 - 1;
+        const T *brow = ocat + (nb - jb.ocat_abs0) * (int64_t)kcat + (lane >> 5) * O::VEC;
+        // two accumulators (even and odd k-steps) halve the MFMA dependency chain
+        f32x16 acc, acc2;
 #pragma unroll
-        for (int u = 0; u < kXiLags; ++u) a[u] = rows[u][k];
+        for (int e = 0; e < 16; ++e) acc[e] = acc2[e] = 0.f;
+        constexpr int U = 8;
+        int ks = 0;
+        for (; ks + U <= nks; ks += U) {
+          typename O::vec af[U], bf[U];
 #pragma unroll
-        for (int u = 0; u < kXiLags; ++u) {
-          re[u] = dot16<T>(c, a[u], re[u]);
-          im[u] = dot16<T>(d, a[u], im[u]);
+          for (int u = 0; u < U; ++u) {
+            af[u] = *(const typename O::vec *)(arow + (ks + u) * O::KS);
+            bf[u] = *(const typename O::vec *)(brow + (ks + u) * O::KS);
+          }
+#pragma unroll
+          for (int u = 0; u < U; u += 2) {
+            acc = O::mfma(af[u], bf[u], acc);
+            acc2 = O::mfma(af[u + 1], bf[u + 1], acc2);
+          }
+        }
+        for (; ks < nks; ++ks)
+          acc = O::mfma(*(const typename O::vec *)(arow + ks * O::KS), *(const typename O::vec *)(brow + ks * O::KS),
+                        acc);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] += acc2[e];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          const int64_t lag = n - ns[p];
+          if (n < a1 && lag >= -K && lag <= K) {
+            const float2 r = acorr[ii[p] * (2 * K + 1) + K + lag];
+            const float dr = acc[2 * p] * sc - (zs[p].x * r.x - zs[p].y * r.y);
+            const float di = acc[2 * p + 1] * sc - (zs[p].x * r.y + zs[p].y * r.x);
+            num[p] += dr * dr + di * di;
+            den[p] += 2.f - 2.f * (r.x * r.x + r.y * r.y);
+          }
         }
       }
+      // sum each trigger's terms over the 32 lanes (samples) of its half-wave
 #pragma unroll
-      for (int u = 0; u < kXiLags; ++u) {
-        for (int off = 1; off < TEAM; off <<= 1) {
-          re[u] += __shfl_xor(re[u], off);
-          im[u] += __shfl_xor(im[u], off);
+      for (int p = 0; p < 8; ++p)
+        for (int off = 1; off < 32; off <<= 1) {
+          num[p] += __shfl_xor(num[p], off);
+          den[p] += __shfl_xor(den[p], off);
         }
-        if (ok[u] && sub == 0) {
-          const float2 r = R[kb + team + (64 / TEAM) * u];
-          const float dr = re[u] * sc - (zs.x * r.x - zs.y * r.y);
-          const float di = im[u] * sc - (zs.x * r.y + zs.y * r.x);
-          num += dr * dr + di * di;
-          den += 2.f - 2.f * (r.x * r.x + r.y * r.y);
+      if ((lane & 31) == 0) {
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          const int tq = 4 * (p >> 1) + 2 * (lane >> 5) + (p & 1);
+          if (tq < nt) jb.peak_xi[ii[p] * jb.ld_peak + (w - jb.w_base)] = den[p] > 0.f ? num[p] / den[p] : 0.f;
         }
       }
     }
-    for (int off = 1; off < 64; off <<= 1) {
-      num += __shfl_xor(num, off);
-      den += __shfl_xor(den, off);
-    }
-    if (lane == src) jb.peak_xi[oo] = den > 0.f ? num / den : 0.f;
+    __syncthreads();
+    i0 = i_next;
   }
 }
 
@@ -1289,13 +1321,13 @@ hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems,
   return hipGetLastError();
 }
 
-hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float thr, hipStream_t s) {
-  if (n_entries <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)(8 * ((blocks_for(n_entries, kXiPerBlock) + 7) / 8));
+hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_windows, float thr, hipStream_t s) {
+  if (n_windows <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)n_windows;   // one workgroup per (job, window)
   switch (t) {
-    case LLOID_F16: k_xi2<_Float16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, thr); break;
-    case LLOID_BF16: k_xi2<__bf16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, thr); break;
-    case LLOID_F32: k_xi2<float><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, thr); break;
+    case LLOID_F16: k_xi2<_Float16><<<blocks, kXiThreads, 0, s>>>(jobs, n_jobs, thr); break;
+    case LLOID_BF16: k_xi2<__bf16><<<blocks, kXiThreads, 0, s>>>(jobs, n_jobs, thr); break;
+    case LLOID_F32: k_xi2<float><<<blocks, kXiThreads, 0, s>>>(jobs, n_jobs, thr); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -90,7 +90,7 @@ int64_t scratch_bytes(const lloid_stream *s, const lloid_bank *b) {
   for (const auto &sl : b->slices)
     if (sl.level > 0)
       for (int64_t ld : low_ld(ts, sl.level)) per += (int64_t)sl.lp * ld * (int64_t)low_esz(b->compute) + 256;
-  per += (int64_t)b->n_templates * s->max_w * (28 + (int64_t)sizeof(lloid_trigger)) + 4096;
+  per += (int64_t)b->n_templates * s->max_w * (36 + (int64_t)sizeof(lloid_trigger)) + 4096;
   return per * s->n_det;
 }
 
@@ -223,6 +223,7 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
       add((size_t)b->n_templates * nw, 4);
       add((size_t)b->n_templates * nw, 4);
       add((size_t)b->n_templates * nw, 4);
+      add((size_t)b->n_templates * nw, 8);
     }
     rows += (int64_t)b->n_templates * s->n_det;
   }
@@ -258,6 +259,7 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
       bb.pdt = cv.take<float>((size_t)b->n_templates * nw);
       bb.psi = cv.take<float>((size_t)b->n_templates * nw);
       bb.pxi = cv.take<float>((size_t)b->n_templates * nw);
+      bb.pz = cv.take<float2>((size_t)b->n_templates * nw);
       bb.ld_peak = nw;
       bb.w_base = wa;
       std::vector<LevelView> lv(s->n_levels);
@@ -315,6 +317,7 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
                                 items.fir, items.mix, items.entries, (int64_t)to.fir, (int64_t)to.mix, to.n_fir,
                                 to.n_mix};
     key.push_back(items.xi2 ? 1 : 0);
+    key.push_back(items.windows);
     for (int h = 0; h < kMaxHops; ++h) {
       key.push_back(items.up[h]);
       key.push_back((int64_t)to.up[h]);
