@@ -8,7 +8,13 @@
  * and summed into one complex SNR series per template, and reduced on the
  * device to per-window SNR peaks; peaks with |SNR| >= threshold (4 by
  * default, Fig. 1 caption) are the triggers, and only they (not the SNR
- * series) come back to the host (Sec. II.B, last paragraph).
+ * series) come back to the host (Sec. II.B, last paragraph).  Each trigger
+ * carries its phase, a sub-sample refinement of its peak and, for banks
+ * given template autocorrelations, its signal-consistency value xi^2.  The
+ * steps around the filter are here too: conditioning of raw strain (PSD,
+ * whitening, gating; lloid_condition) and the coincidence of two detectors'
+ * triggers (lloid_coincide).  Offline blocks go through lloid_filter /
+ * lloid_filter_batch, live strides through the lloid_stream_* calls.
  *
  * Conventions shared by every call:
  *  - Every call returns lloid_status: LLOID_OK (0) or a negative error code.
@@ -331,8 +337,9 @@ typedef struct {
  * strain, ready for lloid_filter).  psd_out: NULL or host [L/2 + 1], the PSD
  * used.  n_gated: NULL or the number of samples zeroed by the gate.
  * EINVAL on a bad length, rate or option, a block shorter than one segment
- * without a PSD, or a non-finite strain sample or PSD value.  Runs on the
- * context's stream and returns when the results are in the caller's buffers. */
+ * without a PSD, or a non-finite PSD value; EDATA if a strain sample is not
+ * finite.  Runs on the context's stream and returns when the results are in
+ * the caller's buffers. */
 lloid_status lloid_condition(lloid_ctx *ctx, int32_t full_rate_hz, const void *strain, lloid_dtype dtype, int64_t n,
                              const lloid_condition_opts *opts, float *out, double *psd_out, int64_t *n_gated);
 

@@ -1015,7 +1015,7 @@ extern "C" lloid_status lloid_condition(lloid_ctx *ctx, int32_t full_rate_hz, co
   if (psd_out) HIP_TRY(hipMemcpyAsync(psd_out, psd, (size_t)nf * 8, hipMemcpyDeviceToHost, st));
   if (host_out) HIP_TRY(hipMemcpyAsync(out, dout, (size_t)n * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (h_bad) return fail(LLOID_EINVAL, "non-finite strain sample");
+  if (h_bad) return fail(LLOID_EDATA, "strain holds a non-finite sample");
   if (n_gated) *n_gated = (int64_t)h_count;
   return LLOID_OK;
   ABI_GUARD_END

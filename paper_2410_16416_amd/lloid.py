@@ -264,15 +264,7 @@ def lloid_condition(ctx, full_rate_hz: int, strain, seg_len: int, gate_threshold
     tensor).  psd: None (estimate it from the block) or [seg_len/2 + 1] float64.
     Returns (conditioned float32 strain, PSD used, samples gated); out may be a
     preallocated float32 numpy array or device tensor of n values."""
-    if isinstance(strain, np.ndarray):
-        strain = np.ascontiguousarray(strain)
-        dt = LLOID_F64 if strain.dtype == np.float64 else LLOID_F32 if strain.dtype == np.float32 else None
-    else:
-        import torch
-        dt = {torch.float64: LLOID_F64, torch.float32: LLOID_F32}.get(strain.dtype)
-    if dt is None:
-        raise LloidError(LLOID_EINVAL, "strain must be float64 or float32")
-    n = strain.shape[0]
+    strain, dt, n = _strain_arg(strain)
     keep = None
     opts = lloid_condition_opts(int(seg_len), int(gate_half_width), float(gate_threshold), 0, None)
     if psd is not None:
@@ -327,16 +319,7 @@ def lloid_filter(bank, detector: int, strain, window=(1, 1), threshold: float = 
     pinned torch uint8 tensor of 48*cap bytes).  snr_out: optional [F, n, 2] float32
     numpy array or torch tensor receiving the complex SNR.
     """
-    if isinstance(strain, np.ndarray):
-        strain = np.ascontiguousarray(strain)
-        dt = LLOID_F64 if strain.dtype == np.float64 else LLOID_F32 if strain.dtype == np.float32 else None
-        n = strain.shape[0]
-    else:
-        import torch
-        dt = {torch.float64: LLOID_F64, torch.float32: LLOID_F32}.get(strain.dtype)
-        n = strain.shape[0]
-    if dt is None:
-        raise LloidError(LLOID_EINVAL, "strain must be float64 or float32")
+    strain, dt, n = _strain_arg(strain)
     info = lloid_bank_query(bank)
     n_templates = info.n_templates
     num, den = window

@@ -92,7 +92,7 @@ def test_condition_errors():
     bad[10] = np.nan
     with pytest.raises(lloid.LloidError) as ei:
         lloid.lloid_condition(ctx(), F0, bad, 256)
-    assert ei.value.status == lloid.LLOID_EINVAL
+    assert ei.value.status == lloid.LLOID_EDATA
 
 
 def test_conditioned_strain_feeds_the_filter():
