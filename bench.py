@@ -36,6 +36,7 @@ PEAK_TFLOPS = {"f16": 2516.6, "bf16": 2516.6, "f32": 157.3}   # dense MFMA, MI35
 PEAK_HBM_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_2410_16416_amd", "csrc", "lloid_kernels.hip")
+TILE_CACHE = os.path.join(ROOT, "paper_2410_16416_amd", "tiles_gfx950.json")
 
 
 def log(msg):
@@ -126,10 +127,15 @@ def cpu_baseline(wl, sample_s: float):
                       f"({os.cpu_count()} host cores visible)"}
 
 
-def run_path(lloid, ctx, wl, xs, compute, steps, warmup, tbufs):
+def run_path(lloid, ctx, wl, xs, compute, steps, warmup, tbufs, args):
     import torch
     bank = lloid.bank_from_svd(ctx, wl.bank, compute)
     try:
+        if compute == args.compute:
+            tiles = pick_tiles(lloid, ctx, [bank], args)
+        else:   # the plain FP32 reference path keeps the default tiles
+            lloid.lloid_ctx_set_tiles(ctx, 0, 0)
+            tiles = {"fir_variant": 0, "mix_variant": 0, "source": "defaults"}
         def step():
             n = 0
             for det, x in enumerate(xs):
@@ -153,7 +159,19 @@ def run_path(lloid, ctx, wl, xs, compute, steps, warmup, tbufs):
         lloid.lloid_ctx_profile(ctx, False)
     finally:
         lloid.lloid_bank_destroy(bank)
-    return wall, n_trig, stages
+    return wall, n_trig, stages, tiles
+
+
+def pick_tiles(lloid, ctx, handles, args):
+    """Tile variants for these banks: the recorded autotuning choice, or a new
+    timing over args.tune_seconds of synthetic strain (recorded in the cache)."""
+    if args.tune_seconds == 0:
+        fv, mv = lloid.lloid_ctx_get_tiles(ctx)
+        return {"fir_variant": fv, "mix_variant": mv, "source": "context (no autotuning)"}
+    seconds = args.tune_seconds if args.tune_seconds > 0 else args.block_seconds
+    (fv, mv), res = lloid.lloid_autotune(ctx, handles, seconds, args.tile_cache)
+    return {"fir_variant": fv, "mix_variant": mv, "source": "timed" if len(res) else "cache",
+            "cache": os.path.relpath(args.tile_cache, ROOT) if args.tile_cache.startswith(ROOT) else args.tile_cache}
 
 
 def batched_work(banks, seconds):
@@ -172,6 +190,7 @@ def bench_batched(args):
     from paper_2410_16416_amd import lloid
     nb = args.banks or 64
     seconds = args.seconds if args.seconds != 1024 else 512
+    args.block_seconds = seconds
     log(f"[bench] batched: generating {nb} banks")
     t0 = time.perf_counter()
     banks = configs.batched_c3_banks(nb)
@@ -182,8 +201,14 @@ def bench_batched(args):
     torch.cuda.init()
     ctx = lloid.lloid_ctx_create(0)
     out = {}
+    tiles = {}
     for compute in [args.compute] + (["f32"] if args.f32_steps and args.compute != "f32" else []):
         hs = [lloid.bank_from_svd(ctx, b, compute) for b in banks]
+        if compute == args.compute:
+            tiles[compute] = pick_tiles(lloid, ctx, hs, args)
+        else:   # the plain FP32 reference path keeps the default tiles
+            lloid.lloid_ctx_set_tiles(ctx, 0, 0)
+            tiles[compute] = {"fir_variant": 0, "mix_variant": 0, "source": "defaults"}
         steps = args.steps if compute == args.compute else args.f32_steps
         nwin = seconds
         cap = sum(b.n_templates for b in banks) * nwin
@@ -227,7 +252,7 @@ def bench_batched(args):
                                    f"and lower, filters 0.5-64 s), 2 detectors x {seconds} s, one launch per stage",
                        "banks": nb, "templates": sum(b.n_templates for b in banks), "detectors": 2,
                        "seconds": seconds, "f0": f0},
-            "paths": out}
+            "tiles": tiles, "paths": out}
 
 
 def bench_serving(args):
@@ -334,6 +359,10 @@ def main():
     ap.add_argument("--xi2-steps", type=int, default=3, help="timed steps of the path with xi2 (0: skip)")
     ap.add_argument("--coinc-reps", type=int, default=5, help="timed coincidence calls on the last triggers (0: skip)")
     ap.add_argument("--cond-reps", type=int, default=5, help="timed conditioning calls on one detector (0: skip)")
+    ap.add_argument("--tune-seconds", type=float, default=-1.0,
+                    help="autotuning of the tile shapes on this much synthetic strain when the cache has no "
+                         "choice for the banks (-1: the workload's block length; 0: default tiles)")
+    ap.add_argument("--tile-cache", default=TILE_CACHE, help="JSON record of autotuned tile shapes")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -357,6 +386,7 @@ def main():
     log(f"[bench] generating workload ({args.seconds} s x 2 detectors)")
     t0 = time.perf_counter()
     wl = configs.multirate_c1(seconds=args.seconds)
+    args.block_seconds = args.seconds
     log(f"[bench] workload ready in {time.perf_counter() - t0:.1f} s: {wl.bank.describe()}")
     torch.cuda.init()
     ctx = lloid.lloid_ctx_create(0)
@@ -369,7 +399,7 @@ def main():
     F, f0 = wl.bank.n_templates, wl.bank.f0
     samples_per_step = F * wl.n_samples * len(xs)
     log(f"[bench] {args.compute}: warmup {args.warmup}, steps {args.steps}")
-    wall, n_trig, stages = run_path(lloid, ctx, wl, xs, args.compute, args.steps, args.warmup, tbufs)
+    wall, n_trig, stages, tiles = run_path(lloid, ctx, wl, xs, args.compute, args.steps, args.warmup, tbufs, args)
     ms_step = wall / args.steps * 1e3
     value = samples_per_step / (wall / args.steps)
     log(f"[bench] {args.compute}: {ms_step:.2f} ms/step, {value:.4g} template-samples/s, stages {stages}")
@@ -397,6 +427,7 @@ def main():
         "triggers_per_step": int(n_trig),
         "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "roofline": dict(roofs[dominant], kernel=dominant),
+        "tiles": tiles,
         "roofline_stages": roofs,
         "p99_stride_latency_ms": None,
     }
@@ -407,7 +438,7 @@ def main():
 
     if args.f32_steps and args.compute != "f32":
         log(f"[bench] plain f32 path: steps {args.f32_steps}")
-        w32, _, st32 = run_path(lloid, ctx, wl, xs, "f32", args.f32_steps, 1, tbufs)
+        w32, _, st32, _ = run_path(lloid, ctx, wl, xs, "f32", args.f32_steps, 1, tbufs, args)
         v32 = samples_per_step / (w32 / args.f32_steps)
         ms, calls = st32["mix"]
         out["f32_path"] = {"value": round(v32, 1), "ms_per_step": round(w32 / args.f32_steps * 1e3, 3),
@@ -453,7 +484,7 @@ def main():
         log(f"[bench] {args.compute} with xi2 over {2 * args.xi2_half + 1} lags: steps {args.xi2_steps}")
         wl.bank.autocorr = bank_autocorrelation(wl.bank, args.xi2_half)
         try:
-            wx, ntx, stx = run_path(lloid, ctx, wl, xs, args.compute, args.xi2_steps, 1, tbufs)
+            wx, ntx, stx, _ = run_path(lloid, ctx, wl, xs, args.compute, args.xi2_steps, 1, tbufs, args)
         finally:
             wl.bank.autocorr = None
         out["xi2_path"] = {"lags": 2 * args.xi2_half + 1, "value": round(samples_per_step / (wx / args.xi2_steps), 1),

@@ -375,6 +375,39 @@ lloid_status lloid_coincide(lloid_ctx *ctx, const lloid_trigger *a, int64_t n_a,
                             int64_t n_b, int64_t max_dt, lloid_coinc *out, int64_t cap, int64_t *n_out,
                             uint8_t *background);
 
+/* ---- tile shapes and their autotuning ----
+ * The FIR and mixing kernels are compiled in a few tile shapes (variants:
+ * FIR 0..2, mixing 0..3; 0 is the default).  Every variant gives
+ * bit-identical results (each output's sum over K runs in the same order);
+ * only the speed differs with the banks' shapes.  A context starts with the
+ * defaults, or the variants named by the environment variables
+ * LLOID_FIR_VARIANT and LLOID_MIX_VARIANT. */
+typedef struct {
+  int32_t fir_variant;
+  int32_t mix_variant;
+  double ms;             /* fastest of two timed lloid_filter_batch calls after a warm-up */
+} lloid_tune_result;
+
+lloid_status lloid_ctx_set_tiles(lloid_ctx *ctx, int32_t fir_variant, int32_t mix_variant);
+lloid_status lloid_ctx_get_tiles(const lloid_ctx *ctx, int32_t *fir_variant, int32_t *mix_variant);
+
+/* Pick the tile variants for a set of banks: time lloid_filter_batch over
+ * `seconds` (0 < seconds <= 4096) of synthetic unit-variance noise on the
+ * device with every variant pair and keep the fastest on the context.
+ *   cache_path: NULL, or a JSON file of earlier choices keyed by device
+ *               architecture, operand type, the banks' shape (count, rows,
+ *               concatenated K, longest filter, rate levels) and the block
+ *               length (rounded up to a power of two; tune with the block
+ *               length the filter calls will use).  A key
+ *               found there is applied without timing (*n_results = 0); a
+ *               new choice is added to the file.
+ *   results:    host, cap entries receiving every timed pair; *n_results is
+ *               the number timed.
+ * EINVAL on a NULL argument, banks of another context, seconds out of range
+ * or a cache file that cannot be written. */
+lloid_status lloid_autotune(lloid_ctx *ctx, lloid_bank *const *banks, int32_t n_banks, double seconds,
+                            const char *cache_path, lloid_tune_result *results, int32_t cap, int32_t *n_results);
+
 /* Device bytes the filter calls of this context may use for the per-chunk
  * operands (the orthogonal SNR of every bank over a run of whole windows);
  * longer blocks are processed in several chunks.  Default 6 GiB. */

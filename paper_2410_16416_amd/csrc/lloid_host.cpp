@@ -2,9 +2,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -94,6 +96,9 @@ extern "C" lloid_status lloid_ctx_create(int device, void *hip_stream, lloid_ctx
   lloid_ctx *c = new lloid_ctx();
   c->device = device;
   c->n_cu = prop.multiProcessorCount;
+  // tile shapes: the defaults, or those named by LLOID_FIR_VARIANT / LLOID_MIX_VARIANT
+  if (const char *v = getenv("LLOID_FIR_VARIANT")) c->fir_variant = std::min(std::max(atoi(v), 0), kFirVariants - 1);
+  if (const char *v = getenv("LLOID_MIX_VARIANT")) c->mix_variant = std::min(std::max(atoi(v), 0), kMixVariants - 1);
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -622,14 +627,14 @@ lloid_status lloid::launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dt
     return ev ? hipEventRecord(ev[2 * (stage - LLOID_STAGE_FIR) + end], st) : hipSuccess;
   };
   HIP_TRY(mark(LLOID_STAGE_FIR, 0));
-  HIP_TRY(launch_fir_jobs(ct, (const FirJob *)(dtab + to.fir), to.n_fir, n.fir, st));
+  HIP_TRY(launch_fir_jobs(ct, ctx->fir_variant, (const FirJob *)(dtab + to.fir), to.n_fir, n.fir, st));
   HIP_TRY(mark(LLOID_STAGE_FIR, 1));
   HIP_TRY(mark(LLOID_STAGE_INTERP, 0));
   for (int h = 0; h < kMaxHops; ++h)
     HIP_TRY(launch_up_jobs(ct, (const UpJob *)(dtab + to.up[h]), to.n_up[h], n.up[h], st));
   HIP_TRY(mark(LLOID_STAGE_INTERP, 1));
   HIP_TRY(mark(LLOID_STAGE_MIX, 0));
-  HIP_TRY(launch_mix_jobs(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.mix, with_snr, st));
+  HIP_TRY(launch_mix_jobs(ct, ctx->mix_variant, (const MixJob *)(dtab + to.mix), to.n_mix, n.mix, with_snr, st));
   HIP_TRY(mark(LLOID_STAGE_MIX, 1));
   HIP_TRY(mark(LLOID_STAGE_PHASE, 0));
   HIP_TRY(launch_peak_phase(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.entries, phase_thr, st));
@@ -715,7 +720,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   const int64_t n_chunks = ceil_div(W, wpc);
   const int64_t chunk_n = std::min<int64_t>(n, win.start(wpc) + 1);   // samples of the longest chunk
 
-  const TileShapes ts(ct);
+  const TileShapes ts(ct, ctx->fir_variant, ctx->mix_variant);
 
   // ---- workspace layout
   const bool host_strain = !is_device_ptr(strain);
@@ -1078,6 +1083,162 @@ extern "C" lloid_status lloid_coincide(lloid_ctx *ctx, const lloid_trigger *a, i
   HIP_TRY(hipStreamSynchronize(st));
   *n_out = h_total;
   if (h_total > cap) return fail(LLOID_ETRUNC, "%lld coincidences, capacity %lld", (long long)h_total, (long long)cap);
+  return LLOID_OK;
+  ABI_GUARD_END
+}
+
+extern "C" lloid_status lloid_ctx_set_tiles(lloid_ctx *ctx, int32_t fir_variant, int32_t mix_variant) {
+  if (!ctx) return fail(LLOID_EINVAL, "NULL context");
+  if (fir_variant < 0 || fir_variant >= kFirVariants || mix_variant < 0 || mix_variant >= kMixVariants)
+    return fail(LLOID_EINVAL, "tile variants must be in [0, %d) and [0, %d)", kFirVariants, kMixVariants);
+  ctx->fir_variant = fir_variant;
+  ctx->mix_variant = mix_variant;
+  return LLOID_OK;
+}
+
+extern "C" lloid_status lloid_ctx_get_tiles(const lloid_ctx *ctx, int32_t *fir_variant, int32_t *mix_variant) {
+  if (!ctx || !fir_variant || !mix_variant) return fail(LLOID_EINVAL, "NULL argument");
+  *fir_variant = ctx->fir_variant;
+  *mix_variant = ctx->mix_variant;
+  return LLOID_OK;
+}
+
+// ---- autotuning of the tile shapes
+namespace {
+
+// Shape class of a bank set on this device: architecture, operand type, the
+// sizes the tiles see (banks, rows, concatenated K, longest filter, levels)
+// and the block length (samples, rounded up to a power of two): short blocks
+// leave most of the GPU idle and can favour other tiles than long ones.
+std::string tune_key(const lloid_ctx *ctx, lloid_bank *const *banks, int nb, int64_t n) {
+  hipDeviceProp_t prop;
+  std::string arch = "gfx";
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+  }
+  int64_t rows = 0, kcat = 0, np = 0;
+  int levels = 0;
+  for (int i = 0; i < nb; ++i) {
+    rows += banks[i]->rows;
+    kcat += banks[i]->kcat;
+    levels = std::max(levels, banks[i]->n_levels);
+    for (const auto &sl : banks[i]->slices) np = std::max<int64_t>(np, sl.np);
+  }
+  int64_t block = 1;
+  while (block < n) block <<= 1;
+  static const char *names[] = {"f64", "f32", "f16", "bf16"};
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s/%s/banks%d/rows%lld/k%lld/taps%lld/levels%d/block%lld", arch.c_str(),
+                names[banks[0]->compute], nb, (long long)rows, (long long)kcat, (long long)np, levels,
+                (long long)block);
+  return buf;
+}
+
+struct TuneEntry {
+  std::string key;
+  int fir = 0, mix = 0;
+  double ms = 0;
+};
+
+// The cache is a JSON object with one line per shape class:
+//   "key": {"fir": F, "mix": M, "ms": T},
+std::vector<TuneEntry> read_tune_cache(const char *path) {
+  std::vector<TuneEntry> out;
+  FILE *f = path ? std::fopen(path, "r") : nullptr;
+  if (!f) return out;
+  char line[1024];
+  while (std::fgets(line, sizeof line, f)) {
+    const char *q0 = std::strchr(line, '"');
+    const char *q1 = q0 ? std::strchr(q0 + 1, '"') : nullptr;
+    if (!q1) continue;
+    TuneEntry e;
+    e.key.assign(q0 + 1, q1);
+    if (std::sscanf(q1 + 1, ": {\"fir\": %d, \"mix\": %d, \"ms\": %lf", &e.fir, &e.mix, &e.ms) == 3 &&
+        e.fir >= 0 && e.fir < kFirVariants && e.mix >= 0 && e.mix < kMixVariants)
+      out.push_back(e);
+  }
+  std::fclose(f);
+  return out;
+}
+
+bool write_tune_cache(const char *path, const std::vector<TuneEntry> &entries) {
+  FILE *f = std::fopen(path, "w");
+  if (!f) return false;
+  std::fprintf(f, "{\n");
+  for (size_t i = 0; i < entries.size(); ++i)
+    std::fprintf(f, "\"%s\": {\"fir\": %d, \"mix\": %d, \"ms\": %.4f}%s\n", entries[i].key.c_str(), entries[i].fir,
+                 entries[i].mix, entries[i].ms, i + 1 < entries.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  return std::fclose(f) == 0;
+}
+
+}  // namespace
+
+extern "C" lloid_status lloid_autotune(lloid_ctx *ctx, lloid_bank *const *banks, int32_t n_banks, double seconds,
+                                      const char *cache_path, lloid_tune_result *results, int32_t cap,
+                                      int32_t *n_results) {
+  ABI_GUARD_BEGIN
+  if (!ctx || !banks || n_banks <= 0 || !n_results) return fail(LLOID_EINVAL, "NULL argument or no banks");
+  for (int i = 0; i < n_banks; ++i)
+    if (!banks[i] || banks[i]->ctx != ctx) return fail(LLOID_EINVAL, "bank %d is NULL or of another context", i);
+  if (!(seconds > 0) || seconds > 4096) return fail(LLOID_EINVAL, "seconds must be in (0, 4096]");
+  if (cap < 0 || (cap > 0 && !results)) return fail(LLOID_EINVAL, "bad result buffer");
+  *n_results = 0;
+  const int64_t n = std::min<int64_t>(kMaxBlock, (int64_t)std::llround(seconds * banks[0]->f0));
+  const std::string key = tune_key(ctx, banks, n_banks, n);
+  std::vector<TuneEntry> cache = read_tune_cache(cache_path);
+  for (const auto &e : cache)
+    if (e.key == key) {
+      ctx->fir_variant = e.fir;
+      ctx->mix_variant = e.mix;
+      return LLOID_OK;
+    }
+  HIP_TRY(hipSetDevice(ctx->device));
+  float *x = nullptr;
+  if (hipMalloc(&x, (size_t)n * sizeof(float)) != hipSuccess) return fail(LLOID_ENOMEM, "tuning strain");
+  struct Free {
+    float *p;
+    ~Free() { (void)hipFree(p); }
+  } guard{x};
+  HIP_TRY(launch_noise(x, n, 0x2410164u, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  int64_t cap_t = 0;
+  for (int i = 0; i < n_banks; ++i) cap_t += (int64_t)banks[i]->n_templates * (n / banks[0]->f0 + 2);
+  std::vector<lloid_trigger> trig((size_t)cap_t);
+  const int fir0 = ctx->fir_variant, mix0 = ctx->mix_variant;
+  int best_f = fir0, best_m = mix0;
+  double best_ms = 1e300;
+  int32_t k = 0;
+  for (int fv = 0; fv < kFirVariants; ++fv)
+    for (int mv = 0; mv < kMixVariants; ++mv) {
+      ctx->fir_variant = fv;
+      ctx->mix_variant = mv;
+      double ms = 1e300;
+      for (int rep = 0; rep < 3; ++rep) {   // the first call warms up
+        int64_t n_trig = 0;
+        const auto t0 = std::chrono::steady_clock::now();
+        const lloid_status st = lloid_filter_batch(banks, n_banks, 0, x, LLOID_F32, n, nullptr, trig.data(), cap_t,
+                                                   &n_trig, nullptr);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (st != LLOID_OK && st != LLOID_ETRUNC) {
+          ctx->fir_variant = fir0;
+          ctx->mix_variant = mix0;
+          return st;
+        }
+        if (rep > 0) ms = std::min(ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+      }
+      if (k < cap) results[k] = lloid_tune_result{fv, mv, ms};
+      ++k;
+      if (ms < best_ms) best_ms = ms, best_f = fv, best_m = mv;
+    }
+  *n_results = k;
+  ctx->fir_variant = best_f;
+  ctx->mix_variant = best_m;
+  if (cache_path) {
+    cache.push_back(TuneEntry{key, best_f, best_m, best_ms});
+    if (!write_tune_cache(cache_path, cache)) return fail(LLOID_EINVAL, "cannot write %s", cache_path);
+  }
   return LLOID_OK;
   ABI_GUARD_END
 }

@@ -134,6 +134,7 @@ struct lloid_ctx {
   void *pinned = nullptr;       // pinned host staging for descriptor tables
   size_t pinned_bytes = 0;
   int64_t chunk_budget = int64_t(6) << 30;  // device bytes of per-chunk operands
+  int fir_variant = 0, mix_variant = 0;     // compiled tile shapes in use (lloid_ctx_set_tiles, lloid_autotune)
   bool profile = false;
   hipEvent_t ev[2 * LLOID_N_STAGES] = {};
   std::vector<hipEvent_t> cev;  // per chunk: start/end of the FIR, interpolation, mixing and phase stages
@@ -163,17 +164,24 @@ hipError_t launch_convert(const void *src, lloid_dtype dt, int64_t n, float *dst
                           int64_t dst_len, float scale, int *bad, hipStream_t s);
 hipError_t launch_decimate(const float *u, int64_t u_lo, int64_t u_len, float *d, int64_t d_lo,
                            int64_t d_len, const float *g, hipStream_t s);
-// Tile shapes (rows x columns per workgroup) of the FIR and mixing kernels in use.
-void fir_tile_shape(int *bm, int *bn);
-void mix_tile_shape(lloid_dtype t, int *bm, int *bn);
+// Compiled tile-shape variants of the FIR and mixing kernels (0 = default);
+// every variant gives bit-identical results (each output's K sum runs in the
+// same order), only the speed differs.  Rows x columns per workgroup:
+constexpr int kFirVariants = 3, kMixVariants = 4;
+void fir_tile_shape(int variant, int *bm, int *bn);
+void mix_tile_shape(lloid_dtype t, int variant, int *bm, int *bn);
 // One launch per stage over a device descriptor table (see the job structs).
-hipError_t launch_fir_jobs(lloid_dtype t, const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s);
+hipError_t launch_fir_jobs(lloid_dtype t, int variant, const FirJob *jobs, int n_jobs, int64_t n_items,
+                           hipStream_t s);
 hipError_t launch_up_jobs(lloid_dtype t, const UpJob *jobs, int n_jobs, int64_t n_items, hipStream_t s);
 // Work items of an interpolation job: four 32-channel x 128-sample wave tasks each.
 constexpr int kUpCols = 128;
 // Mixing and window peaks; then the phase at peaks with |z| >= phase_thr (0 for the others).
-hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_items, bool with_snr,
-                           hipStream_t s);
+hipError_t launch_mix_jobs(lloid_dtype t, int variant, const MixJob *jobs, int n_jobs, int64_t n_items,
+                           bool with_snr, hipStream_t s);
+// White noise of unit variance (a counter-based hash of the sample index and
+// seed, uniform on [-sqrt 3, sqrt 3]): synthetic strain for tuning runs.
+hipError_t launch_noise(float *x, int64_t n, uint32_t seed, hipStream_t s);
 hipError_t launch_peak_phase(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float phase_thr,
                              hipStream_t s);
 // Signal-consistency value at the peaks with |z| >= thr of the jobs that carry
@@ -277,9 +285,9 @@ struct BankBufs {
 
 struct TileShapes {
   int fbm, fbn, mbm, mbn;
-  explicit TileShapes(lloid_dtype t) {
-    fir_tile_shape(&fbm, &fbn);
-    mix_tile_shape(t, &mbm, &mbn);
+  TileShapes(lloid_dtype t, int fir_variant, int mix_variant) {
+    fir_tile_shape(fir_variant, &fbm, &fbn);
+    mix_tile_shape(t, mix_variant, &mbm, &mbn);
   }
 };
 

@@ -1182,16 +1182,24 @@ __global__ void k_coinc_write(const lloid_trigger *__restrict__ a, int64_t na, c
   if (bg_a) bg_a[i] = m == m0 ? 1 : 0;
 }
 
+// ---------------------------------------------------------- tuning input
+// Counter-based hash (the 32-bit finaliser of MurmurHash3 applied to the
+// sample index and seed) mapped to a uniform value of unit variance.
+__global__ void k_noise(float *__restrict__ x, int64_t n, uint32_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t h = (uint32_t)i ^ (uint32_t)(i >> 32) * 0x9e3779b9u ^ seed;
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  x[i] = ((float)h * (1.f / 4294967296.f) - 0.5f) * 3.4641016f;
+}
+
 // ------------------------------------------------------------ launchers
 
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
-
-// Tile-shape variant of a GEMM kernel: 0 (default) unless the named
-// environment variable selects another compiled shape.
-static int kernel_variant(const char *name) {
-  const char *v = getenv(name);
-  return v ? atoi(v) : 0;
-}
 
 hipError_t launch_convert(const void *src, lloid_dtype dt, int64_t n, float *dst, int64_t dst_lo,
                           int64_t dst_len, float scale, int *bad, hipStream_t s) {
@@ -1202,6 +1210,12 @@ hipError_t launch_convert(const void *src, lloid_dtype dt, int64_t n, float *dst
   else
     k_convert<float><<<blocks_for(dst_len, 256), 256, 0, s>>>((const float *)src, n, dst, dst_lo, dst_len,
                                                                 scale, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_noise(float *x, int64_t n, uint32_t seed, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_noise<<<blocks_for(n, 256), 256, 0, s>>>(x, n, seed);
   return hipGetLastError();
 }
 
@@ -1219,8 +1233,8 @@ static hipError_t fir_v(const FirJob *jobs, int n_jobs, int64_t n_items, hipStre
 }
 
 template <typename T>
-static hipError_t fir_t(const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s) {
-  switch (kernel_variant("LLOID_FIR_VARIANT")) {
+static hipError_t fir_t(int variant, const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s) {
+  switch (variant) {
     case 1: return fir_v<T, 4, 4, 4, kBK>(jobs, n_jobs, n_items, s);
     case 2: return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
     default:
@@ -1230,13 +1244,13 @@ static hipError_t fir_t(const FirJob *jobs, int n_jobs, int64_t n_items, hipStre
   }
 }
 
-void fir_tile_shape(int *bm, int *bn) {
+void fir_tile_shape(int variant, int *bm, int *bn) {
   *bm = 32 * kFirMT;
-  *bn = kernel_variant("LLOID_FIR_VARIANT") == 1 ? 4 * 32 * 4 : kFirWaves * 32 * kFirNT;
+  *bn = variant == 1 ? 4 * 32 * 4 : kFirWaves * 32 * kFirNT;
 }
 
-void mix_tile_shape(lloid_dtype, int *bm, int *bn) {
-  switch (kernel_variant("LLOID_MIX_VARIANT")) {
+void mix_tile_shape(lloid_dtype, int variant, int *bm, int *bn) {
+  switch (variant) {
     case 1: *bm = 32 * 4 * 2, *bn = 32 * 2 * 2; break;
     case 2: *bm = 32 * 2 * 4, *bn = 32 * 2 * 2; break;
     case 3: *bm = 32 * kMixMT * kMixWM, *bn = 32 * kMixNT * kMixWN; break;
@@ -1244,12 +1258,13 @@ void mix_tile_shape(lloid_dtype, int *bm, int *bn) {
   }
 }
 
-hipError_t launch_fir_jobs(lloid_dtype t, const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s) {
+hipError_t launch_fir_jobs(lloid_dtype t, int variant, const FirJob *jobs, int n_jobs, int64_t n_items,
+                           hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   switch (t) {
-    case LLOID_F16: return fir_t<_Float16>(jobs, n_jobs, n_items, s);
-    case LLOID_BF16: return fir_t<__bf16>(jobs, n_jobs, n_items, s);
-    case LLOID_F32: return fir_t<float>(jobs, n_jobs, n_items, s);
+    case LLOID_F16: return fir_t<_Float16>(variant, jobs, n_jobs, n_items, s);
+    case LLOID_BF16: return fir_t<__bf16>(variant, jobs, n_jobs, n_items, s);
+    case LLOID_F32: return fir_t<float>(variant, jobs, n_jobs, n_items, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1275,8 +1290,8 @@ static hipError_t mix_v(const MixJob *jobs, int n_jobs, int64_t n_items, bool wi
 }
 
 template <typename T>
-static hipError_t mix_t(const MixJob *jobs, int n_jobs, int64_t n_items, bool with_snr, hipStream_t s) {
-  switch (kernel_variant("LLOID_MIX_VARIANT")) {
+static hipError_t mix_t(int variant, const MixJob *jobs, int n_jobs, int64_t n_items, bool with_snr, hipStream_t s) {
+  switch (variant) {
     case 1: return mix_v<T, 4, 2, 2, 2, 32>(jobs, n_jobs, n_items, with_snr, s);
     case 2: return mix_v<T, 2, 2, 4, 2, 32>(jobs, n_jobs, n_items, with_snr, s);
     case 3: return mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 32>(jobs, n_jobs, n_items, with_snr, s);
@@ -1287,13 +1302,13 @@ static hipError_t mix_t(const MixJob *jobs, int n_jobs, int64_t n_items, bool wi
   }
 }
 
-hipError_t launch_mix_jobs(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_items, bool with_snr,
-                           hipStream_t s) {
+hipError_t launch_mix_jobs(lloid_dtype t, int variant, const MixJob *jobs, int n_jobs, int64_t n_items,
+                           bool with_snr, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   switch (t) {
-    case LLOID_F16: return mix_t<_Float16>(jobs, n_jobs, n_items, with_snr, s);
-    case LLOID_BF16: return mix_t<__bf16>(jobs, n_jobs, n_items, with_snr, s);
-    case LLOID_F32: return mix_t<float>(jobs, n_jobs, n_items, with_snr, s);
+    case LLOID_F16: return mix_t<_Float16>(variant, jobs, n_jobs, n_items, with_snr, s);
+    case LLOID_BF16: return mix_t<__bf16>(variant, jobs, n_jobs, n_items, with_snr, s);
+    case LLOID_F32: return mix_t<float>(variant, jobs, n_jobs, n_items, with_snr, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -199,7 +199,7 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
   s->w_next = wb;
   s->windows += nw;
   if (act.empty()) return LLOID_OK;
-  const TileShapes ts(s->ct);
+  const TileShapes ts(s->ct, ctx->fir_variant, ctx->mix_variant);
   const size_t esz = dtype_size(s->ct);
   const int64_t tlen = t1 - t0;
   // scratch layout
@@ -317,6 +317,7 @@ lloid_status run_tick(lloid_stream *s, int64_t wa, int64_t wb) {
                                 items.fir, items.mix, items.entries, (int64_t)to.fir, (int64_t)to.mix, to.n_fir,
                                 to.n_mix};
     key.push_back(items.xi2 ? 1 : 0);
+    key.push_back(ctx->fir_variant * 16 + ctx->mix_variant);
     key.push_back(items.windows);
     for (int h = 0; h < kMaxHops; ++h) {
       key.push_back(items.up[h]);

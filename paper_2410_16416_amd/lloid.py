@@ -93,6 +93,8 @@ TRIGGER_DTYPE = np.dtype([("bank", np.int32), ("detector", np.int32), ("template
                           ("snr_interp", np.float32), ("dt", np.float32)])
 assert TRIGGER_DTYPE.itemsize == 48
 
+TUNE_DTYPE = np.dtype([("fir_variant", np.int32), ("mix_variant", np.int32), ("ms", np.float64)])
+
 COINC_DTYPE = np.dtype([("a", np.int64), ("b", np.int64), ("bank", np.int32), ("template_id", np.int32),
                         ("snr_net", np.float32), ("dt", np.float32)])
 assert COINC_DTYPE.itemsize == 32
@@ -116,6 +118,10 @@ def _load():
         "lloid_bank_destroy": ([vp], ctypes.c_int),
         "lloid_filter": ([vp, i32, vp, ctypes.c_int, i64, ctypes.POINTER(lloid_trigger_opts), vp, i64,
                           ctypes.POINTER(i64), vp, ctypes.POINTER(lloid_peaks)], ctypes.c_int),
+        "lloid_ctx_set_tiles": ([vp, i32, i32], ctypes.c_int),
+        "lloid_ctx_get_tiles": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
+        "lloid_autotune": ([vp, ctypes.POINTER(vp), i32, ctypes.c_double, ctypes.c_char_p, vp, i32,
+                            ctypes.POINTER(i32)], ctypes.c_int),
         "lloid_condition": ([vp, i32, vp, ctypes.c_int, i64, ctypes.POINTER(lloid_condition_opts), vp, vp,
                              ctypes.POINTER(i64)], ctypes.c_int),
         "lloid_coincide": ([vp, vp, i64, vp, i64, i64, vp, i64, ctypes.POINTER(i64), vp], ctypes.c_int),
@@ -164,7 +170,7 @@ def exported_symbols():
             "lloid_filter", "lloid_filter_batch", "lloid_ctx_set_chunk_bytes",
             "lloid_stream_create", "lloid_stream_admit", "lloid_stream_remove", "lloid_stream_push",
             "lloid_stream_poll", "lloid_stream_flush", "lloid_stream_stats_get", "lloid_stream_destroy",
-            "lloid_coincide", "lloid_condition"]
+            "lloid_coincide", "lloid_condition", "lloid_ctx_set_tiles", "lloid_ctx_get_tiles", "lloid_autotune"]
 
 
 def lloid_version() -> str:
@@ -256,6 +262,29 @@ class FilterResult:
     peak_sample: np.ndarray | None = None
     peak_phase: np.ndarray | None = None
     snr: object = None
+
+
+def lloid_ctx_set_tiles(ctx, fir_variant: int, mix_variant: int):
+    _check(_lib.lloid_ctx_set_tiles(ctx, int(fir_variant), int(mix_variant)))
+
+
+def lloid_ctx_get_tiles(ctx):
+    f, m = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(_lib.lloid_ctx_get_tiles(ctx, ctypes.byref(f), ctypes.byref(m)))
+    return f.value, m.value
+
+
+def lloid_autotune(ctx, banks, seconds: float, cache_path: str | None = None):
+    """Pick the tile variants for these banks (see include/lloid.h); returns
+    the chosen (fir, mix) pair and the TUNE_DTYPE timings (empty when the
+    cache held the choice)."""
+    arr = (ctypes.c_void_p * len(banks))(*[b.value for b in banks])
+    res = np.zeros(64, dtype=TUNE_DTYPE)
+    n = ctypes.c_int32(0)
+    _check(_lib.lloid_autotune(ctx, arr, len(banks), float(seconds),
+                               cache_path.encode() if cache_path else None, res.ctypes.data, res.shape[0],
+                               ctypes.byref(n)))
+    return lloid_ctx_get_tiles(ctx), res[:n.value].copy()
 
 
 def lloid_condition(ctx, full_rate_hz: int, strain, seg_len: int, gate_threshold: float = 0.0,

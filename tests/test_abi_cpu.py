@@ -58,6 +58,7 @@ int main(void) {
   printf("lloid_stream_stats %zu\\n", sizeof(lloid_stream_stats));
   printf("lloid_coinc %zu\\n", sizeof(lloid_coinc));
   printf("lloid_condition_opts %zu\\n", sizeof(lloid_condition_opts));
+  printf("lloid_tune_result %zu\\n", sizeof(lloid_tune_result));
   P(lloid_condition_opts, gate_threshold) P(lloid_condition_opts, psd)
   P(lloid_coinc, bank) P(lloid_coinc, template_id) P(lloid_coinc, snr_net) P(lloid_coinc, dt)
   P(lloid_stream_opts, use_graph) P(lloid_stream_opts, hbm_budget) P(lloid_stream_opts, trig)
@@ -82,6 +83,7 @@ int main(void) {
         assert int(got[name]) == ctypes.sizeof(cls), name
     assert int(got["lloid_trigger"]) == lloid.TRIGGER_DTYPE.itemsize
     assert int(got["lloid_coinc"]) == lloid.COINC_DTYPE.itemsize
+    assert int(got["lloid_tune_result"]) == lloid.TUNE_DTYPE.itemsize
     from workloads.triggers import TRIGGER_DTYPE as synthetic
     assert synthetic == lloid.TRIGGER_DTYPE
     for f in ("bank", "template_id", "snr_net", "dt"):

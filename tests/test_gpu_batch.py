@@ -89,3 +89,71 @@ def test_c3_shaped_banks_alone_equal_in_batch():
     finally:
         for h in handles:
             lloid.lloid_bank_destroy(h)
+
+
+@pytest.mark.parametrize("compute", ["f16", "f32"])
+def test_tile_variants_give_identical_results(compute):
+    """Every compiled tile shape of the FIR and mixing kernels gives the same
+    triggers and peaks, bit for bit: each output's sum over K runs in the same
+    order whatever the tile."""
+    from paper_2410_16416_amd import lloid
+    banks = [configs.small_uneven_bank(i) for i in range(4)]
+    x = np.random.default_rng(6).standard_normal(6 * 1024 + 333)
+    c = lloid.lloid_ctx_create(0)
+    handles = [lloid.bank_from_svd(c, b, compute) for b in banks]
+    try:
+        ref = None
+        for fv in range(3):
+            for mv in range(4):
+                lloid.lloid_ctx_set_tiles(c, fv, mv)
+                assert lloid.lloid_ctx_get_tiles(c) == (fv, mv)
+                r = lloid.lloid_filter_batch(handles, 0, x, window=(1, 4), threshold=3.0, peaks=True)
+                if ref is None:
+                    ref = r
+                    assert r.n_triggers > 0
+                    continue
+                assert np.array_equal(r.triggers, ref.triggers), (fv, mv)
+                for k in range(len(banks)):
+                    assert np.array_equal(r.peak_snr[k], ref.peak_snr[k]), (fv, mv, k)
+                    assert np.array_equal(r.peak_sample[k], ref.peak_sample[k]), (fv, mv, k)
+        with pytest.raises(lloid.LloidError) as ei:
+            lloid.lloid_ctx_set_tiles(c, 3, 0)
+        assert ei.value.status == lloid.LLOID_EINVAL
+    finally:
+        for h in handles:
+            lloid.lloid_bank_destroy(h)
+        lloid.lloid_ctx_destroy(c)
+
+
+def test_autotune_picks_the_fastest_and_caches(tmp_path):
+    """The autotuner times every variant pair, keeps the fastest on the
+    context and records it; a new context with the same banks takes the
+    recorded choice without timing."""
+    from paper_2410_16416_amd import lloid
+    banks = [configs.small_uneven_bank(i) for i in range(3)]
+    cache = str(tmp_path / "tiles.json")
+    c = lloid.lloid_ctx_create(0)
+    handles = [lloid.bank_from_svd(c, b, "f16") for b in banks]
+    try:
+        best, res = lloid.lloid_autotune(c, handles, 4.0, cache)
+        log(f"[autotune] best {best}; " + ", ".join(f"{r['fir_variant']}/{r['mix_variant']}: {r['ms']:.2f} ms"
+                                                   for r in res))
+        assert res.shape[0] == 12 and np.all(res["ms"] > 0)
+        k = int(np.argmin(res["ms"]))
+        assert best == (int(res["fir_variant"][k]), int(res["mix_variant"][k]))
+        text = open(cache).read()
+        assert "f16" in text and f'"fir": {best[0]}, "mix": {best[1]}' in text
+    finally:
+        for h in handles:
+            lloid.lloid_bank_destroy(h)
+        lloid.lloid_ctx_destroy(c)
+    c2 = lloid.lloid_ctx_create(0)
+    handles = [lloid.bank_from_svd(c2, b, "f16") for b in banks]
+    try:
+        lloid.lloid_ctx_set_tiles(c2, 0, 0)
+        again, res2 = lloid.lloid_autotune(c2, handles, 4.0, cache)
+        assert res2.shape[0] == 0 and again == best
+    finally:
+        for h in handles:
+            lloid.lloid_bank_destroy(h)
+        lloid.lloid_ctx_destroy(c2)
