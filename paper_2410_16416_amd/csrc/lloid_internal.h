@@ -167,8 +167,8 @@ hipError_t launch_decimate(const float *u, int64_t u_lo, int64_t u_len, float *d
 // Compiled tile-shape variants of the FIR and mixing kernels (0 = default);
 // every variant gives bit-identical results (each output's K sum runs in the
 // same order), only the speed differs.  Rows x columns per workgroup:
-constexpr int kFirVariants = 3, kMixVariants = 4;
-void fir_tile_shape(int variant, int *bm, int *bn);
+constexpr int kFirVariants = 4, kMixVariants = 4;
+void fir_tile_shape(lloid_dtype t, int variant, int *bm, int *bn);
 void mix_tile_shape(lloid_dtype t, int variant, int *bm, int *bn);
 // One launch per stage over a device descriptor table (see the job structs).
 hipError_t launch_fir_jobs(lloid_dtype t, int variant, const FirJob *jobs, int n_jobs, int64_t n_items,
@@ -286,7 +286,7 @@ struct BankBufs {
 struct TileShapes {
   int fbm, fbn, mbm, mbn;
   TileShapes(lloid_dtype t, int fir_variant, int mix_variant) {
-    fir_tile_shape(fir_variant, &fbm, &fbn);
+    fir_tile_shape(t, fir_variant, &fbm, &fbn);
     mix_tile_shape(t, mix_variant, &mbm, &mbn);
   }
 };

@@ -199,13 +199,21 @@ template <typename T, int ROWS, int BK = kBK, int THREADS = kThreads> struct Chu
 // consecutive samples are one aligned read whatever its column; the basis
 // streams through double-buffered LDS with the next chunk's global reads in
 // flight during the current chunk's MFMAs.
-template <typename T, int MT, int NT, int NW, int BK>
+// HR (16-bit operands): the Hankel operand repeats itself shifted, so the
+// fragment of column block nt at k-step g is that of block 0 at k-step
+// g + 2 nt (32 columns = 2 k-steps of 16 taps).  Each wave then keeps, per
+// k-step parity, a window of NT fragments in registers and reads one new
+// fragment from LDS per k-step instead of NT.
+template <typename T, int MT, int NT, int NW, int BK, bool HR = false>
 __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs, int n_jobs) {
   typedef Op<T> O;
+  static_assert(!HR || O::KS == 16, "the fragment window needs 16 taps per k-step");
   constexpr int THREADS = 64 * NW;
   constexpr int BM = 32 * MT, BN = NW * 32 * NT;
   constexpr int P = Pitch<T, BK>::value;
-  constexpr int WC = BN + kFirKSup + 16;
+  // strain window: BN columns + kFirKSup taps (+ the fragments the HR window
+  // reads ahead past its last k-step)
+  constexpr int WC = BN + kFirKSup + 16 + (HR ? 2 * NT * 16 : 0);
   __shared__ __attribute__((aligned(16))) T As[2][BM * P];
   __shared__ __attribute__((aligned(16))) T Bc[O::VEC * WC];
 
@@ -243,6 +251,7 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
   const int64_t wcol = i0 + wave * NT * 32;
   const int live = (int)(jb.k_hi <= wcol ? 0 : std::min<int64_t>(NT, (jb.k_hi - wcol + 31) / 32));
   int ksup = 0;
+  typename O::vec hw[2][HR ? NT : 1];   // HR: fragment windows of the even and odd k-steps
   for (int c = 0; c < nchunks; ++c) {
     const int cur = c & 1, kc = c * BK;
     if (kc % kFirKSup == 0) {
@@ -279,8 +288,44 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
             if (decltype(all)::value || nt < live) acc[mt][nt] = O::mfma(af[mt], bf[nt], acc[mt][nt]);
       }
     };
-    if (live == NT) ksteps(std::true_type{});
-    else if (live > 0) ksteps(std::false_type{});
+    if constexpr (HR) {
+      if (live == NT) {
+        // F(j): block-0 fragment j k-steps into the strain window
+        auto F = [&](int j) __attribute__((always_inline)) {
+          return *(const typename O::vec *)(bl + j * O::KS);
+        };
+        const int g0 = (kc - ksup) / O::KS;
+        if (kc == ksup) {
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            hw[0][nt] = F(2 * nt);
+            hw[1][nt] = F(1 + 2 * nt);
+          }
+        }
+#pragma unroll
+        for (int ks = 0; ks < BK / O::KS; ++ks) {
+          if (BK > kBK && kc + ks * O::KS >= np) break;
+          typename O::vec af[MT];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            af[mt] = *(const typename O::vec *)(As[cur] + (mt * 32 + (lane & 31)) * P + ks * O::KS +
+                                                 (lane >> 5) * O::VEC);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = O::mfma(af[mt], hw[ks & 1][nt], acc[mt][nt]);
+          // this parity's next k-step (g + 2) needs blocks shifted by one
+#pragma unroll
+          for (int nt = 0; nt + 1 < NT; ++nt) hw[ks & 1][nt] = hw[ks & 1][nt + 1];
+          hw[ks & 1][NT - 1] = F(g0 + ks + 2 * NT);
+        }
+      } else if (live > 0) {
+        ksteps(std::false_type{});
+      }
+    } else {
+      if (live == NT) ksteps(std::true_type{});
+      else if (live > 0) ksteps(std::false_type{});
+    }
   }
 
   // store: lane holds column i, rows rb..rb+3 for each group of four; level-0
@@ -1226,9 +1271,9 @@ hipError_t launch_decimate(const float *u, int64_t u_lo, int64_t u_len, float *d
   return hipGetLastError();
 }
 
-template <typename T, int MT, int NT, int NW, int BK>
+template <typename T, int MT, int NT, int NW, int BK, bool HR = false>
 static hipError_t fir_v(const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s) {
-  k_fir<T, MT, NT, NW, BK><<<(unsigned)n_items, 64 * NW, 0, s>>>(jobs, n_jobs);
+  k_fir<T, MT, NT, NW, BK, HR><<<(unsigned)n_items, 64 * NW, 0, s>>>(jobs, n_jobs);
   return hipGetLastError();
 }
 
@@ -1237,6 +1282,10 @@ static hipError_t fir_t(int variant, const FirJob *jobs, int n_jobs, int64_t n_i
   switch (variant) {
     case 1: return fir_v<T, 4, 4, 4, kBK>(jobs, n_jobs, n_items, s);
     case 2: return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
+    case 3:
+      // 16-bit operands: 64 x 1024 tiles with the Hankel fragment window
+      if constexpr (sizeof(T) == 2) return fir_v<T, 2, 4, kFirWaves, 2 * kBK, true>(jobs, n_jobs, n_items, s);
+      else return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
     default:
       // 16-bit operands: K chunks of 64 (twice the MFMAs per barrier)
       if constexpr (sizeof(T) == 2) return fir_v<T, kFirMT, kFirNT, kFirWaves, 2 * kBK>(jobs, n_jobs, n_items, s);
@@ -1244,9 +1293,10 @@ static hipError_t fir_t(int variant, const FirJob *jobs, int n_jobs, int64_t n_i
   }
 }
 
-void fir_tile_shape(int variant, int *bm, int *bn) {
+void fir_tile_shape(lloid_dtype t, int variant, int *bm, int *bn) {
   *bm = 32 * kFirMT;
   *bn = variant == 1 ? 4 * 32 * 4 : kFirWaves * 32 * kFirNT;
+  if (variant == 3 && t != LLOID_F32) *bm = 32 * 2, *bn = kFirWaves * 32 * 4;
 }
 
 void mix_tile_shape(lloid_dtype, int variant, int *bm, int *bn) {
