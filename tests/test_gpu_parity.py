@@ -306,6 +306,47 @@ def test_xi2_matches_oracle(compute):
     log(f"  {t.shape[0]} triggers, {n_cmp} compared, max |d xi2| {worst:.2e}")
 
 
+def test_xi2_more_triggers_than_one_list_pass():
+    """A window with more triggers than the kernel lists at once (threshold 0:
+    every one of 1500 templates triggers in every window) is handled in
+    several passes over the templates; every value still matches the oracle."""
+    from paper_2410_16416_amd import lloid
+    from workloads import SliceSpec, bank_autocorrelation
+    rng = np.random.default_rng(71)
+    bank = configs.random_basis_bank(1500, [SliceSpec(1024, 0, 96, 12), SliceSpec(256, 96, 40, 8)], 1024, rng)
+    half = 6
+    r = bank_autocorrelation(bank, half)
+    bank.autocorr = r
+    x = rng.standard_normal(3 * 1024 + 77)
+    n = x.shape[0]
+    h = lloid.bank_from_svd(ctx(), bank, "f32")
+    try:
+        t = lloid.lloid_filter(h, 0, x, window=(1, 1), threshold=0.0).triggers
+    finally:
+        lloid.lloid_bank_destroy(h)
+    assert t.shape[0] == 1500 * 4
+    z = oracle.lloid_snr(bank, x)
+    a = np.abs(z)
+    starts = oracle.window_starts(5, 1024, 1, 1)
+    worst, n_cmp = 0.0, 0
+    for rec in t:
+        i, s_, w = int(rec["template_id"]), int(rec["sample"]), int(rec["window"])
+        if a[i, starts[w]:min(starts[w + 1], n)].argmax() + starts[w] != s_:
+            continue
+        want = oracle.xi2(z[i], 0, n, s_, r[i])
+        lag = np.arange(-half, half + 1)
+        ok = (s_ + lag >= 0) & (s_ + lag < n)
+        d = z[i, (s_ + lag)[ok]] - z[i, s_] * r[i, ok]
+        den = np.sum(2.0 - 2.0 * np.abs(r[i, ok]) ** 2)
+        eps = EPS_ABS["f32"]     # the bound of test_xi2_matches_oracle
+        tol = (4 * eps * np.sum(np.abs(d)) + 4 * eps ** 2 * ok.sum()) / den + 1e-5 * want
+        assert abs(float(rec["xi2"]) - want) <= tol, (i, w, float(rec["xi2"]), want, tol)
+        worst = max(worst, abs(float(rec["xi2"]) - want))
+        n_cmp += 1
+    log(f"[xi2 passes] {t.shape[0]} triggers, {n_cmp} compared, max |d xi2| {worst:.2e}")
+    assert n_cmp > 0.95 * t.shape[0]
+
+
 @pytest.mark.parametrize("compute", PRECISIONS)
 def test_subsample_peaks_match_oracle(compute):
     """Every trigger's sub-sample refinement equals the oracle's parabola through
