@@ -13,7 +13,6 @@
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
-#include <type_traits>
 
 #include "lloid_internal.h"
 
@@ -246,8 +245,10 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
   // lane's shifted copy: its column offset within a fragment is constant mod VEC
   const int lr = (lane & 31) % O::VEC;
   const T *bl = Bc + lr * WC + (wave * NT * 32 + (lane & 31) + (lane >> 5) * O::VEC - lr);
-  // 32-column fragments of this wave that start before k_hi: past the end of
-  // a ragged last tile a wave skips their MFMAs (it still loads and syncs)
+  // 32-column fragments of this wave that start before k_hi: a wave wholly
+  // past the end of a ragged last tile skips its MFMAs (it still loads and
+  // syncs); the HR window needs all NT fragments, so a partly live wave takes
+  // the plain k-steps
   const int64_t wcol = i0 + wave * NT * 32;
   const int live = (int)(jb.k_hi <= wcol ? 0 : std::min<int64_t>(NT, (jb.k_hi - wcol + 31) / 32));
   int ksup = 0;
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
     la.store(As[cur]);
     __syncthreads();
     if (c + 1 < nchunks) la.load(ra, (kc + BK) * (int)sizeof(T));
-    auto ksteps = [&](auto all) __attribute__((always_inline)) {
+    auto ksteps = [&]() __attribute__((always_inline)) {
 #pragma unroll
       for (int ks = 0; ks < BK / O::KS; ++ks) {
         if (BK > kBK && kc + ks * O::KS >= np) break;
@@ -278,14 +279,11 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
         for (int mt = 0; mt < MT; ++mt)
           af[mt] = *(const typename O::vec *)(As[cur] + (mt * 32 + (lane & 31)) * P + ks * O::KS + (lane >> 5) * O::VEC);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          if (decltype(all)::value || nt < live)
-            bf[nt] = *(const typename O::vec *)(bl + (kc - ksup) + nt * 32 + ks * O::KS);
+        for (int nt = 0; nt < NT; ++nt) bf[nt] = *(const typename O::vec *)(bl + (kc - ksup) + nt * 32 + ks * O::KS);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt)
-            if (decltype(all)::value || nt < live) acc[mt][nt] = O::mfma(af[mt], bf[nt], acc[mt][nt]);
+          for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = O::mfma(af[mt], bf[nt], acc[mt][nt]);
       }
     };
     if constexpr (HR) {
@@ -320,11 +318,10 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
           hw[ks & 1][NT - 1] = F(g0 + ks + 2 * NT);
         }
       } else if (live > 0) {
-        ksteps(std::false_type{});
+        ksteps();
       }
     } else {
-      if (live == NT) ksteps(std::true_type{});
-      else if (live > 0) ksteps(std::false_type{});
+      if (live > 0) ksteps();
     }
   }
 
@@ -1280,9 +1277,8 @@ static hipError_t fir_v(const FirJob *jobs, int n_jobs, int64_t n_items, hipStre
 template <typename T>
 static hipError_t fir_t(int variant, const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s) {
   switch (variant) {
-    case 1: return fir_v<T, 4, 4, 4, kBK>(jobs, n_jobs, n_items, s);
-    case 2: return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
-    case 3:
+    case 1: return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
+    case 2:
       // 16-bit operands: 64 x 1024 tiles with the Hankel fragment window
       if constexpr (sizeof(T) == 2) return fir_v<T, 2, 4, kFirWaves, 2 * kBK, true>(jobs, n_jobs, n_items, s);
       else return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
@@ -1295,8 +1291,8 @@ static hipError_t fir_t(int variant, const FirJob *jobs, int n_jobs, int64_t n_i
 
 void fir_tile_shape(lloid_dtype t, int variant, int *bm, int *bn) {
   *bm = 32 * kFirMT;
-  *bn = variant == 1 ? 4 * 32 * 4 : kFirWaves * 32 * kFirNT;
-  if (variant == 3 && t != LLOID_F32) *bm = 32 * 2, *bn = kFirWaves * 32 * 4;
+  *bn = kFirWaves * 32 * kFirNT;
+  if (variant == 2 && t != LLOID_F32) *bm = 32 * 2, *bn = kFirWaves * 32 * 4;
 }
 
 void mix_tile_shape(lloid_dtype, int variant, int *bm, int *bn) {
