@@ -385,7 +385,7 @@ lloid_status lloid_coincide(lloid_ctx *ctx, const lloid_trigger *a, int64_t n_a,
 typedef struct {
   int32_t fir_variant;
   int32_t mix_variant;
-  double ms;             /* fastest of two timed lloid_filter_batch calls after a warm-up */
+  double ms;             /* fastest of four timed lloid_filter_batch calls after a warm-up */
 } lloid_tune_result;
 
 lloid_status lloid_ctx_set_tiles(lloid_ctx *ctx, int32_t fir_variant, int32_t mix_variant);

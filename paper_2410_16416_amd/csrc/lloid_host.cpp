@@ -1215,7 +1215,7 @@ extern "C" lloid_status lloid_autotune(lloid_ctx *ctx, lloid_bank *const *banks,
       ctx->fir_variant = fv;
       ctx->mix_variant = mv;
       double ms = 1e300;
-      for (int rep = 0; rep < 3; ++rep) {   // the first call warms up
+      for (int rep = 0; rep < 5; ++rep) {   // the first call warms up; the fastest of the others counts
         int64_t n_trig = 0;
         const auto t0 = std::chrono::steady_clock::now();
         const lloid_status st = lloid_filter_batch(banks, n_banks, 0, x, LLOID_F32, n, nullptr, trig.data(), cap_t,
