@@ -211,8 +211,12 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
   constexpr int BM = 32 * MT, BN = NW * 32 * NT;
   constexpr int P = Pitch<T, BK>::value;
   // strain window: BN columns + kFirKSup taps (+ the fragments the HR window
-  // reads ahead past its last k-step)
-  constexpr int WC = BN + kFirKSup + 16 + (HR ? 2 * NT * 16 : 0);
+  // reads ahead past its last k-step).  With 16-bit operands the copies are
+  // padded to WC = 32 mod 64 elements: the 16-byte fragment reads, each lane
+  // in its own copy, then run without LDS bank conflicts (measured with the
+  // bank-conflict counter; other residues mod 64 conflict)
+  constexpr int WC0 = BN + kFirKSup + 16 + (HR ? 2 * NT * 16 : 0);
+  constexpr int WC = O::VEC == 8 ? (WC0 + 31) / 64 * 64 + 32 : WC0;
   __shared__ __attribute__((aligned(16))) T As[2][BM * P];
   __shared__ __attribute__((aligned(16))) T Bc[O::VEC * WC];
 
@@ -259,12 +263,27 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
       // new strain window for taps [kc, kc + kFirKSup); out-of-range samples read as zero
       if (c > 0) __syncthreads();
       ksup = kc;
+      // copy r holds x[w0 + t + r] at t: a thread takes G consecutive
+      // positions of every copy, issues the G + VEC - 1 sample reads it needs
+      // back to back, and writes each copy's G values as one 16-byte store
       const int64_t w0 = i0 + kc + jb.base - jb.x_lo;
-      for (int e = threadIdx.x; e < O::VEC * WC; e += THREADS) {
-        const int r = e / WC, t = e - r * WC;
-        const int64_t idx = w0 + t + r;
-        const int off = (idx >= 0 && idx < x_len) ? (int)idx * 4 : -4;
-        Bc[e] = O::cvt(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, off, 0, 0)));
+      constexpr int G = 16 / (int)sizeof(T);
+      static_assert(WC % G == 0, "the strain window is whole 16-byte units");
+      for (int t0 = threadIdx.x * G; t0 < WC; t0 += THREADS * G) {
+        float v[G + O::VEC - 1];
+#pragma unroll
+        for (int u = 0; u < G + O::VEC - 1; ++u) {
+          const int64_t idx = w0 + t0 + u;
+          const int off = (idx >= 0 && idx < x_len) ? (int)idx * 4 : -4;
+          v[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, off, 0, 0));
+        }
+#pragma unroll
+        for (int r = 0; r < O::VEC; ++r) {
+          T h[G];
+#pragma unroll
+          for (int g = 0; g < G; ++g) h[g] = O::cvt(v[r + g]);
+          *(uint4 *)(Bc + r * WC + t0) = __builtin_bit_cast(uint4, h);
+        }
       }
     }
     la.store(As[cur]);

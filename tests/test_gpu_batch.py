@@ -103,20 +103,33 @@ def test_tile_variants_give_identical_results(compute):
     c = lloid.lloid_ctx_create(0)
     handles = [lloid.bank_from_svd(c, b, compute) for b in banks]
     try:
-        ref = None
-        for fv in range(3):
-            for mv in range(4):
-                lloid.lloid_ctx_set_tiles(c, fv, mv)
-                assert lloid.lloid_ctx_get_tiles(c) == (fv, mv)
-                r = lloid.lloid_filter_batch(handles, 0, x, window=(1, 4), threshold=3.0, peaks=True)
-                if ref is None:
-                    ref = r
-                    assert r.n_triggers > 0
-                    continue
-                assert np.array_equal(r.triggers, ref.triggers), (fv, mv)
-                for k in range(len(banks)):
-                    assert np.array_equal(r.peak_snr[k], ref.peak_snr[k]), (fv, mv, k)
-                    assert np.array_equal(r.peak_sample[k], ref.peak_sample[k]), (fv, mv, k)
+        # quarter-second windows: one column tile each; 0.75 s: three, with a
+        # ragged last window (odd and even chunk counts per window)
+        for window in ((1, 4), (3, 4)):
+            ref = None
+            for fv in range(3):
+                for mv in range(4):
+                    lloid.lloid_ctx_set_tiles(c, fv, mv)
+                    assert lloid.lloid_ctx_get_tiles(c) == (fv, mv)
+                    r = lloid.lloid_filter_batch(handles, 0, x, window=window, threshold=3.0, peaks=True)
+                    if ref is None:
+                        ref = r
+                        assert r.n_triggers > 0
+                        continue
+                    assert np.array_equal(r.triggers, ref.triggers), (window, fv, mv)
+                    for k in range(len(banks)):
+                        assert np.array_equal(r.peak_snr[k], ref.peak_snr[k]), (window, fv, mv, k)
+                        assert np.array_equal(r.peak_sample[k], ref.peak_sample[k]), (window, fv, mv, k)
+        # the complex SNR series too (the kernels' series-writing forms)
+        series = None
+        for mv in range(4):
+            lloid.lloid_ctx_set_tiles(c, 0, mv)
+            r = lloid.lloid_filter(handles[0], 0, x, window=(3, 4), threshold=3.0,
+                                   snr_out=np.zeros((banks[0].n_templates, x.size, 2), np.float32))
+            if series is None:
+                series = r.snr
+            else:
+                assert np.array_equal(r.snr, series), mv
         with pytest.raises(lloid.LloidError) as ei:
             lloid.lloid_ctx_set_tiles(c, 3, 0)
         assert ei.value.status == lloid.LLOID_EINVAL
@@ -139,7 +152,7 @@ def test_autotune_picks_the_fastest_and_caches(tmp_path):
         best, res = lloid.lloid_autotune(c, handles, 4.0, cache)
         log(f"[autotune] best {best}; " + ", ".join(f"{r['fir_variant']}/{r['mix_variant']}: {r['ms']:.2f} ms"
                                                    for r in res))
-        assert res.shape[0] == 12 and np.all(res["ms"] > 0)
+        assert res.shape[0] == 3 * 4 and np.all(res["ms"] > 0)   # FIR x mixing shapes
         k = int(np.argmin(res["ms"]))
         assert best == (int(res["fir_variant"][k]), int(res["mix_variant"][k]))
         text = open(cache).read()
