@@ -392,12 +392,45 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
 // time-major mixing operand, computes D[t][c] with the operands swapped, so
 // each store instruction writes 32 consecutive channels of two samples.
 // TS: source and low-rate buffer type; TD: operand type of the last hop.
+// 16-bit sources: the fragment of tile t at k-step ks is the VEC-sample block
+// 2 ks + SB t past the lane's first one (tiles are 32 / R = 8 SB samples
+// apart), so a lane reads each block of its whole source window once, all
+// reads issued before the MFMAs.
+template <typename TS, bool TM, int SB>
+__device__ __forceinline__ void upsample_blocks(__amdgpu_buffer_rsrc_t rs, int64_t base0,
+                                                const typename Op<TS>::vec *hfr, f32x16 *acc) {
+  typedef Op<TS> O;
+  static_assert(O::VEC == 8 && O::KS == 2 * O::VEC, "16-bit fragments");
+  constexpr int NKS = 64 / O::KS, CT = kUpCols / 32;
+  constexpr int NB = 2 * (NKS - 1) + SB * (CT - 1) + 1;
+  typename O::vec blk[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (SB == 2 && (j & 1)) continue;   // x2 hops use the even blocks only
+    const int off = (int)((base0 + j * O::VEC) * (int64_t)sizeof(TS));
+    blk[j] = __builtin_bit_cast(typename O::vec, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+  }
+  __builtin_amdgcn_sched_barrier(0);   // keep every read ahead of the MFMAs
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const typename O::vec a = blk[2 * ks + SB * t];
+      acc[t] = TM ? O::mfma(hfr[ks], a, acc[t]) : O::mfma(a, hfr[ks], acc[t]);
+    }
+  }
+}
+
 template <typename TS, typename TD, bool TM>
 __device__ __forceinline__ void upsample_task(const UpJob &jb, int lane, int r0, int64_t n0) {
   typedef Op<TS> O;
   constexpr int NKS = 64 / O::KS;  // k-steps over the 64 composite taps
   constexpr int CT = kUpCols / 32; // 32-sample tiles per task
   const int R = jb.r;
+  const int lgR = R == 4 ? 2 : 1;  // R is 2 or 4: shifts, not 64-bit divisions (their
+                                   // branches would keep the tiles' reads apart)
   const TS *hf = (const TS *)jb.hf;
   typename O::vec hfr[NKS];
 #pragma unroll
@@ -406,23 +439,24 @@ __device__ __forceinline__ void upsample_task(const UpJob &jb, int lane, int r0,
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(jb.src, jb.src_bytes);
   const int64_t rowoff = (int64_t)(r0 + (lane & 31)) * jb.ld_src;
   f32x16 acc[CT];
+  if constexpr (O::VEC == 8) {
+    const int64_t base0 = rowoff + (((n0 >> lgR) - cR) - jb.src_lo) + (lane >> 5) * O::VEC;
+    if (R == 4) upsample_blocks<TS, TM, 1>(rs, base0, hfr, acc);
+    else upsample_blocks<TS, TM, 2>(rs, base0, hfr, acc);
+  } else {
+    // FP32 sources: one sample per lane and k-step
 #pragma unroll
-  for (int t = 0; t < CT; ++t) {
+    for (int t = 0; t < CT; ++t) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
-    const int64_t u0 = (n0 + 32 * t) / R - cR;   // n0 + 32 t is a multiple of R: exact
-    const int64_t base = rowoff + (u0 - jb.src_lo) + (lane >> 5) * O::VEC;
+      for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
+      const int64_t u0 = ((n0 + 32 * t) >> lgR) - cR;   // n0 + 32 t is a multiple of R: exact
+      const int64_t base = rowoff + (u0 - jb.src_lo) + (lane >> 5) * O::VEC;
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) {
-      const int off = (int)((base + ks * O::KS) * (int64_t)sizeof(TS));
-      typename O::vec a;
-      if constexpr (O::VEC == 8) {
-        auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-        a = __builtin_bit_cast(typename O::vec, v);
-      } else {
-        a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+      for (int ks = 0; ks < NKS; ++ks) {
+        const int off = (int)((base + ks * O::KS) * (int64_t)sizeof(TS));
+        const typename O::vec a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+        acc[t] = TM ? O::mfma(hfr[ks], a, acc[t]) : O::mfma(a, hfr[ks], acc[t]);
       }
-      acc[t] = TM ? O::mfma(hfr[ks], a, acc[t]) : O::mfma(a, hfr[ks], acc[t]);
     }
   }
   if constexpr (TM) {
