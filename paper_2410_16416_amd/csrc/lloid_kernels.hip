@@ -895,28 +895,31 @@ __global__ __launch_bounds__(kXiThreads) void k_xi2(const MixJob *__restrict__ j
         const int64_t n = s0 + (lane & 31);
         const int64_t nb = n < a1 ? n : a1 - 1;
         const T *brow = ocat + (nb - jb.ocat_abs0) * (int64_t)kcat + (lane >> 5) * O::VEC;
-        // two accumulators (even and odd k-steps) halve the MFMA dependency chain
+        // two accumulators (even and odd k-steps) halve the MFMA dependency
+        // chain.  Blocks of U k-steps issue all their reads before their MFMAs;
+        // in the last block the k-steps past nks read k-step nks - 1 (in
+        // range) and multiply a zero operand, so no k-step waits on its own
+        // read alone and the block has no branches.
         f32x16 acc, acc2;
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[e] = acc2[e] = 0.f;
         constexpr int U = 8;
-        int ks = 0;
-        for (; ks + U <= nks; ks += U) {
+        for (int ks = 0; ks < nks; ks += U) {
           typename O::vec af[U], bf[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            af[u] = *(const typename O::vec *)(arow + (ks + u) * O::KS);
-            bf[u] = *(const typename O::vec *)(brow + (ks + u) * O::KS);
+            const int k = min(ks + u, nks - 1);
+            af[u] = *(const typename O::vec *)(arow + k * O::KS);
+            bf[u] = *(const typename O::vec *)(brow + k * O::KS);
+            if (ks + u >= nks) bf[u] = typename O::vec{};
           }
+          __builtin_amdgcn_sched_barrier(0);   // keep the block's reads ahead of its MFMAs
 #pragma unroll
           for (int u = 0; u < U; u += 2) {
             acc = O::mfma(af[u], bf[u], acc);
             acc2 = O::mfma(af[u + 1], bf[u + 1], acc2);
           }
         }
-        for (; ks < nks; ++ks)
-          acc = O::mfma(*(const typename O::vec *)(arow + ks * O::KS), *(const typename O::vec *)(brow + ks * O::KS),
-                        acc);
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[e] += acc2[e];
 #pragma unroll
