@@ -7,6 +7,7 @@
 // and per-window peak epilogue, and trigger compaction (Sec. II.B: only the
 // triggers leave the device).  FP64 appears only in the sigma^2 sums.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <math.h>
 #include <stdint.h>
 
@@ -891,49 +892,56 @@ __global__ __launch_bounds__(kXiThreads) void k_xi2(const MixJob *__restrict__ j
       int64_t a0 = ws + (l_key[t0] >> 32) - K, a1 = ws + (l_key[t0 + nt - 1] >> 32) + K + 1;
       if (a0 < 0) a0 = 0;
       if (a1 > jb.n_end) a1 = jb.n_end;
-      for (int64_t s0 = a0; s0 < a1; s0 += 32) {
-        const int64_t n = s0 + (lane & 31);
-        const int64_t nb = n < a1 ? n : a1 - 1;
-        const T *brow = ocat + (nb - jb.ocat_abs0) * (int64_t)kcat + (lane >> 5) * O::VEC;
-        // two accumulators (even and odd k-steps) halve the MFMA dependency
-        // chain.  Blocks of U k-steps issue all their reads before their MFMAs;
-        // in the last block the k-steps past nks read k-step nks - 1 (in
-        // range) and multiply a zero operand, so no k-step waits on its own
-        // read alone and the block has no branches.
-        f32x16 acc, acc2;
+      // blocks of U = 10 k-steps when that takes fewer blocks than U = 8 (30
+      // k-steps: 3 instead of 4), else 8; more staging registers than 10 per
+      // block would halve the occupancy
+      auto tiles = [&](auto u_const) {
+        constexpr int U = decltype(u_const)::value;
+        for (int64_t s0 = a0; s0 < a1; s0 += 32) {
+          const int64_t n = s0 + (lane & 31);
+          const int64_t nb = n < a1 ? n : a1 - 1;
+          const T *brow = ocat + (nb - jb.ocat_abs0) * (int64_t)kcat + (lane >> 5) * O::VEC;
+          // two accumulators (even and odd k-steps) halve the MFMA dependency
+          // chain.  Blocks of U k-steps issue all their reads before their MFMAs;
+          // in the last block the k-steps past nks read k-step nks - 1 (in
+          // range) and multiply a zero operand, so no k-step waits on its own
+          // read alone and the block has no branches.
+          f32x16 acc, acc2;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[e] = acc2[e] = 0.f;
-        constexpr int U = 8;
-        for (int ks = 0; ks < nks; ks += U) {
-          typename O::vec af[U], bf[U];
+          for (int e = 0; e < 16; ++e) acc[e] = acc2[e] = 0.f;
+          for (int ks = 0; ks < nks; ks += U) {
+            typename O::vec af[U], bf[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int k = min(ks + u, nks - 1);
-            af[u] = *(const typename O::vec *)(arow + k * O::KS);
-            bf[u] = *(const typename O::vec *)(brow + k * O::KS);
-            if (ks + u >= nks) bf[u] = typename O::vec{};
+            for (int u = 0; u < U; ++u) {
+              const int k = min(ks + u, nks - 1);
+              af[u] = *(const typename O::vec *)(arow + k * O::KS);
+              bf[u] = *(const typename O::vec *)(brow + k * O::KS);
+              if (ks + u >= nks) bf[u] = typename O::vec{};
+            }
+            __builtin_amdgcn_sched_barrier(0);   // keep the block's reads ahead of its MFMAs
+#pragma unroll
+            for (int u = 0; u < U; u += 2) {
+              acc = O::mfma(af[u], bf[u], acc);
+              acc2 = O::mfma(af[u + 1], bf[u + 1], acc2);
+            }
           }
-          __builtin_amdgcn_sched_barrier(0);   // keep the block's reads ahead of its MFMAs
 #pragma unroll
-          for (int u = 0; u < U; u += 2) {
-            acc = O::mfma(af[u], bf[u], acc);
-            acc2 = O::mfma(af[u + 1], bf[u + 1], acc2);
+          for (int e = 0; e < 16; ++e) acc[e] += acc2[e];
+#pragma unroll
+          for (int p = 0; p < 8; ++p) {
+            const int64_t lag = n - ns[p];
+            if (n < a1 && lag >= -K && lag <= K) {
+              const float2 r = acorr[ii[p] * (2 * K + 1) + K + lag];
+              const float dr = acc[2 * p] * sc - (zs[p].x * r.x - zs[p].y * r.y);
+              const float di = acc[2 * p + 1] * sc - (zs[p].x * r.y + zs[p].y * r.x);
+              num[p] += dr * dr + di * di;
+              den[p] += 2.f - 2.f * (r.x * r.x + r.y * r.y);
+            }
           }
         }
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[e] += acc2[e];
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-          const int64_t lag = n - ns[p];
-          if (n < a1 && lag >= -K && lag <= K) {
-            const float2 r = acorr[ii[p] * (2 * K + 1) + K + lag];
-            const float dr = acc[2 * p] * sc - (zs[p].x * r.x - zs[p].y * r.y);
-            const float di = acc[2 * p + 1] * sc - (zs[p].x * r.y + zs[p].y * r.x);
-            num[p] += dr * dr + di * di;
-            den[p] += 2.f - 2.f * (r.x * r.x + r.y * r.y);
-          }
-        }
-      }
+      };
+      if ((nks + 9) / 10 < (nks + 7) / 8) tiles(std::integral_constant<int, 10>{});
+      else tiles(std::integral_constant<int, 8>{});
       // sum each trigger's terms over the 32 lanes (samples) of its half-wave
 #pragma unroll
       for (int p = 0; p < 8; ++p)

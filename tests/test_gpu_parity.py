@@ -347,6 +347,51 @@ def test_xi2_more_triggers_than_one_list_pass():
     assert n_cmp > 0.95 * t.shape[0]
 
 
+@pytest.mark.parametrize("compute", ["f16", "f32"])
+def test_xi2_long_concatenated_basis(compute):
+    """A bank whose concatenated basis takes 18 (FP16) or 144 (FP32) k-steps:
+    the signal-consistency kernel then runs its k-steps in blocks of 10 with a
+    partial last block; every trigger's value matches the oracle (threshold 0:
+    every template triggers in every window)."""
+    from paper_2410_16416_amd import lloid
+    from workloads import SliceSpec, bank_autocorrelation
+    rng = np.random.default_rng(73)
+    specs = [SliceSpec(1024, 0, 160, 128), SliceSpec(256, 160, 96, 96), SliceSpec(64, 544, 80, 64)]
+    bank = configs.random_basis_bank(200, specs, 1024, rng)
+    half = 24
+    r = bank_autocorrelation(bank, half)
+    bank.autocorr = r
+    x = rng.standard_normal(6 * 1024 + 301)
+    n = x.shape[0]
+    h = lloid.bank_from_svd(ctx(), bank, compute)
+    try:
+        assert lloid.lloid_bank_query(h).concat_k == 288
+        t = lloid.lloid_filter(h, 0, x, window=(1, 1), threshold=0.0).triggers
+    finally:
+        lloid.lloid_bank_destroy(h)
+    assert t.shape[0] == 200 * 7
+    z = oracle.lloid_snr(bank, x)
+    a = np.abs(z)
+    starts = oracle.window_starts(7, 1024, 1, 1)
+    worst, n_cmp = 0.0, 0
+    for rec in t:
+        i, s_, w = int(rec["template_id"]), int(rec["sample"]), int(rec["window"])
+        if a[i, starts[w]:min(starts[w + 1], n)].argmax() + starts[w] != s_:
+            continue
+        want = oracle.xi2(z[i], 0, n, s_, r[i])
+        lag = np.arange(-half, half + 1)
+        ok = (s_ + lag >= 0) & (s_ + lag < n)
+        d = z[i, (s_ + lag)[ok]] - z[i, s_] * r[i, ok]
+        den = np.sum(2.0 - 2.0 * np.abs(r[i, ok]) ** 2)
+        eps = EPS_ABS[compute]   # the bound of test_xi2_matches_oracle
+        tol = (4 * eps * np.sum(np.abs(d)) + 4 * eps ** 2 * ok.sum()) / den + 1e-5 * want
+        assert abs(float(rec["xi2"]) - want) <= tol, (i, w, float(rec["xi2"]), want, tol)
+        worst = max(worst, abs(float(rec["xi2"]) - want))
+        n_cmp += 1
+    log(f"[xi2 long K] {compute}: {t.shape[0]} triggers, {n_cmp} compared, max |d xi2| {worst:.2e}")
+    assert n_cmp > 0.9 * t.shape[0]
+
+
 @pytest.mark.parametrize("compute", PRECISIONS)
 def test_subsample_peaks_match_oracle(compute):
     """Every trigger's sub-sample refinement equals the oracle's parabola through
