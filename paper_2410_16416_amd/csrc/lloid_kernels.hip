@@ -214,8 +214,8 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
   // strain window: BN columns + kFirKSup taps (+ the fragments the HR window
   // reads ahead past its last k-step).  With 16-bit operands the copies are
   // padded to WC = 32 mod 64 elements: the 16-byte fragment reads, each lane
-  // in its own copy, then run without LDS bank conflicts (measured with the
-  // bank-conflict counter; other residues mod 64 conflict)
+  // in its own copy, then run without LDS bank conflicts (the bank-conflict
+  // counter reads zero there; at 0, 16, 40 and 48 mod 64 it does not)
   constexpr int WC0 = BN + kFirKSup + 16 + (HR ? 2 * NT * 16 : 0);
   constexpr int WC = O::VEC == 8 ? (WC0 + 31) / 64 * 64 + 32 : WC0;
   __shared__ __attribute__((aligned(16))) T As[2][BM * P];
@@ -394,9 +394,9 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
 // each store instruction writes 32 consecutive channels of two samples.
 // TS: source and low-rate buffer type; TD: operand type of the last hop.
 // 16-bit sources: the fragment of tile t at k-step ks is the VEC-sample block
-// 2 ks + SB t past the lane's first one (tiles are 32 / R = 8 SB samples
-// apart), so a lane reads each block of its whole source window once, all
-// reads issued before the MFMAs.
+// 2 ks + SB t past the lane's first one (the tiles' source windows start
+// 32 / R = 8 SB samples apart), so a lane reads each block of its whole
+// source window once, all reads issued before the MFMAs.
 template <typename TS, bool TM, int SB>
 __device__ __forceinline__ void upsample_blocks(__amdgpu_buffer_rsrc_t rs, int64_t base0,
                                                 const typename Op<TS>::vec *hfr, f32x16 *acc) {
