@@ -393,23 +393,27 @@ __global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs
 // time-major mixing operand, computes D[t][c] with the operands swapped, so
 // each store instruction writes 32 consecutive channels of two samples.
 // TS: source and low-rate buffer type; TD: operand type of the last hop.
-// 16-bit sources: the fragment of tile t at k-step ks is the VEC-sample block
-// 2 ks + SB t past the lane's first one (the tiles' source windows start
-// 32 / R = 8 SB samples apart), so a lane reads each block of its whole
-// source window once, all reads issued before the MFMAs.
+// The fragment of tile t at k-step ks is the VEC-sample block 2 ks + SB t
+// past the lane's first one (the tiles' source windows start 32 / R = SB VEC
+// samples apart), so a lane reads each block of its source window that the
+// MFMAs use once, all reads issued before the MFMAs.  With SB even only the
+// even blocks are used.
 template <typename TS, bool TM, int SB>
 __device__ __forceinline__ void upsample_blocks(__amdgpu_buffer_rsrc_t rs, int64_t base0,
                                                 const typename Op<TS>::vec *hfr, f32x16 *acc) {
   typedef Op<TS> O;
-  static_assert(O::VEC == 8 && O::KS == 2 * O::VEC, "16-bit fragments");
+  static_assert(O::KS == 2 * O::VEC, "two VEC blocks per k-step");
   constexpr int NKS = 64 / O::KS, CT = kUpCols / 32;
   constexpr int NB = 2 * (NKS - 1) + SB * (CT - 1) + 1;
   typename O::vec blk[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    if (SB == 2 && (j & 1)) continue;   // x2 hops use the even blocks only
+    if (SB % 2 == 0 && (j & 1)) continue;
     const int off = (int)((base0 + j * O::VEC) * (int64_t)sizeof(TS));
-    blk[j] = __builtin_bit_cast(typename O::vec, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    if constexpr (O::VEC == 8)
+      blk[j] = __builtin_bit_cast(typename O::vec, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    else
+      blk[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
   }
   __builtin_amdgcn_sched_barrier(0);   // keep every read ahead of the MFMAs
 #pragma unroll
@@ -440,26 +444,10 @@ __device__ __forceinline__ void upsample_task(const UpJob &jb, int lane, int r0,
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(jb.src, jb.src_bytes);
   const int64_t rowoff = (int64_t)(r0 + (lane & 31)) * jb.ld_src;
   f32x16 acc[CT];
-  if constexpr (O::VEC == 8) {
-    const int64_t base0 = rowoff + (((n0 >> lgR) - cR) - jb.src_lo) + (lane >> 5) * O::VEC;
-    if (R == 4) upsample_blocks<TS, TM, 1>(rs, base0, hfr, acc);
-    else upsample_blocks<TS, TM, 2>(rs, base0, hfr, acc);
-  } else {
-    // FP32 sources: one sample per lane and k-step
-#pragma unroll
-    for (int t = 0; t < CT; ++t) {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
-      const int64_t u0 = ((n0 + 32 * t) >> lgR) - cR;   // n0 + 32 t is a multiple of R: exact
-      const int64_t base = rowoff + (u0 - jb.src_lo) + (lane >> 5) * O::VEC;
-#pragma unroll
-      for (int ks = 0; ks < NKS; ++ks) {
-        const int off = (int)((base + ks * O::KS) * (int64_t)sizeof(TS));
-        const typename O::vec a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
-        acc[t] = TM ? O::mfma(hfr[ks], a, acc[t]) : O::mfma(a, hfr[ks], acc[t]);
-      }
-    }
-  }
+  const int64_t base0 = rowoff + (((n0 >> lgR) - cR) - jb.src_lo) + (lane >> 5) * O::VEC;
+  constexpr int SB4 = 8 / O::VEC;   // 32 / R in VEC blocks for R = 4; twice that for R = 2
+  if (R == 4) upsample_blocks<TS, TM, SB4>(rs, base0, hfr, acc);
+  else upsample_blocks<TS, TM, 2 * SB4>(rs, base0, hfr, acc);
   if constexpr (TM) {
     // lane holds channel r0 + lane % 32 at samples n0 + 32 t + 8 g + 4 (lane / 32) + q
     const int c = r0 + (lane & 31);
