@@ -103,10 +103,14 @@ def fir(basis: np.ndarray, x: Seq, shift: int, k_lo: int, k_hi: int, chunk: int 
     n_taps = basis.shape[1]
     out = np.empty((basis.shape[0], k_hi - k_lo))
     rev = np.ascontiguousarray(basis[:, ::-1])       # rev[l, m'] = basis[l, N-1-m']
+    # the windows are copied out contiguously so that the dot products run in
+    # BLAS; a copy holds at most 2^27 values (long filters take fewer outputs)
+    chunk = max(1, min(chunk, (1 << 27) // n_taps))
     for c0 in range(k_lo, k_hi, chunk):
         c1 = min(k_hi, c0 + chunk)
         xs = x.window(c0 - shift - n_taps + 1, c1 - shift)
-        win = sliding_window_view(xs, n_taps)         # win[k', m'] = x[c0 - shift - N + 1 + k' + m']
+        # win[k', m'] = x[c0 - shift - N + 1 + k' + m']
+        win = np.ascontiguousarray(sliding_window_view(xs, n_taps))
         out[:, c0 - k_lo:c1 - k_lo] = rev @ win.T
     return out
 
@@ -251,7 +255,7 @@ def triggers(z: np.ndarray, n_lo: int, f0: int, num: int, den: int, threshold: f
 
 
 def subsample_peak(a_prev, a_peak, a_next):
-    """Sub-sample refinement of a sampled maximum (Sec. III.B names sub-sample
+    """Sub-sample refinement of a sampled maximum (Sec. III.C names sub-sample
     interpolation at the SNR peak as the feature behind the port's slightly
     lower network SNRs).  The parabola through (-1, a_prev), (0, a_peak),
     (+1, a_next) has its vertex at
