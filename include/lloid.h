@@ -69,7 +69,7 @@ typedef enum {
   LLOID_ETRUNC = -4,  /* output buffer too small; the required count is returned */
   LLOID_EDEVICE = -5, /* a HIP runtime call failed */
   LLOID_EORDER = -6,  /* stream stride does not continue the previous one */
-  LLOID_EDATA = -7    /* non-finite strain sample */
+  LLOID_EDATA = -7    /* strain sample not finite once converted to FP32 and scaled */
 } lloid_status;
 
 typedef enum { LLOID_F64 = 0, LLOID_F32 = 1, LLOID_F16 = 2, LLOID_BF16 = 3 } lloid_dtype;
@@ -106,7 +106,7 @@ typedef struct {
 } lloid_bank_desc;
 
 /* A trigger: the SNR peak of one template in one window with |z| >= threshold,
- * with its sub-sample refinement (Sec. III.B: the interpolation at the SNR
+ * with its sub-sample refinement (Sec. III.C: the interpolation at the SNR
  * peak that the paper's port leaves out) and its signal-consistency value
  * (Sec. II.A: phase and xi^2 are computed for every trigger). */
 typedef struct {
@@ -335,7 +335,9 @@ typedef struct {
 /* Condition one block of strain (host or device, F64 or F32, n >= 1 samples
  * at full_rate_hz) into out (n floats, host or device: the whitened and gated
  * strain, ready for lloid_filter).  psd_out: NULL or host [L/2 + 1], the PSD
- * used.  n_gated: NULL or the number of samples zeroed by the gate.
+ * used (the device estimates and applies it in FP32, a compensated mean over
+ * the segments; a caller's PSD is rounded to FP32).  n_gated: NULL or the
+ * number of samples zeroed by the gate.
  * EINVAL on a bad length, rate or option, a block shorter than one segment
  * without a PSD, or a non-finite PSD value; EDATA if a strain sample is not
  * finite.  Runs on the context's stream and returns when the results are in

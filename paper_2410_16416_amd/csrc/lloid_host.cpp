@@ -980,7 +980,7 @@ extern "C" lloid_status lloid_condition(lloid_ctx *ctx, int32_t full_rate_hz, co
   if (host_strain) add((size_t)n, dtype_size(dtype));
   add((size_t)n, 4);                       // float strain
   add((size_t)(nseg_p * nf), 4);           // periodograms
-  add((size_t)nf, 8);                      // PSD
+  add((size_t)nf, 4);                      // PSD (FP32 on the device)
   add((size_t)nf, 4);                      // gain
   add((size_t)(nseg_w * L), 4);            // whitened segments
   if (gating) add((size_t)n, 4), add((size_t)n, 1);
@@ -998,7 +998,7 @@ extern "C" lloid_status lloid_condition(lloid_ctx *ctx, int32_t full_rate_hz, co
   }
   float *x = cv.take<float>((size_t)n);
   float *parts = cv.take<float>((size_t)(nseg_p * nf));
-  double *psd = cv.take<double>((size_t)nf);
+  float *psd = cv.take<float>((size_t)nf);
   float *gain = cv.take<float>((size_t)nf);
   float *y = cv.take<float>((size_t)(nseg_w * L));
   float *xw = gating ? cv.take<float>((size_t)n) : nullptr;
@@ -1009,17 +1009,23 @@ extern "C" lloid_status lloid_condition(lloid_ctx *ctx, int32_t full_rate_hz, co
   HIP_TRY(launch_fill_u8(bad, sizeof(int), st));
   HIP_TRY(launch_fill_u8(count, 8, st));
   if (gating) HIP_TRY(launch_fill_u8(mask, (size_t)n, st));
-  if (!estimate) HIP_TRY(hipMemcpyAsync(psd, opts->psd, (size_t)nf * 8, hipMemcpyHostToDevice, st));
+  std::vector<float> psd_h((size_t)nf);
+  if (!estimate) {
+    for (int f = 0; f < nf; ++f) psd_h[f] = (float)opts->psd[f];
+    HIP_TRY(hipMemcpyAsync(psd, psd_h.data(), (size_t)nf * 4, hipMemcpyHostToDevice, st));
+  }
   HIP_TRY(launch_convert(d_strain, dtype, n, x, 0, n, 1.f, bad, st));
-  HIP_TRY(launch_condition(x, n, L, estimate, (double)full_rate_hz, parts, psd, gain, y, xw, opts->gate_threshold,
+  HIP_TRY(launch_condition(x, n, L, estimate, (float)full_rate_hz, parts, psd, gain, y, xw, opts->gate_threshold,
                            opts->gate_half_width, mask, dout, count, st));
   int h_bad = 0;
   unsigned long long h_count = 0;
   HIP_TRY(hipMemcpyAsync(&h_bad, bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(&h_count, count, sizeof h_count, hipMemcpyDeviceToHost, st));
-  if (psd_out) HIP_TRY(hipMemcpyAsync(psd_out, psd, (size_t)nf * 8, hipMemcpyDeviceToHost, st));
+  if (psd_out) HIP_TRY(hipMemcpyAsync(psd_h.data(), psd, (size_t)nf * 4, hipMemcpyDeviceToHost, st));
   if (host_out) HIP_TRY(hipMemcpyAsync(out, dout, (size_t)n * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  if (psd_out)
+    for (int f = 0; f < nf; ++f) psd_out[f] = (double)psd_h[f];
   if (h_bad) return fail(LLOID_EDATA, "strain holds a non-finite sample");
   if (n_gated) *n_gated = (int64_t)h_count;
   return LLOID_OK;

@@ -196,8 +196,8 @@ hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems,
 // add into xw (or straight into out without gating), gating into out with
 // the gated-sample count added to *count (mask zeroed by the caller).
 constexpr int kCondMinLen = 64, kCondMaxLen = 4096;
-hipError_t launch_condition(const float *x, int64_t T, int L, bool estimate, double f0, float *parts,
-                            double *psd, float *gain, float *y, float *xw, float gate_thr, int gate_half,
+hipError_t launch_condition(const float *x, int64_t T, int L, bool estimate, float f0, float *parts,
+                            float *psd, float *gain, float *y, float *xw, float gate_thr, int gate_half,
                             uint8_t *mask, float *out, unsigned long long *count, hipStream_t s);
 // Coincidences of two sorted trigger lists: per-trigger counts (na slots),
 // their scan, pairs at the scanned offsets; *bad set when a list is out of order.

@@ -5,7 +5,8 @@
 // GEMM on MFMA, interpolation of the low-rate orthogonal SNR to the full
 // rate, the mixing GEMM over the concatenated basis with a fused complex-SNR
 // and per-window peak epilogue, and trigger compaction (Sec. II.B: only the
-// triggers leave the device).  FP64 appears only in the sigma^2 sums.
+// triggers leave the device).  FP64 arithmetic appears only in the sigma^2 sums
+// (FP64 inputs are converted once).
 #include <hip/hip_runtime.h>
 #include <type_traits>
 #include <math.h>
@@ -82,12 +83,13 @@ __global__ void k_convert(const TI *__restrict__ src, int64_t n, float *__restri
   int64_t a = dst_lo + t;
   float v = 0.f;
   if (a >= 0 && a < n) {
-    double s = (double)src[a];
-    if (!isfinite(s)) {
+    // FP32 from here on: the scale is a power of two, so the product is the
+    // scaled value rounded once; a sample that is not finite in FP32 is flagged
+    v = (float)src[a] * scale;
+    if (!isfinite(v)) {
       atomicOr(bad, 1);
-      s = 0.0;
+      v = 0.f;
     }
-    v = (float)(s * (double)scale);
   }
   dst[t] = v;
 }
@@ -1152,23 +1154,30 @@ __global__ __launch_bounds__(256) void k_cond_segment(const float *__restrict__ 
   for (int n = threadIdx.x; n < L; n += blockDim.x) y[(int64_t)blockIdx.x * L + n] = Y[n].x * inv;
 }
 
-// Per bin f <= L/2: the mean periodogram in FP64, c_f / (nseg f0 sum w^2) times
-// the sum over segments (sum w^2 = 3 L / 8 for the periodic Hann window).
-__global__ void k_psd_mean(const float *__restrict__ parts, int64_t nseg, int L, double f0, double *__restrict__ psd) {
+// Per bin f <= L/2: the mean periodogram, c_f / (nseg f0 sum w^2) times the
+// sum over segments (sum w^2 = 3 L / 8 for the periodic Hann window).  The
+// sum over segments is compensated (Kahan): in FP32 its error stays at a few
+// units of rounding whatever the number of segments.
+__global__ void k_psd_mean(const float *__restrict__ parts, int64_t nseg, int L, float f0, float *__restrict__ psd) {
   const int nf = L / 2 + 1;
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nf) return;
-  double acc = 0.0;
-  for (int64_t m = 0; m < nseg; ++m) acc += (double)parts[m * nf + f];
-  const double c = (f == 0 || f == L / 2) ? 1.0 : 2.0;
-  psd[f] = c * acc / ((double)nseg * f0 * (3.0 * L / 8.0));
+  float acc = 0.f, comp = 0.f;
+  for (int64_t m = 0; m < nseg; ++m) {
+    const float y = parts[m * nf + f] - comp;
+    const float t = acc + y;
+    comp = (t - acc) - y;
+    acc = t;
+  }
+  const float c = (f == 0 || f == L / 2) ? 1.f : 2.f;
+  psd[f] = c * acc / ((float)nseg * f0 * (0.375f * (float)L));
 }
 
-__global__ void k_psd_gain(const double *__restrict__ psd, int nf, double f0, float *__restrict__ gain) {
+__global__ void k_psd_gain(const float *__restrict__ psd, int nf, float f0, float *__restrict__ gain) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nf) return;
-  const double s = psd[f];
-  gain[f] = s > 0.0 ? (float)(1.0 / sqrt(s * f0 / 2.0)) : 0.f;
+  const float s = psd[f];
+  gain[f] = s > 0.f ? 1.f / sqrtf(s * f0 * 0.5f) : 0.f;
 }
 
 // xw[n] = the two segments' outputs over sample n (segment m starts at m L/2;
@@ -1446,8 +1455,8 @@ hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_w
   return hipGetLastError();
 }
 
-hipError_t launch_condition(const float *x, int64_t T, int L, bool estimate, double f0, float *parts,
-                            double *psd, float *gain, float *y, float *xw, float gate_thr, int gate_half,
+hipError_t launch_condition(const float *x, int64_t T, int L, bool estimate, float f0, float *parts,
+                            float *psd, float *gain, float *y, float *xw, float gate_thr, int gate_half,
                             uint8_t *mask, float *out, unsigned long long *count, hipStream_t s) {
   int lg = 0;
   while ((1 << lg) < L) ++lg;

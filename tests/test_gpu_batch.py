@@ -5,6 +5,8 @@ bit for bit (every output is accumulated in the same order whatever the tile,
 chunk or batch it lands in), and must match the FP64 oracle.
 """
 
+import functools
+
 import numpy as np
 import pytest
 
@@ -171,3 +173,101 @@ def test_autotune_picks_the_fastest_and_caches(tmp_path):
         for h in handles:
             lloid.lloid_bank_destroy(h)
         lloid.lloid_ctx_destroy(c2)
+
+
+# Banks of the batched measurement's recipe at its real shapes: two drawn
+# with real chirp SVD spectra (bank 36: 2000 templates, 2048 + 1024 Hz with
+# 208 + 256 basis filters; bank 53: four slices at 2048/1024/512/128 Hz,
+# 1899 templates), the longest single-slice filter among the measured banks
+# (bank 35: 121456 taps, random orthonormal basis) and the recipe's extreme
+# (one 64 s slice of 131072 taps, 400 basis filters, 2000 templates).
+C3_SECONDS = 70
+C3_WINDOWS = {"bank36": (0, 66, 67), "bank53": (0, 66, 67), "bank35": (66, 67), "longest": (66, 67)}
+
+
+@functools.lru_cache(maxsize=None)
+def c3_parity_case():
+    from workloads import Injection, add_waveform, inject
+    f0 = 2048
+    banks = {"bank36": configs.batched_bank(36), "bank53": configs.batched_bank(53),
+             "bank35": configs.batched_c3_bank(35), "longest": configs.longest_c3_bank()}
+    x = np.random.default_rng(configs.seed(3, 5)).standard_normal(C3_SECONDS * f0)
+    injected = {"bank36": (Injection(11, 66 * f0 + 700, 12.0, 0.7), None),
+                "bank53": (Injection(1234, 67 * f0 + 300, 15.0, 2.2), None),
+                "bank35": (None, (77, 66 * f0 + 1200, 15.0, 1.1)),
+                "longest": (None, (1500, 67 * f0 + 1800, 15.0, 2.0))}
+    for name, (inj, rec) in injected.items():
+        if inj is not None:
+            x = inject(x, banks[name].family, [inj])
+        else:
+            t, t0, amp, phase = rec
+            x = add_waveform(x, amp * configs.reconstructed_waveform(banks[name], t, phase), t0)
+    tmpl = {k: (v[0].template if v[0] is not None else v[1][0]) for k, v in injected.items()}
+    ref = {}
+    for name, b in banks.items():
+        for w in C3_WINDOWS[name]:
+            z = oracle.lloid_snr(b, x, w * f0, (w + 1) * f0)
+            _, pa, ps, _ = oracle.peak_table(z, w * f0, f0, 1, 1)
+            ref[name, w] = (z, pa, ps)
+    return banks, x, tmpl, ref
+
+
+@pytest.mark.parametrize("compute", ["f16", "bf16", "f32"])
+def test_c3_shaped_banks_match_oracle(compute):
+    """The batched form at the batched recipe's real shapes against the FP64
+    oracle: every template's 1 s window peaks of the batch call on sampled
+    windows (the first, and two with an injection, where the longest filters
+    have their whole history), and the complex SNR series of a template subset
+    (each bank alone; its peaks equal the batch's bit for bit)."""
+    import torch
+    from paper_2410_16416_amd import lloid
+    from gpu_util import compare_series, record_precision
+    banks, x, tmpl, ref = c3_parity_case()
+    names = list(banks)
+    log(f"[c3-oracle] compute={compute} " + " | ".join(f"{k}: {banks[k].describe()}" for k in names))
+    handles = [lloid.bank_from_svd(ctx(), banks[k], compute) for k in names]
+    f0, n = 2048, x.shape[0]
+    stats = {}
+    try:
+        res = lloid.lloid_filter_batch(handles, 0, x, window=(1, 1), peaks=True)
+        for k, name in enumerate(names):
+            F = banks[name].n_templates
+            sub = np.unique(np.concatenate([np.arange(0, F, max(1, F // 48)), [tmpl[name]]]))
+            snr = torch.zeros((F, n, 2), dtype=torch.float32, device="cuda")
+            one = lloid.lloid_filter(handles[k], 0, x, window=(1, 1), peaks=True, snr_out=snr)
+            assert np.array_equal(one.peak_snr, res.peak_snr[k]), name
+            assert np.array_equal(one.peak_sample, res.peak_sample[k]), name
+            wins = C3_WINDOWS[name]
+            zg = torch.cat([snr[torch.from_numpy(sub).cuda(), w * f0:(w + 1) * f0] for w in wins], dim=1).cpu().numpy()
+            del snr
+            zg = zg[..., 0].astype(np.float64) + 1j * zg[..., 1].astype(np.float64)
+            zo = np.concatenate([ref[name, w][0][sub] for w in wins], axis=1)
+            s = compare_series(zg, zo, compute, f"c3/{name}/{compute}")
+            peaks = {"max_abs_peak": 0.0, "near_ties": 0, "windows": 0}
+            for w in wins:
+                z, pa, ps = ref[name, w]
+
+                class R:
+                    pass
+                r = R()
+                r.peak_snr, r.peak_sample = res.peak_snr[k][:, [w]], res.peak_sample[k][:, [w]]
+                p = compare_peaks(r, np.abs(z), pa, ps, compute, n_lo=w * f0, label=f"c3/{name}/{compute}/w{w}",
+                                  eps_series=s["max_abs"])
+                peaks["max_abs_peak"] = max(peaks["max_abs_peak"], p["max_abs_peak"])
+                peaks["near_ties"] += p["near_ties"]
+                peaks["windows"] += p["windows"]
+            # the injected template's peak stands out of the noise in its window
+            wi = [w for w in wins if w in (66, 67)]
+            top = max(res.peak_snr[k][tmpl[name], w] for w in wi)
+            assert top > 6.0, (name, top)
+            stats[name] = {**s, **peaks}
+            log(f"  {name}: series {s} peaks {peaks}")
+    finally:
+        for h in handles:
+            lloid.lloid_bank_destroy(h)
+    worst = {"max_abs": max(v["max_abs"] for v in stats.values()),
+             "max_rel_at6": max(v["max_rel_at6"] for v in stats.values()),
+             "max_abs_peak": max(v["max_abs_peak"] for v in stats.values()),
+             "near_ties": sum(v["near_ties"] for v in stats.values()),
+             "windows": sum(v["windows"] for v in stats.values())}
+    record_precision("batched_c3 banks 35, 36, 53 and the 131072-tap extreme, sampled 1 s windows", compute, **worst)

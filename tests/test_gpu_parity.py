@@ -47,7 +47,7 @@ def test_c0_series_and_peaks(compute):
     res = run_filter(wl.bank, x, compute, (1, 10), snr=True)
     zg = gpu_complex(res)
     s = compare_series(zg, z, compute, f"c0/{compute}")
-    p = compare_peaks(res, np.abs(z), pa, ps, compute, label=f"c0/{compute}")
+    p = compare_peaks(res, np.abs(z), pa, ps, compute, label=f"c0/{compute}", eps_series=s["max_abs"])
     log(f"  series {s} peaks {p}")
     inj = wl.injections[0]
     assert res.peak_sample[inj.template, 40] == 4146
@@ -66,7 +66,7 @@ def test_mini_multirate_ragged(compute):
     wl, x, z, pa, ps, ph = mini_case()
     res = run_filter(wl.bank, x, compute, (1, 4), snr=True)
     s = compare_series(gpu_complex(res), z, compute, f"mini/{compute}")
-    p = compare_peaks(res, np.abs(z), pa, ps, compute, label=f"mini/{compute}")
+    p = compare_peaks(res, np.abs(z), pa, ps, compute, label=f"mini/{compute}", eps_series=s["max_abs"])
     log(f"  series {s} peaks {p}")
 
 
@@ -197,7 +197,7 @@ def test_c1_bank_short_block(compute):
     zg = gpu_complex(res)[tsel]
     s = compare_series(zg, z, compute, f"c1short/{compute}")
     res.peak_snr, res.peak_sample = res.peak_snr[tsel], res.peak_sample[tsel]
-    p = compare_peaks(res, np.abs(z), pa, ps, compute, label=f"c1short/{compute}")
+    p = compare_peaks(res, np.abs(z), pa, ps, compute, label=f"c1short/{compute}", eps_series=s["max_abs"])
     log(f"  series {s} peaks {p}")
     record_precision(f"multirate_c1 bank, 36 s block, {len(tsel)} templates, every sample", compute, **s, **p)
     for inj in injs:
@@ -214,7 +214,7 @@ def c1_full_inputs():
     return wl
 
 
-@pytest.mark.parametrize("compute", ["f16", "f32"])
+@pytest.mark.parametrize("compute", PRECISIONS)
 def test_c1_full_size_sampled_windows(compute):
     """2 detectors x 1024 s at the benchmark's launch configuration; the oracle
     recomputes all 1024 templates on sampled 1 s windows (injection windows,

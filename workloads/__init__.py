@@ -11,12 +11,12 @@ oracle and the HIP library each implement that on their own.
 
 from .chirp import ChirpFamily, mass_chirps, duration_chirps
 from .bank import SvdBank, BankSlice, SliceSpec, build_svd_bank, slice_matrix, autocorrelation, bank_autocorrelation
-from .strain import white_noise, Injection, inject, draw_injections
+from .strain import white_noise, Injection, inject, draw_injections, add_waveform
 from . import configs
 
 __all__ = [
     "ChirpFamily", "mass_chirps", "duration_chirps",
     "SvdBank", "BankSlice", "SliceSpec", "build_svd_bank", "slice_matrix", "autocorrelation",
     "bank_autocorrelation",
-    "white_noise", "Injection", "inject", "draw_injections", "configs",
+    "white_noise", "Injection", "inject", "draw_injections", "add_waveform", "configs",
 ]

@@ -222,12 +222,35 @@ def random_basis_bank(n_templates: int, specs, f0: int, rng: np.random.Generator
     return bank
 
 
-def batched_c3_banks(n_banks: int = 64, f0: int = 2048):
-    """Uneven banks for the batched measurement: shapes drawn by draw_bank_specs,
+def batched_c3_bank(index: int, f0: int = 2048) -> SvdBank:
+    """Bank `index` of the batched measurement: shape drawn by draw_bank_specs,
     values from random_basis_bank."""
-    banks = []
-    for i in range(n_banks):
-        rng = np.random.default_rng(seed(3, 9) + 1000 * i)
-        n_t, d_max, specs = draw_bank_specs(rng, f0)
-        banks.append(random_basis_bank(n_t, specs, f0, rng))
-    return banks
+    rng = np.random.default_rng(seed(3, 9) + 1000 * index)
+    n_t, d_max, specs = draw_bank_specs(rng, f0)
+    return random_basis_bank(n_t, specs, f0, rng)
+
+
+def batched_c3_banks(n_banks: int = 64, f0: int = 2048):
+    """Uneven banks for the batched measurement (banks 0 .. n_banks - 1)."""
+    return [batched_c3_bank(i, f0) for i in range(n_banks)]
+
+
+def longest_c3_bank(f0: int = 2048) -> SvdBank:
+    """The batched recipe's extreme FIR shape: one slice at f0 with the longest
+    filter (64 s, 131072 taps), the most basis filters (400) and the most
+    templates (2000); random orthonormal basis as in random_basis_bank."""
+    rng = np.random.default_rng(seed(3, 7))
+    return random_basis_bank(2000, [SliceSpec(f0, 0, 64 * f0, 400)], f0, rng)
+
+
+def reconstructed_waveform(bank: SvdBank, template: int, phase: float = 0.0) -> np.ndarray:
+    """Template `template` of a single-slice bank at the full rate, as its SVD
+    bank reconstructs it (row r of M U; tap m is m samples before
+    coalescence): cos(phase) h_cos + sin(phase) h_sin, unit-normalised.  An
+    injection for banks without a chirp family (random bases)."""
+    if len(bank.slices) != 1 or bank.slices[0].rate != bank.f0 or bank.slices[0].start_tap != 0:
+        raise ValueError("needs a single slice at the full rate starting at tap 0")
+    sl = bank.slices[0]
+    h = sl.mixing[[2 * template, 2 * template + 1]] @ sl.basis
+    g = np.cos(phase) * h[0] + np.sin(phase) * h[1]
+    return g / np.linalg.norm(g)

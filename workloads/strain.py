@@ -39,14 +39,20 @@ def injection_waveform(family: ChirpFamily, inj: Injection) -> np.ndarray:
     return inj.snr * g / np.linalg.norm(g)
 
 
+def add_waveform(x: np.ndarray, w: np.ndarray, t0: int) -> np.ndarray:
+    """x[t0 - j] += w[j] for every tap j (samples outside x are dropped); a copy."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    j = np.arange(w.shape[0])
+    n = t0 - j
+    ok = (n >= 0) & (n < x.shape[0])
+    x[n[ok]] += w[ok]
+    return x
+
+
 def inject(x: np.ndarray, family: ChirpFamily, injections) -> np.ndarray:
     x = np.array(x, dtype=np.float64, copy=True)
     for inj in injections:
-        w = injection_waveform(family, inj)
-        j = np.arange(w.shape[0])
-        n = inj.t0 - j
-        ok = (n >= 0) & (n < x.shape[0])
-        x[n[ok]] += w[ok]
+        x = add_waveform(x, injection_waveform(family, inj), inj.t0)
     return x
 
 
