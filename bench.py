@@ -12,11 +12,15 @@ resident in HBM to triggers in pinned host memory, through the C ABI.
 
 Prints one JSON line: whole-job template-samples of SNR per second, the
 roofline of the dominant kernel (device time from HIP events on the
-library's stream over the timed steps), the plain FP32 path beside it, the
-same path with every trigger's xi2 signal-consistency value (bank
-autocorrelations over 2K + 1 lags), the conditioning of one detector's
-block (PSD, whitening, gating), the coincidence of the two detectors'
-triggers, and the FP64 oracle timed on the host cores on a bounded sample.
+library's stream over the timed steps), the plain FP32 and the BF16 paths
+beside it, the SNR-series output mode (HBM-bound), the same path with every
+trigger's xi2 signal-consistency value (bank autocorrelations over 2K + 1
+lags), the latency of the 64-template single-rate block, the conditioning of
+one detector's block (PSD, whitening, gating), the coincidence of the two
+detectors' triggers, the batched form (64 uneven banks) and the serving form
+(128 banks streamed in 1 s strides: p50/p99 stride latency at 16x real time
+and at saturation), and the FP64 oracle timed on the host cores (one
+single-threaded process per core over disjoint ranges) on a bounded sample.
 """
 
 from __future__ import annotations
@@ -90,48 +94,100 @@ def load_traffic(stage: str, compute: str):
 
 
 def cpu_baseline_1thread(wl, sample_s: float):
-    """The same oracle sample restricted to one BLAS thread (the paper's
-    single-CPU-core framing)."""
+    """The oracle on one BLAS thread in this process (the paper's single-CPU-core
+    framing): detector 0, outputs on [32 s, 32 s + sample_s)."""
     try:
         from threadpoolctl import threadpool_limits
     except Exception:
         return None
     with threadpool_limits(limits=1):
-        r = cpu_baseline(wl, sample_s)
-    r["cores"] = 1
-    return r
-
-
-def cpu_baseline(wl, sample_s: float):
-    """The FP64 oracle on a bounded sample: detector 0, outputs on
-    [32 s, 32 s + sample_s) with the 32 s of history the longest slice needs."""
-    import numpy as np
-    import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count()
-    f0 = wl.bank.f0
-    lo, hi = 32 * f0, int((32 + sample_s) * f0)
-    x = wl.strains[0][: hi + 4 * f0]
-    t0 = time.perf_counter()
-    z = oracle.lloid_snr(wl.bank, x, lo, hi)
-    _ = oracle.triggers(z, lo, f0, 1, 1, 4.0)
-    wall = time.perf_counter() - t0
-    value = wl.bank.n_templates * (hi - lo) / wall
-    return {"value": round(value, 1), "unit": "template-samples/s", "cores": int(threads), "kind": "oracle",
+        r = _oracle_range(wl.bank, wl.strains[0], 32.0, 32.0 + sample_s, 1.0)
+    return {"value": round(r["samples"] / r["wall"], 1), "unit": "template-samples/s", "cores": 1,
+            "kind": "oracle",
             "sample": f"detector 0, outputs on [32 s, {32 + sample_s:g} s) of the same workload (all "
-                      f"{wl.bank.n_templates} templates, 32 s history), FP64 NumPy/SciPy multi-rate form "
-                      f"plus window peaks and triggers; wall {wall:.2f} s on {threads} BLAS threads "
-                      f"({os.cpu_count()} host cores visible)"}
+                      f"{wl.bank.n_templates} templates, 32 s history), FP64 NumPy/SciPy multi-rate form plus "
+                      f"window peaks and triggers; wall {r['wall']:.2f} s on 1 BLAS thread"}
+
+
+def _oracle_range(bank, x, s_lo: float, s_hi: float, piece_s: float):
+    """Oracle outputs and triggers of x on [s_lo, s_hi) seconds in pieces of
+    piece_s seconds (bounded memory), timed."""
+    import oracle
+    f0 = bank.f0
+    t0 = time.perf_counter()
+    n_trig = 0
+    a = int(s_lo * f0)
+    end = int(s_hi * f0)
+    # each piece starts its strain 34 s (the longest filter plus the resampler
+    # halos) before its outputs, at a multiple of 2^7 samples: the multi-rate
+    # form is shift-equivariant by such multiples, so the outputs are those of
+    # the whole block
+    hist = 34 * f0
+    while a < end:
+        b = min(end, a + int(piece_s * f0))
+        o = max(0, (a - hist) // 128 * 128)
+        z = oracle.lloid_snr(bank, x[o: b + 4 * f0], a - o, b - o)
+        n_trig += len(oracle.triggers(z, a, f0, 1, 1, 4.0))
+        a = b
+    return {"samples": bank.n_templates * (end - int(s_lo * f0)), "wall": time.perf_counter() - t0,
+            "triggers": n_trig}
+
+
+def _cpu_worker(bank, x, s_lo, s_hi):
+    """One single-threaded oracle process (spawned: BLAS threads limited before
+    numpy is imported)."""
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        return _oracle_range(bank, x, s_lo, s_hi, 8.0)
+
+
+def cpu_baseline(wl, seconds_per_worker: float, workers: int):
+    """The FP64 oracle on the host cores: `workers` single-threaded processes,
+    each computing detector 0's outputs on its own disjoint range of
+    seconds_per_worker seconds from 32 s on (the oracle's sub-range
+    evaluation, each range with the history it needs); the value is all
+    ranges' template-samples over the wall time from the first start to the
+    last end.  Run before the GPU is initialised."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    f0 = wl.bank.f0
+    total_s = wl.n_samples / f0
+    workers = max(1, min(workers, int((total_s - 32) // seconds_per_worker)))
+    ranges = [(32 + k * seconds_per_worker, 32 + (k + 1) * seconds_per_worker) for k in range(workers)]
+    x = wl.strains[0][: int(ranges[-1][1] * f0) + 4 * f0]
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        # start every worker (imports done) before the clock starts
+        list(ex.map(_cpu_warm, range(workers)))
+        t0 = time.perf_counter()
+        res = list(ex.map(_cpu_worker, [wl.bank] * workers, [x] * workers, [r[0] for r in ranges],
+                          [r[1] for r in ranges]))
+        wall = time.perf_counter() - t0
+    samples = sum(r["samples"] for r in res)
+    return {"value": round(samples / wall, 1), "unit": "template-samples/s", "cores": workers, "kind": "oracle",
+            "sample": f"detector 0, outputs on [32 s, {ranges[-1][1]:g} s) of the same workload (all "
+                      f"{wl.bank.n_templates} templates) split into {workers} disjoint ranges of "
+                      f"{seconds_per_worker:g} s, one single-threaded process each with its own history; "
+                      f"FP64 NumPy/SciPy multi-rate form plus window peaks and triggers; wall {wall:.2f} s "
+                      f"({os.cpu_count()} host cores visible)",
+            "triggers": int(sum(r["triggers"] for r in res))}
+
+
+def _cpu_warm(_):
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    import numpy  # noqa: F401
+    import scipy.signal  # noqa: F401
+    import oracle  # noqa: F401
+    return 0
 
 
 def run_path(lloid, ctx, wl, xs, compute, steps, warmup, tbufs, args):
     import torch
     bank = lloid.bank_from_svd(ctx, wl.bank, compute)
     try:
-        if compute == args.compute:
+        if compute != "f32" or args.compute == "f32":
             tiles = pick_tiles(lloid, ctx, [bank], args)
         else:   # the plain FP32 reference path keeps the default tiles
             lloid.lloid_ctx_set_tiles(ctx, 0, 0)
@@ -180,6 +236,53 @@ def batched_work(banks, seconds):
     return fir, mix
 
 
+def measure_batched(lloid, ctx, banks, xs, compute, steps, warmup, seconds, args, tiles_from_cache=True):
+    """One step filters both detectors' strain (device) with every bank
+    (lloid_filter_batch, one launch per stage per chunk); returns the step's
+    throughput, wall time and algorithmic MFMA fraction."""
+    import torch
+    hs = [lloid.bank_from_svd(ctx, b, compute) for b in banks]
+    try:
+        if tiles_from_cache:
+            tiles = pick_tiles(lloid, ctx, hs, args)
+        else:   # the plain FP32 reference path keeps the default tiles
+            lloid.lloid_ctx_set_tiles(ctx, 0, 0)
+            tiles = {"fir_variant": 0, "mix_variant": 0, "source": "defaults"}
+        cap = sum(b.n_templates for b in banks) * seconds
+        tbuf = torch.empty(cap * lloid.TRIGGER_DTYPE.itemsize, dtype=torch.uint8, pin_memory=True)
+
+        def step():
+            n = 0
+            for d, x in enumerate(xs):
+                n += lloid.lloid_filter_batch(hs, d, x, window=(1, 1), triggers_out=tbuf).n_triggers
+            return n
+        for _ in range(max(warmup, 1)):
+            step()
+        torch.cuda.synchronize()
+        lloid.lloid_ctx_profile(ctx, True)
+        lloid.lloid_ctx_stage_times(ctx, reset=True)
+        t = time.perf_counter()
+        for _ in range(steps):
+            ntr = step()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / steps
+        stages = lloid.lloid_ctx_stage_times(ctx, reset=True)
+        lloid.lloid_ctx_profile(ctx, False)
+    finally:
+        for h in hs:
+            lloid.lloid_bank_destroy(h)
+    f0 = banks[0].f0
+    samples = sum(b.n_templates for b in banks) * seconds * f0 * len(xs)
+    fir, mix = batched_work(banks, seconds * len(xs))
+    return {"value": round(samples / wall, 1), "ms_per_step": round(wall * 1e3, 2), "steps": steps,
+            "triggers_per_step": int(ntr),
+            "algorithmic_tflop_per_step": round((fir + mix) / 1e12, 2),
+            "algorithmic_tflops": round((fir + mix) / wall / 1e12, 1),
+            "mfma_frac_of_peak": round((fir + mix) / wall / 1e12 / PEAK_TFLOPS[compute], 4),
+            "stage_ms_per_step": {k: round(v[0] / steps, 3) for k, v in stages.items()},
+            "tiles": tiles}
+
+
 def bench_batched(args):
     """64 uneven banks (F 200-2000, 1-4 slices, filters 0.5-64 s), 2 detectors x
     512 s; one step filters both detectors with every bank, one launch per
@@ -201,46 +304,10 @@ def bench_batched(args):
     torch.cuda.init()
     ctx = lloid.lloid_ctx_create(0)
     out = {}
-    tiles = {}
     for compute in [args.compute] + (["f32"] if args.f32_steps and args.compute != "f32" else []):
-        hs = [lloid.bank_from_svd(ctx, b, compute) for b in banks]
-        if compute == args.compute:
-            tiles[compute] = pick_tiles(lloid, ctx, hs, args)
-        else:   # the plain FP32 reference path keeps the default tiles
-            lloid.lloid_ctx_set_tiles(ctx, 0, 0)
-            tiles[compute] = {"fir_variant": 0, "mix_variant": 0, "source": "defaults"}
-        steps = args.steps if compute == args.compute else args.f32_steps
-        nwin = seconds
-        cap = sum(b.n_templates for b in banks) * nwin
-        tbuf = torch.empty(cap * lloid.TRIGGER_DTYPE.itemsize, dtype=torch.uint8, pin_memory=True)
-
-        def step():
-            n = 0
-            for d, x in enumerate(xs):
-                n += lloid.lloid_filter_batch(hs, d, x, window=(1, 1), triggers_out=tbuf).n_triggers
-            return n
-        for _ in range(max(args.warmup, 1) if compute == args.compute else 1):
-            step()
-        torch.cuda.synchronize()
-        lloid.lloid_ctx_profile(ctx, True)
-        lloid.lloid_ctx_stage_times(ctx, reset=True)
-        t = time.perf_counter()
-        for _ in range(steps):
-            ntr = step()
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t) / steps
-        stages = lloid.lloid_ctx_stage_times(ctx, reset=True)
-        lloid.lloid_ctx_profile(ctx, False)
-        for h in hs:
-            lloid.lloid_bank_destroy(h)
-        samples = sum(b.n_templates for b in banks) * seconds * f0 * 2
-        fir, mix = batched_work(banks, seconds * 2)
-        out[compute] = {"value": round(samples / wall, 1), "ms_per_step": round(wall * 1e3, 2),
-                        "triggers_per_step": int(ntr),
-                        "algorithmic_tflop_per_step": round((fir + mix) / 1e12, 2),
-                        "algorithmic_tflops": round((fir + mix) / wall / 1e12, 1),
-                        "mfma_frac_of_peak": round((fir + mix) / wall / 1e12 / PEAK_TFLOPS[compute], 4),
-                        "stage_ms_last_chunk": {k: round(v[0] / max(v[1], 1), 3) for k, v in stages.items()}}
+        main_ = compute == args.compute
+        out[compute] = measure_batched(lloid, ctx, banks, xs, compute, args.steps if main_ else args.f32_steps,
+                                       args.warmup if main_ else 1, seconds, args, tiles_from_cache=main_)
         log(f"[bench] batched {compute}: {out[compute]}")
     lloid.lloid_ctx_destroy(ctx)
     main_ = out[args.compute]
@@ -252,14 +319,69 @@ def bench_batched(args):
                                    f"and lower, filters 0.5-64 s), 2 detectors x {seconds} s, one launch per stage",
                        "banks": nb, "templates": sum(b.n_templates for b in banks), "detectors": 2,
                        "seconds": seconds, "f0": f0},
-            "tiles": tiles, "paths": out}
+            "paths": out}
+
+
+def measure_serving(lloid, ctx, banks, hs, compute, rate, n_str, xs, use_graph=False, warm=4):
+    """Push n_str 1 s strides of 2 detectors (after `warm` untimed ones) at
+    `rate` x real time (0: as fast as the stream takes them) into a stream
+    holding every bank of hs; latency of each stride from its push to its
+    triggers being visible to the host (the library's clock), throughput over
+    the wall time of the timed strides."""
+    import numpy as np
+    f0 = banks[0].f0
+    total = xs[0].shape[0] // f0
+    s = lloid.lloid_stream_create(ctx, f0, compute, n_detectors=2, min_rate_hz=128, window=(1, 1),
+                                  max_filter_s=66.0, max_windows_per_tick=2, use_graph=use_graph)
+    try:
+        for h in hs:
+            lloid.lloid_stream_admit(s, h)
+        n_trig = 0
+        t_start = None
+        for i in range(n_str + warm):
+            if i == warm:
+                lloid.lloid_stream_poll(s, wait_ms=-1)      # the warm-up strides are done
+                lloid.lloid_stream_stats_reset(s)
+                t_start = time.perf_counter()
+            if t_start is not None and rate > 0:
+                due = t_start + (i - warm) / rate
+                while time.perf_counter() < due:
+                    pass
+            j = i % total   # strain cycles through the generated seconds
+            for d in range(2):
+                lloid.lloid_stream_push(s, d, i * f0, xs[d][j * f0:(j + 1) * f0])
+            if i >= warm:
+                n_trig += lloid.lloid_stream_poll(s).shape[0]
+        n_trig += lloid.lloid_stream_poll(s, wait_ms=-1).shape[0]
+        wall = time.perf_counter() - t_start
+        st = lloid.lloid_stream_stats_get(s)
+    finally:
+        lloid.lloid_stream_destroy(s)
+    samples = sum(b.n_templates for b in banks) * n_str * f0 * 2
+    fir, mix = batched_work(banks, n_str * 2)
+    return {"value": round(samples / wall, 1), "wall_s": round(wall, 3), "strides": n_str,
+            "rate_x_real_time": rate if rate > 0 else "saturation",
+            "p50_stride_latency_ms": round(st.latency_p50_ms, 3),
+            "p99_stride_latency_ms": round(st.latency_p99_ms, 3),
+            "max_stride_latency_ms": round(st.latency_max_ms, 3),
+            "ms_per_stride": round(wall / n_str * 1e3, 3),
+            "mfma_frac_of_peak": round((fir + mix) / wall / 1e12 / PEAK_TFLOPS[compute], 4),
+            "kept_up": bool(rate <= 0 or wall <= n_str / rate * 1.05), "triggers": int(n_trig),
+            "hip_graph": bool(use_graph), "graph_captures": int(st.graph_captures),
+            "graph_replays": int(st.graph_replays)}
+
+
+def serving_inputs(seconds: int = 64):
+    import numpy as np
+    from workloads import configs
+    return [np.random.default_rng(configs.seed(4, d)).standard_normal(seconds * 2048).astype(np.float32)
+            for d in range(2)]
 
 
 def bench_serving(args):
     """128 banks drawn as in the batched workload, 2 detectors, strain pushed in
     1 s strides at `rate` x real time; p50/p99 latency from the push that
     completes a stride to its triggers on the host, and template-samples/s."""
-    import numpy as np
     import torch
     from workloads import configs
     from paper_2410_16416_amd import lloid
@@ -268,66 +390,31 @@ def bench_serving(args):
     banks = configs.batched_c3_banks(nb)
     f0 = 2048
     n_strides = args.strides
-    warm = 4
-    total = (n_strides + warm) * f0
-    xs = [np.random.default_rng(configs.seed(4, d)).standard_normal(total).astype(np.float32) for d in range(2)]
+    xs = serving_inputs()
     torch.cuda.init()
     ctx = lloid.lloid_ctx_create(0)
     out = {}
-    def serve(hs, compute, rate, n_str, use_graph=False):
-        """Push n_str strides (after `warm` untimed ones) at `rate` x real time."""
-        s = lloid.lloid_stream_create(ctx, f0, compute, n_detectors=2, min_rate_hz=128, window=(1, 1),
-                                      max_filter_s=66.0, max_windows_per_tick=2, use_graph=use_graph)
-        for h in hs:
-            lloid.lloid_stream_admit(s, h)
-        n_trig = 0
-        lat = []
-        t_start = None
-        for i in range(n_str + warm):
-            if i == warm:
-                t_start = time.perf_counter()
-            if t_start is not None:
-                due = t_start + (i - warm) / rate
-                while time.perf_counter() < due:
-                    pass
-            j = i % (total // f0)   # strain cycles through the generated seconds
-            for d in range(2):
-                lloid.lloid_stream_push(s, d, i * f0, xs[d][j * f0:(j + 1) * f0])
-            n_trig += lloid.lloid_stream_poll(s).shape[0]
-            if i >= warm:
-                lat.append((time.perf_counter() - (t_start + (i - warm) / rate)) * 1e3)
-        wall = time.perf_counter() - t_start
-        st = lloid.lloid_stream_stats_get(s)
-        lloid.lloid_stream_destroy(s)
-        samples = sum(b.n_templates for b in banks) * n_str * f0 * 2
-        lat = np.array(lat)
-        return {"value": round(samples / wall, 1), "wall_s": round(wall, 3), "strides": n_str,
-                "rate_x_real_time": rate,
-                "p50_stride_latency_ms": round(float(np.percentile(lat, 50)), 3),
-                "p99_stride_latency_ms": round(float(np.percentile(lat, 99)), 3),
-                "library_p50_ms": round(st.latency_p50_ms, 3), "library_p99_ms": round(st.latency_p99_ms, 3),
-                "kept_up": bool(wall <= n_str / rate * 1.05), "triggers": int(n_trig),
-                "hip_graph": bool(use_graph), "graph_captures": int(st.graph_captures),
-                "graph_replays": int(st.graph_replays)}
-
     sweep = []
     for compute in [args.compute] + (["f32"] if args.f32_steps and args.compute != "f32" else []):
         hs = [lloid.bank_from_svd(ctx, b, compute) for b in banks]
-        out[compute] = serve(hs, compute, args.rate, n_strides)
+        out[compute] = measure_serving(lloid, ctx, banks, hs, compute, args.rate, n_strides, xs)
         log(f"[bench] serving {compute}: {out[compute]}")
         if compute == args.compute:
-            out[compute + "_hip_graph"] = serve(hs, compute, args.rate, n_strides, use_graph=True)
+            out[compute + "_hip_graph"] = measure_serving(lloid, ctx, banks, hs, compute, args.rate, n_strides, xs,
+                                                          use_graph=True)
             log(f"[bench] serving {compute} (HIP graph ticks): {out[compute + '_hip_graph']}")
+            out[compute + "_saturation"] = measure_serving(lloid, ctx, banks, hs, compute, 0, n_strides, xs)
+            log(f"[bench] serving {compute} at saturation: {out[compute + '_saturation']}")
         if compute == args.compute and args.rates:
             for r in [float(v) for v in args.rates.split(",") if v]:
-                sweep.append(serve(hs, compute, r, min(1000, int(60 * r))))
+                sweep.append(measure_serving(lloid, ctx, banks, hs, compute, r, min(1000, int(60 * r)), xs))
                 log(f"[bench] serving {compute} at {r:g}x: {sweep[-1]}")
         for h in hs:
             lloid.lloid_bank_destroy(h)
     lloid.lloid_ctx_destroy(ctx)
     m = out[args.compute]
     return {"metric": METRIC, "value": m["value"], "unit": "template-samples/s", "n_gpus": 1,
-            "steps": n_strides, "warmup": warm, "ms_per_step": round(m["wall_s"] / n_strides * 1e3, 3),
+            "steps": n_strides, "warmup": 4, "ms_per_step": m["ms_per_stride"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.compute,
             "data": "synthetic (seeded white Gaussian noise; uneven bank shapes with seeded random orthonormal bases)",
             "config": {"workload": f"serving_c4: {nb} banks, 2 detectors, 1 s strides at {args.rate:g}x real time",
@@ -335,6 +422,127 @@ def bench_serving(args):
                        "strides": n_strides, "rate_x_real_time": args.rate, "f0": f0},
             "p50_stride_latency_ms": m["p50_stride_latency_ms"], "p99_stride_latency_ms": m["p99_stride_latency_ms"],
             "paths": out, "rate_sweep": sweep}
+
+
+def stated_error(compute: str):
+    """The precision's measured SNR error against the FP64 oracle on the
+    1024-template bank (recorded by the parity test)."""
+    err_path = os.path.join(PROFILES, "precision_multirate_c1.json")
+    if not os.path.exists(err_path):
+        return None
+    with open(err_path) as f:
+        return json.load(f).get(compute)
+
+
+def bench_snr_series(lloid, ctx, wl, xs, args):
+    """SNR-series output mode: the complex SNR of every template at every
+    sample written to a device buffer [F][n][2] FP32 beside the triggers (8 B
+    per template-sample; HBM-bound)."""
+    import torch
+    F, n = wl.bank.n_templates, wl.n_samples
+    log(f"[bench] snr-series mode: steps {args.snr_steps} ({F * n * 8 / 1e9:.1f} GB per detector)")
+    dz = torch.empty((F, n, 2), dtype=torch.float32, device="cuda")
+    bank = lloid.bank_from_svd(ctx, wl.bank, args.compute)
+    try:
+        tiles = pick_tiles(lloid, ctx, [bank], args)
+
+        def step():
+            for d, x in enumerate(xs):
+                lloid.lloid_filter(bank, d, x, window=(1, 1), threshold=4.0, snr_out=dz)
+        step()
+        torch.cuda.synchronize()
+        lloid.lloid_ctx_profile(ctx, True)
+        lloid.lloid_ctx_stage_times(ctx, reset=True)
+        t0 = time.perf_counter()
+        for _ in range(args.snr_steps):
+            step()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.snr_steps
+        st = lloid.lloid_ctx_stage_times(ctx, reset=True)
+        lloid.lloid_ctx_profile(ctx, False)
+    finally:
+        lloid.lloid_bank_destroy(bank)
+        del dz
+        torch.cuda.empty_cache()
+    ms_mix = st["mix"][0] / max(st["mix"][1], 1)
+    series_bytes = F * n * 8
+    return {"value": round(F * n * len(xs) / wall, 1), "ms_per_step": round(wall * 1e3, 3),
+            "series_bytes_per_detector": series_bytes,
+            "mix_ms_per_launch": round(ms_mix, 3),
+            "mix_write_gbs": round(series_bytes / (ms_mix / 1e3) / 1e9, 1),
+            "hbm_peak_gbs": PEAK_HBM_GBS, "floor_ms_per_step": round(series_bytes * len(xs) / PEAK_HBM_GBS / 1e6, 3),
+            "tiles": tiles}
+
+
+def bench_c0_latency(lloid, ctx, args):
+    """Latency of one call on the single-rate 64-template workload (8 s at
+    1024 Hz, one detector, 0.1 s windows): host strain in, triggers out."""
+    import numpy as np
+    from workloads import configs
+    wl = configs.plain_c0()
+    x = wl.strains[0]
+    bank = lloid.bank_from_svd(ctx, wl.bank, args.compute)
+    try:
+        for _ in range(10):
+            lloid.lloid_filter(bank, 0, x, window=(1, 10))
+        lat = []
+        for _ in range(args.c0_calls):
+            t0 = time.perf_counter()
+            r = lloid.lloid_filter(bank, 0, x, window=(1, 10))
+            lat.append((time.perf_counter() - t0) * 1e3)
+    finally:
+        lloid.lloid_bank_destroy(bank)
+    lat = np.array(lat)
+    return {"workload": "plain_c0: 64 chirp templates at 1024 Hz, 32 basis filters, 8 s, 0.1 s windows",
+            "calls": args.c0_calls, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3), "triggers": int(r.n_triggers),
+            "template_samples_per_s_at_p50": round(64 * x.shape[0] / (np.percentile(lat, 50) / 1e3), 1),
+            "timing": "host wall time of lloid_filter (host FP64 strain in, triggers in host memory out)"}
+
+
+def bench_c3_c4(lloid, ctx, args):
+    """The batched form (64 uneven banks, 2 detectors x 512 s) and the serving
+    form (128 banks streamed in 1 s strides at 16x real time and at
+    saturation), the operand type of the headline."""
+    import numpy as np
+    import torch
+    from workloads import configs
+    n_banks = 128 if args.c4_strides else 64
+    log(f"[bench] generating {n_banks} uneven banks")
+    t0 = time.perf_counter()
+    banks = configs.batched_c3_banks(n_banks)
+    log(f"[bench] banks ready in {time.perf_counter() - t0:.1f} s")
+    out = {}
+    if args.c3_steps:
+        seconds = 512
+        c3 = banks[:64]
+        xs = [torch.from_numpy(np.random.default_rng(configs.seed(3, d)).standard_normal(seconds * 2048)).to("cuda")
+              for d in range(2)]
+        saved = args.block_seconds
+        args.block_seconds = seconds
+        r = measure_batched(lloid, ctx, c3, xs, args.compute, args.c3_steps, 1, seconds, args)
+        args.block_seconds = saved
+        del xs
+        out["batched_c3"] = dict(workload="batched_c3: 64 uneven SVD banks (F U[200,2000], 1-4 slices, filters "
+                                          "0.5-64 s), 2 detectors x 512 s, one launch per stage",
+                                 templates=sum(b.n_templates for b in c3), **r)
+        log(f"[bench] batched_c3: {r['ms_per_step']} ms/step, MFMA fraction {r['mfma_frac_of_peak']}")
+    if args.c4_strides:
+        xs = serving_inputs()
+        hs = [lloid.bank_from_svd(ctx, b, args.compute) for b in banks]
+        lloid.lloid_ctx_set_tiles(ctx, 0, 0)   # serving ticks keep the default tiles
+        try:
+            a = measure_serving(lloid, ctx, banks, hs, args.compute, 16.0, args.c4_strides, xs)
+            log(f"[bench] serving_c4 16x: {a}")
+            b = measure_serving(lloid, ctx, banks, hs, args.compute, 0, args.c4_strides, xs)
+            log(f"[bench] serving_c4 saturation: {b}")
+        finally:
+            for h in hs:
+                lloid.lloid_bank_destroy(h)
+        out["serving_c4"] = {"workload": "serving_c4: 128 uneven banks, 2 detectors, 1 s strides, max 2 windows "
+                                         "per tick, default tiles",
+                             "templates": sum(b.n_templates for b in banks), "at_16x": a, "at_saturation": b}
+    return out
 
 
 def main():
@@ -345,7 +553,20 @@ def main():
     ap.add_argument("--compute", default="f16", choices=["f16", "bf16", "f32"])
     ap.add_argument("--seconds", type=int, default=1024, help="seconds of strain per detector")
     ap.add_argument("--f32-steps", type=int, default=3, help="timed steps of the plain FP32 path (0: skip)")
-    ap.add_argument("--cpu-sample-s", type=float, default=24.0, help="oracle sample length (0: skip)")
+    ap.add_argument("--cpu-sample-s", type=float, default=60.0,
+                    help="seconds of outputs per oracle process (0: skip the CPU baseline)")
+    ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="single-threaded oracle processes, one per host core (at most 16)")
+    ap.add_argument("--bf16-steps", type=int, default=3, help="timed steps of the BF16 path (0: skip)")
+    ap.add_argument("--snr-steps", type=int, default=2,
+                    help="timed steps of the SNR-series output mode (complex SNR of every template and "
+                         "sample written to HBM; 0: skip)")
+    ap.add_argument("--c0-calls", type=int, default=100, help="timed calls of the 64-template single-rate "
+                                                              "block (latency; 0: skip)")
+    ap.add_argument("--c3-steps", type=int, default=2, help="default run: timed steps of the 64 uneven banks "
+                                                            "(2 detectors x 512 s; 0: skip)")
+    ap.add_argument("--c4-strides", type=int, default=200, help="default run: timed 1 s strides of the 128-bank "
+                                                                "serving stream at 16x and at saturation (0: skip)")
     ap.add_argument("--workload", default="multirate_c1", choices=["multirate_c1", "batched_c3", "serving_c4"],
                     help="multirate_c1 (headline), batched_c3 (64 uneven banks, one launch per stage), "
                          "serving_c4 (128 banks streamed in 1 s strides)")
@@ -388,6 +609,13 @@ def main():
     wl = configs.multirate_c1(seconds=args.seconds)
     args.block_seconds = args.seconds
     log(f"[bench] workload ready in {time.perf_counter() - t0:.1f} s: {wl.bank.describe()}")
+    cpu = cpu1 = None
+    if args.cpu_sample_s > 0:
+        # before the GPU is initialised: spawned single-threaded oracle processes
+        log(f"[bench] cpu baseline: {args.cpu_workers} oracle processes x {args.cpu_sample_s:g} s")
+        cpu = cpu_baseline(wl, args.cpu_sample_s, args.cpu_workers)
+        cpu1 = cpu_baseline_1thread(wl, 4.0)
+        log(f"[bench] cpu baseline: {cpu['value']:.4g} template-samples/s on {cpu['cores']} processes")
     torch.cuda.init()
     ctx = lloid.lloid_ctx_create(0)
     xs = [torch.from_numpy(x).to("cuda") for x in wl.strains]
@@ -431,10 +659,7 @@ def main():
         "roofline_stages": roofs,
         "p99_stride_latency_ms": None,
     }
-    err_path = os.path.join(PROFILES, "precision_multirate_c1.json")
-    if os.path.exists(err_path):
-        with open(err_path) as f:
-            out["stated_snr_error"] = json.load(f).get(args.compute)
+    out["stated_snr_error"] = stated_error(args.compute)
 
     if args.f32_steps and args.compute != "f32":
         log(f"[bench] plain f32 path: steps {args.f32_steps}")
@@ -501,12 +726,28 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = nbytes
         del a, b2
-    if args.cpu_sample_s > 0:
-        log(f"[bench] cpu baseline: oracle on {args.cpu_sample_s:g} s")
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_s)
-        one = cpu_baseline_1thread(wl, min(args.cpu_sample_s, 4.0))
-        if one:
-            out["cpu_baseline_1_thread"] = one
+    if args.bf16_steps and args.compute != "bf16":
+        log(f"[bench] bf16 path: steps {args.bf16_steps}")
+        wb, nb16, stb, tb = run_path(lloid, ctx, wl, xs, "bf16", args.bf16_steps, 1, tbufs, args)
+        ms, calls = stb["mix"]
+        out["bf16_path"] = {"value": round(samples_per_step / (wb / args.bf16_steps), 1),
+                            "ms_per_step": round(wb / args.bf16_steps * 1e3, 3), "triggers_per_step": int(nb16),
+                            "stage_ms_per_step": {k: round(v[0] / args.bf16_steps, 3) for k, v in stb.items()},
+                            "roofline_mix": roofline_entry("mfma", work["mix"][1], ms / max(calls, 1), "bf16"),
+                            "stated_snr_error": stated_error("bf16"), "tiles": tb}
+    if args.snr_steps:
+        out["snr_series_mode"] = bench_snr_series(lloid, ctx, wl, xs, args)
+    if args.c0_calls:
+        out["c0_latency"] = bench_c0_latency(lloid, ctx, args)
+    if args.c3_steps or args.c4_strides:
+        out.update(bench_c3_c4(lloid, ctx, args))
+        if "serving_c4" in out:
+            out["p99_stride_latency_ms"] = out["serving_c4"]["at_16x"]["p99_stride_latency_ms"]
+            out["p50_stride_latency_ms"] = out["serving_c4"]["at_16x"]["p50_stride_latency_ms"]
+    if cpu:
+        out["cpu_baseline"] = cpu
+    if cpu1:
+        out["cpu_baseline_1_thread"] = cpu1
     lloid.lloid_ctx_destroy(ctx)
     print(json.dumps(out), flush=True)
 

@@ -244,18 +244,27 @@ lloid_status lloid_filter_batch(lloid_bank *const *banks, int32_t n_banks, int32
                                 lloid_peaks *peaks);
 
 /* ---- streaming (serving) ----
- * Strain arrives in strides per detector; the down-sampled strain of every
- * rate stays on the device as the filters' history.  Every time all
- * detectors hold enough strain to complete trigger windows, one tick filters
- * those windows for every admitted bank and detector, one launch per stage
- * for all of them, and queues the triggers for lloid_stream_poll.  Banks
- * ("requests") are admitted into slots while their arrays plus their per-tick
- * scratch fit the device-memory budget; later ones wait in arrival order and
- * are admitted when slots are removed.  A bank reports the windows from its
- * admission on; since the history is complete, every result equals the one
- * lloid_filter gives for the whole stream (bit for bit).  After
- * lloid_stream_flush (zero strain past the end, as lloid_filter assumes) the
- * stream emits its remaining windows and accepts no more strain. */
+ * Sec. II.B (online, low-latency mode): strain arrives in strides per
+ * detector; the down-sampled strain of every rate stays on the device as the
+ * filters' history.  Every time all detectors hold enough strain to complete
+ * trigger windows, one tick filters those windows for every admitted bank and
+ * detector, one launch per stage for all of them, and queues the triggers for
+ * lloid_stream_poll.  Banks ("requests") are admitted into slots while their
+ * arrays plus their per-tick scratch fit the device-memory budget; later ones
+ * wait in arrival order and are admitted when slots are removed.  A bank
+ * reports the windows from its admission on; since the history is complete,
+ * every result equals the one lloid_filter gives for the whole stream (bit for
+ * bit).  After lloid_stream_flush (zero strain past the end, as lloid_filter
+ * assumes) the stream emits its remaining windows and accepts no more strain.
+ *
+ * The work runs asynchronously: lloid_stream_push checks a stride and copies
+ * it into a staging ring, then returns; a library thread uploads, converts
+ * and decimates the strides in order on a second HIP stream and enqueues the
+ * ticks on the context's stream without waiting for them, and another thread
+ * queues each tick's triggers when its device work completes.  The upload of
+ * the next stride and the host work of the next tick overlap the device work
+ * of the current one.  Calls on one stream must not overlap (one producer
+ * thread); lloid_stream_poll may wait for the work pushed before it. */
 typedef struct {
   int32_t n_detectors;          /* 1..16 */
   int32_t min_rate_hz;          /* lowest slice rate an admitted bank may use */
@@ -269,6 +278,10 @@ typedef struct {
   int64_t hbm_budget;           /* device bytes for admitted banks (arrays + per-tick scratch);
                                    0 means no limit */
   lloid_trigger_opts trig;      /* window length, threshold, strain scale */
+  int32_t queue_strides;        /* staging entries of the stride ring (each holds up to
+                                   max(f0, max_windows_per_tick window lengths + 1) samples):
+                                   push waits while all hold strides not yet uploaded; 0 means 64 */
+  int32_t reserved;
 } lloid_stream_opts;
 
 typedef struct {
@@ -276,7 +289,9 @@ typedef struct {
   int64_t windows;              /* windows emitted (per detector) */
   int64_t triggers;             /* triggers queued so far */
   int64_t next_window;          /* first window not yet emitted */
-  double latency_p50_ms;        /* push of the stride that completed a tick -> its triggers queued */
+  double latency_p50_ms;        /* push of the stride that completed a tick -> the tick's device
+                                   work done and its triggers queued for poll (over the ticks since
+                                   creation or the last lloid_stream_stats_reset) */
   double latency_p99_ms;
   double latency_max_ms;
   int32_t active_slots;
@@ -284,29 +299,48 @@ typedef struct {
   int64_t bytes_in_use;         /* budget taken by active slots */
   int64_t graph_captures;       /* with use_graph: ticks that captured a new graph */
   int64_t graph_replays;        /* with use_graph: ticks that replayed the previous one */
+  int64_t queued_strides;       /* pushed pieces not yet taken by the library thread */
+  int64_t ticks_in_flight;      /* ticks enqueued on the device and not yet completed */
 } lloid_stream_stats;
 
 lloid_status lloid_stream_create(lloid_ctx *ctx, int32_t full_rate_hz, lloid_dtype compute,
                                  const lloid_stream_opts *opts, lloid_stream **out);
 /* Admit a bank (same context, full rate and compute type as the stream).  The
- * bank must outlive its slot.  *slot receives the slot id, which trigger
+ * bank must outlive its slot.  It joins at the stream's position after every
+ * stride pushed so far (the call waits until the library thread has taken
+ * them) and reports from the next window not yet enqueued
+ * (lloid_stream_stats.next_window).  *slot receives the slot id, which trigger
  * records carry in their `bank` field.  EAGAIN: the bank is queued and becomes
  * active when enough budget frees up; ENOMEM: it can never fit the budget;
  * EINVAL: its filters are longer than the stream's history. */
 lloid_status lloid_stream_admit(lloid_stream *s, lloid_bank *bank, int32_t *slot);
-/* Remove an active or queued slot; queued banks are admitted as budget frees up. */
+/* Remove an active or queued slot at the stream's position after every stride
+ * pushed so far; queued banks are admitted as budget frees up.  Returns when
+ * no tick in flight reads the bank any more (it may then be destroyed). */
 lloid_status lloid_stream_remove(lloid_stream *s, int32_t slot);
-/* Append n samples (host or device, F64 or F32) of detector `detector`
+/* Queue n samples (host or device, F64 or F32) of detector `detector`
  * starting at full-rate sample t0, which must continue the previous stride
- * (EORDER otherwise); runs every tick the new strain completes.  EDATA on a
- * non-finite sample. */
+ * (EORDER otherwise).  Non-blocking: the call checks every sample, copies the
+ * stride into the staging ring and returns; it waits only while every ring
+ * entry holds a stride not yet uploaded.  EDATA if a sample (scaled, in FP32)
+ * is not finite: nothing of the stride is queued and the detector still
+ * expects t0.  Errors of the asynchronous work are returned by the next call. */
 lloid_status lloid_stream_push(lloid_stream *s, int32_t detector, int64_t t0, const void *data,
                                lloid_dtype dtype, int64_t n);
 /* Move up to cap queued triggers (tick order; within a tick by slot,
- * detector, template, window) into out (host). */
-lloid_status lloid_stream_poll(lloid_stream *s, lloid_trigger *out, int64_t cap, int64_t *n_out);
+ * detector, template, window) into out (host).  wait_ms = 0: return at once
+ * with what is queued; > 0: first wait up to wait_ms milliseconds until every
+ * stride pushed before the call is filtered; < 0: wait for that without a
+ * limit. */
+lloid_status lloid_stream_poll(lloid_stream *s, lloid_trigger *out, int64_t cap, int64_t *n_out, int32_t wait_ms);
+/* Zero strain past the end of every detector (which must hold the same
+ * number of samples); returns when every window is filtered and queued. */
 lloid_status lloid_stream_flush(lloid_stream *s);
 lloid_status lloid_stream_stats_get(const lloid_stream *s, lloid_stream_stats *out);
+/* Clear the latency record and the tick, window, trigger and graph counts. */
+lloid_status lloid_stream_stats_reset(lloid_stream *s);
+/* Stops the library threads (strides not yet taken are dropped), waits for
+ * the ticks in flight and frees the stream. */
 lloid_status lloid_stream_destroy(lloid_stream *s);
 
 /* ---- conditioning before the filter ----

@@ -75,7 +75,7 @@ class lloid_stream_opts(ctypes.Structure):
     _fields_ = [("n_detectors", ctypes.c_int32), ("min_rate_hz", ctypes.c_int32),
                 ("max_windows_per_tick", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("max_filter_s", ctypes.c_double), ("hbm_budget", ctypes.c_int64),
-                ("trig", lloid_trigger_opts)]
+                ("trig", lloid_trigger_opts), ("queue_strides", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class lloid_stream_stats(ctypes.Structure):
@@ -84,7 +84,8 @@ class lloid_stream_stats(ctypes.Structure):
                 ("latency_p99_ms", ctypes.c_double), ("latency_max_ms", ctypes.c_double),
                 ("active_slots", ctypes.c_int32), ("queued_banks", ctypes.c_int32),
                 ("bytes_in_use", ctypes.c_int64), ("graph_captures", ctypes.c_int64),
-                ("graph_replays", ctypes.c_int64)]
+                ("graph_replays", ctypes.c_int64), ("queued_strides", ctypes.c_int64),
+                ("ticks_in_flight", ctypes.c_int64)]
 
 
 TRIGGER_DTYPE = np.dtype([("bank", np.int32), ("detector", np.int32), ("template_id", np.int32),
@@ -134,7 +135,8 @@ def _load():
         "lloid_stream_admit": ([vp, vp, ctypes.POINTER(i32)], ctypes.c_int),
         "lloid_stream_remove": ([vp, i32], ctypes.c_int),
         "lloid_stream_push": ([vp, i32, i64, vp, ctypes.c_int, i64], ctypes.c_int),
-        "lloid_stream_poll": ([vp, vp, i64, ctypes.POINTER(i64)], ctypes.c_int),
+        "lloid_stream_poll": ([vp, vp, i64, ctypes.POINTER(i64), i32], ctypes.c_int),
+        "lloid_stream_stats_reset": ([vp], ctypes.c_int),
         "lloid_stream_flush": ([vp], ctypes.c_int),
         "lloid_stream_stats_get": ([vp, ctypes.POINTER(lloid_stream_stats)], ctypes.c_int),
         "lloid_stream_destroy": ([vp], ctypes.c_int),
@@ -169,7 +171,8 @@ def exported_symbols():
             "lloid_bank_create", "lloid_bank_sigma2", "lloid_bank_query", "lloid_bank_destroy",
             "lloid_filter", "lloid_filter_batch", "lloid_ctx_set_chunk_bytes",
             "lloid_stream_create", "lloid_stream_admit", "lloid_stream_remove", "lloid_stream_push",
-            "lloid_stream_poll", "lloid_stream_flush", "lloid_stream_stats_get", "lloid_stream_destroy",
+            "lloid_stream_poll", "lloid_stream_flush", "lloid_stream_stats_get", "lloid_stream_stats_reset",
+            "lloid_stream_destroy",
             "lloid_coincide", "lloid_condition", "lloid_ctx_set_tiles", "lloid_ctx_get_tiles", "lloid_autotune"]
 
 
@@ -459,12 +462,12 @@ def bank_from_svd(ctx, svd_bank, compute: str = "f16"):
 def lloid_stream_create(ctx, full_rate_hz: int, compute: str = "f16", n_detectors: int = 1,
                         min_rate_hz: int | None = None, window=(1, 1), threshold: float = 4.0,
                         strain_scale: float = 0.0, hbm_budget: int = 0, max_filter_s: float = 0.0,
-                        max_windows_per_tick: int = 0, use_graph: bool = False):
+                        max_windows_per_tick: int = 0, use_graph: bool = False, queue_strides: int = 0):
     opts = lloid_stream_opts(int(n_detectors), int(min_rate_hz or max(1, full_rate_hz // 16)),
                              int(max_windows_per_tick), 1 if use_graph else 0, float(max_filter_s),
                              int(hbm_budget),
                              lloid_trigger_opts(int(window[0]), int(window[1]), float(threshold),
-                                                float(strain_scale)))
+                                                float(strain_scale)), int(queue_strides), 0)
     out = ctypes.c_void_p()
     _check(_lib.lloid_stream_create(ctx, int(full_rate_hz), DTYPES[compute], ctypes.byref(opts),
                                     ctypes.byref(out)))
@@ -490,10 +493,13 @@ def lloid_stream_push(stream, detector: int, t0: int, data):
     _check(_lib.lloid_stream_push(stream, int(detector), int(t0), ctypes.c_void_p(_ptr(data)), dt, n))
 
 
-def lloid_stream_poll(stream, cap: int = 1 << 20) -> np.ndarray:
+def lloid_stream_poll(stream, cap: int = 1 << 20, wait_ms: int = 0) -> np.ndarray:
+    """Queued triggers; wait_ms > 0 (or < 0: no limit) first waits for the
+    strides pushed so far to be filtered."""
     out = np.empty(max(cap, 1), dtype=TRIGGER_DTYPE)
     n = ctypes.c_int64()
-    _check(_lib.lloid_stream_poll(stream, ctypes.c_void_p(out.ctypes.data), int(cap), ctypes.byref(n)))
+    _check(_lib.lloid_stream_poll(stream, ctypes.c_void_p(out.ctypes.data), int(cap), ctypes.byref(n),
+                                  int(wait_ms)))
     return out[: n.value]
 
 
@@ -505,6 +511,10 @@ def lloid_stream_stats_get(stream) -> lloid_stream_stats:
     st = lloid_stream_stats()
     _check(_lib.lloid_stream_stats_get(stream, ctypes.byref(st)))
     return st
+
+
+def lloid_stream_stats_reset(stream):
+    _check(_lib.lloid_stream_stats_reset(stream))
 
 
 def lloid_stream_destroy(stream):

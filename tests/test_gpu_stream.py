@@ -126,6 +126,8 @@ def test_continuous_batching_admission_and_removal(use_graph):
                 assert not act_c                          # over budget: queued
                 assert lloid.lloid_stream_stats_get(s).queued_banks == 1
             if k == 12:
+                # the strides pushed so far filtered: next_window is where the removal takes effect
+                got.append(lloid.lloid_stream_poll(s, wait_ms=-1))
                 removed[a] = lloid.lloid_stream_stats_get(s).next_window
                 lloid.lloid_stream_remove(s, a)
             for d in range(2):
@@ -170,6 +172,10 @@ def test_stream_errors():
         with pytest.raises(lloid.LloidError) as ei:
             lloid.lloid_stream_push(s, 0, 1024, bad)
         assert ei.value.status == lloid.LLOID_EDATA
+        lloid.lloid_stream_push(s, 0, 1024, x)            # the rejected stride left the detector at 1024
+        lloid.lloid_stream_poll(s, wait_ms=-1)
+        st = lloid.lloid_stream_stats_get(s)
+        assert st.queued_strides == 0 and st.ticks_in_flight == 0
     finally:
         lloid.lloid_stream_destroy(s)
     # a stream whose history is shorter than the bank's filters refuses it
@@ -192,3 +198,95 @@ def test_stream_errors():
     finally:
         lloid.lloid_stream_destroy(s)
         lloid.lloid_bank_destroy(h2)
+
+
+def test_stream_recovers_after_rejected_strides():
+    """A stride with a non-finite sample (host or device) is rejected by its own
+    push with EDATA and nothing of it is queued; the detector still expects
+    the same t0, and the stream's triggers over the clean strides pushed in
+    its place equal the offline result."""
+    import torch
+    from paper_2410_16416_amd import lloid
+    wl = configs.mini_multirate(seconds=10, detectors=2, n_injections=2)
+    h = lloid.bank_from_svd(ctx(), wl.bank, "f16")
+    s = lloid.lloid_stream_create(ctx(), 1024, "f16", n_detectors=2, min_rate_hz=64, window=(1, 4),
+                                  max_filter_s=8.0)
+    try:
+        slot, _ = lloid.lloid_stream_admit(s, h)
+        n = wl.strains[0].shape[0]
+        got = []
+        for k, pos in enumerate(range(0, n, 1024)):
+            for d in range(2):
+                piece = wl.strains[d][pos:pos + 1024]
+                if k in (3, 6) and d == 1:
+                    bad = piece.copy()
+                    bad[100] = np.nan if k == 3 else -np.inf
+                    if k == 6:
+                        bad = torch.from_numpy(bad).to("cuda")     # a device stride
+                    with pytest.raises(lloid.LloidError) as ei:
+                        lloid.lloid_stream_push(s, d, pos, bad)
+                    assert ei.value.status == lloid.LLOID_EDATA
+                    with pytest.raises(lloid.LloidError) as ei:
+                        lloid.lloid_stream_push(s, d, pos + 1024, piece)   # still expects pos
+                    assert ei.value.status == lloid.LLOID_EORDER
+                lloid.lloid_stream_push(s, d, pos, piece)
+            got.append(lloid.lloid_stream_poll(s))
+        lloid.lloid_stream_flush(s)
+        got.append(lloid.lloid_stream_poll(s))
+        mine = canon(np.concatenate(got))
+        want = offline(lloid, h, wl.strains, (1, 4), slot)
+        log(f"[recover] {len(mine)} triggers")
+        assert len(mine) > 0 and np.array_equal(mine, want)
+    finally:
+        lloid.lloid_stream_destroy(s)
+        lloid.lloid_bank_destroy(h)
+
+
+def test_pushes_overlap_ticks_and_equal_offline():
+    """Strides pushed back to back (push returns once the stride is copied)
+    while earlier ticks are still on the device: the library thread uploads
+    and converts stride N + 1 and builds its tick while tick N runs.  Every
+    trigger equals the offline result, alone and in a mix of banks; the
+    stream is seen holding queued strides or ticks in flight right after
+    pushes."""
+    from paper_2410_16416_amd import lloid
+    f0 = 2048
+    banks = [configs.multirate_c1_bank(), configs.batched_c3_bank(1), configs.batched_c3_bank(2)]
+    rng = np.random.default_rng(33)
+    n = 80 * f0
+    strains = [rng.standard_normal(n), rng.standard_normal(n)]
+    hs = [lloid.bank_from_svd(ctx(), b, "f16") for b in banks]
+    try:
+        results = {}
+        for mix in ([0], [0, 1, 2]):
+            s = lloid.lloid_stream_create(ctx(), f0, "f16", n_detectors=2, min_rate_hz=128, window=(1, 1),
+                                          max_filter_s=66.0, max_windows_per_tick=2)
+            try:
+                slots = [lloid.lloid_stream_admit(s, hs[i])[0] for i in mix]
+                busy = 0
+                got = []
+                for pos in range(0, n, f0):
+                    for d in range(2):
+                        lloid.lloid_stream_push(s, d, pos, strains[d][pos:pos + f0])
+                    st = lloid.lloid_stream_stats_get(s)
+                    busy += (st.queued_strides + st.ticks_in_flight) > 0
+                    got.append(lloid.lloid_stream_poll(s))
+                lloid.lloid_stream_flush(s)
+                got.append(lloid.lloid_stream_poll(s))
+                got = np.concatenate(got)
+                log(f"[overlap] banks {mix}: {len(got)} triggers, work pending after {busy} of {n // f0} pushes")
+                assert busy > 0
+                for slot, i in zip(slots, mix):
+                    mine = canon(got[got["bank"] == slot])
+                    mine["bank"] = 0
+                    results[(tuple(mix), i)] = mine
+            finally:
+                lloid.lloid_stream_destroy(s)
+        for i in range(len(banks)):
+            want = offline(lloid, hs[i], strains, (1, 1), 0)
+            for mix in ([0], [0, 1, 2]):
+                if i in mix:
+                    assert len(want) > 0 and np.array_equal(results[(tuple(mix), i)], want), (mix, i)
+    finally:
+        for h in hs:
+            lloid.lloid_bank_destroy(h)
