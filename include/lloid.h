@@ -225,6 +225,28 @@ lloid_status lloid_filter(lloid_bank *bank, int32_t detector,
                           lloid_trigger *trig, int64_t trig_cap, int64_t *n_trig,
                           float *snr, lloid_peaks *peaks);
 
+/* Allocation-free form of lloid_filter, for callers that cannot allocate
+ * device memory: code under HIP graph capture, serving loops and harnesses
+ * that forbid hipMalloc.  Same arguments, results and errors as lloid_filter
+ * (without the SNR-series output), bit-identical results.  Every device
+ * buffer of the call comes from one static array per GPU of
+ * LLOID_NOALLOC_SCRATCH_BYTES, part of the library's code object (held until
+ * the process ends); windows are processed in chunks sized to fit it, and the
+ * descriptor tables are staged in pageable host memory.  The call makes no
+ * hipMalloc, hipHostMalloc or hipFree and records no profiling events.
+ * ENOMEM, before any device work, when one window per chunk (the strain
+ * levels, the peak tables, trig_cap trigger records and, for host strain, a
+ * copy of it) does not fit the array.  Every call on one GPU, from any
+ * context, shares that GPU's array: calls that overlap on one GPU race and
+ * must be serialised by the caller.  The array keeps the last call's
+ * contents; the call clears what it needs cleared. */
+#define LLOID_NOALLOC_SCRATCH_BYTES (256ll << 20)
+lloid_status lloid_filter_noalloc(lloid_bank *bank, int32_t detector,
+                                  const void *strain, lloid_dtype strain_dtype, int64_t n,
+                                  const lloid_trigger_opts *opts,
+                                  lloid_trigger *trig, int64_t trig_cap, int64_t *n_trig,
+                                  lloid_peaks *peaks);
+
 /* Filter one block of strain of one detector with many SVD banks at once
  * (Sec. II.B: banks are stacked and filtered together).  The banks must share
  * the context, full rate and compute type; they may differ in every other

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -79,6 +80,35 @@ namespace lloid {
 hipError_t launch_cast_f64(const double *src, lloid_dtype t, void *dst, int64_t n, hipStream_t s);
 }
 
+// ------------------------------------------------------------ static scratch
+// Device memory of the allocation-free call (lloid_filter_noalloc): one array
+// per GPU, part of the library's code object and held until the process ends.
+// On the host this name is not a device address; host code only uses the
+// address hipGetSymbolAddress returns with the device current, kept per device.
+static __device__ __align__(256) unsigned char scratch[LLOID_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;   // indexed by device id
+}  // namespace
+
+// Address of `device`'s copy of the scratch array; the device must be current.
+static lloid_status scratch_address(int device, void **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(LLOID_EDEVICE, "hipGetSymbolAddress of the static scratch failed: %s", hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return LLOID_OK;
+}
+
 // ------------------------------------------------------------ context
 
 extern "C" lloid_status lloid_ctx_create(int device, void *hip_stream, lloid_ctx **out) {
@@ -93,9 +123,15 @@ extern "C" lloid_status lloid_ctx_create(int device, void *hip_stream, lloid_ctx
   HIP_TRY(hipGetDeviceProperties(&prop, device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(LLOID_EDEVICE, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+  void *scr = nullptr;
+  {
+    const lloid_status r = scratch_address(device, &scr);
+    if (r != LLOID_OK) return r;
+  }
   lloid_ctx *c = new lloid_ctx();
   c->device = device;
   c->n_cu = prop.multiProcessorCount;
+  c->static_scratch = scr;
   // tile shapes: the defaults, or those named by LLOID_FIR_VARIANT / LLOID_MIX_VARIANT
   if (const char *v = getenv("LLOID_FIR_VARIANT")) c->fir_variant = std::min(std::max(atoi(v), 0), kFirVariants - 1);
   if (const char *v = getenv("LLOID_MIX_VARIANT")) c->mix_variant = std::min(std::max(atoi(v), 0), kMixVariants - 1);
@@ -644,9 +680,13 @@ lloid_status lloid::launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dt
 }
 // Filter one block of strain of one detector with every bank of `banks`
 // (same context, full rate and operand type) and compact the triggers.
+// no_alloc: every device buffer comes from the context's static scratch
+// (chunks of windows sized to fit it) and the descriptor tables are staged in
+// pageable host memory: no device or pinned allocation, no profiling events.
 static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detector, const void *strain,
                                  lloid_dtype sdt, int64_t n, const lloid_trigger_opts *opts, lloid_trigger *trig,
-                                 int64_t trig_cap, int64_t *n_trig, float *snr, lloid_peaks *peaks) {
+                                 int64_t trig_cap, int64_t *n_trig, float *snr, lloid_peaks *peaks,
+                                 bool no_alloc = false) {
   if (!banks || nb <= 0 || !strain || !n_trig) return fail(LLOID_EINVAL, "NULL argument");
   for (int i = 0; i < nb; ++i)
     if (!banks[i]) return fail(LLOID_EINVAL, "bank %d is NULL", i);
@@ -717,12 +757,9 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   for (int i = 0; i < nb; ++i)
     if (!operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1) + 2 * operand_margin(banks[i])))
       return fail(LLOID_EINVAL, "one trigger window of bank %d needs buffers over 2 GiB", i);
-  const int64_t n_chunks = ceil_div(W, wpc);
-  const int64_t chunk_n = std::min<int64_t>(n, win.start(wpc) + 1);   // samples of the longest chunk
-
   const TileShapes ts(ct, ctx->fir_variant, ctx->mix_variant);
 
-  // ---- workspace layout
+  // ---- workspace layout for chunks of wpc_ windows
   const bool host_strain = !is_device_ptr(strain);
   const bool host_snr = snr && !is_device_ptr(snr);
   int64_t total_rows = 0;
@@ -734,39 +771,76 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
       ++n_fir;
       if (sl.level > 0) n_up += up_plan(0, 1, sl.level).r.size();
     }
-  const size_t tab_bytes = (size_t)n_chunks * (n_fir * sizeof(FirJob) + n_up * sizeof(UpJob) + nb * sizeof(MixJob) +
-                                               64 * (3 + kMaxHops)) +
-                           nb * sizeof(TrigJob) + 256;
-  size_t bytes = 0;
-  auto add = [&](size_t cnt, size_t sz) { bytes = (size_t)round_up((int64_t)bytes, 256) + cnt * sz; };
-  if (host_strain) add((size_t)n, dtype_size(sdt));
-  for (int k = 0; k < n_levels; ++k) add((size_t)sup[k].size(), 4);
-  for (int i = 0; i < nb; ++i) {
-    const size_t tab = (size_t)banks[i]->n_templates * W;
-    add(tab, 4);
-    add(tab, 8);
-    add(tab, 4);
-    add(tab, 4);
-    add(tab, 4);
-    add(tab, 4);
-    add(tab, 8);
-    const int64_t ops = chunk_n + 2 * operand_margin(banks[i]);
-    add((size_t)ops * banks[i]->kcat, esz);
-    for (const auto &sl : banks[i]->slices)
-      if (sl.level > 0)
-        for (int64_t ld : low_ld(ops, sl.level)) add((size_t)sl.lp * ld, low_esz(ct));
+  auto table_bytes = [&](int64_t chunks) -> size_t {
+    return (size_t)chunks * (n_fir * sizeof(FirJob) + n_up * sizeof(UpJob) + nb * sizeof(MixJob) +
+                             64 * (3 + kMaxHops)) +
+           nb * sizeof(TrigJob) + 256;
+  };
+  auto layout_bytes = [&](int64_t wpc_) -> size_t {
+    const int64_t chunk_n_ = std::min<int64_t>(n, win.start(wpc_) + 1);
+    size_t bytes = 0;
+    auto add = [&](size_t cnt, size_t sz) { bytes = (size_t)round_up((int64_t)bytes, 256) + cnt * sz; };
+    if (host_strain) add((size_t)n, dtype_size(sdt));
+    for (int k = 0; k < n_levels; ++k) add((size_t)sup[k].size(), 4);
+    for (int i = 0; i < nb; ++i) {
+      const size_t tab = (size_t)banks[i]->n_templates * W;
+      add(tab, 4);
+      add(tab, 8);
+      add(tab, 4);
+      add(tab, 4);
+      add(tab, 4);
+      add(tab, 4);
+      add(tab, 8);
+      const int64_t ops = chunk_n_ + 2 * operand_margin(banks[i]);
+      add((size_t)ops * banks[i]->kcat, esz);
+      for (const auto &sl : banks[i]->slices)
+        if (sl.level > 0)
+          for (int64_t ld : low_ld(ops, sl.level)) add((size_t)sl.lp * ld, low_esz(ct));
+    }
+    add((size_t)trig_blocks(total_rows * W) + 2, 8);
+    add(1, 4);
+    add((size_t)std::max<int64_t>(dev_cap, 1), sizeof(lloid_trigger));
+    if (host_snr) add((size_t)n * 2 * banks[0]->n_templates, 4);
+    add(table_bytes(ceil_div(W, wpc_)), 1);
+    return bytes;
+  };
+  if (no_alloc) {
+    // the largest chunk of windows whose buffers fit the static scratch
+    const size_t cap = (size_t)LLOID_NOALLOC_SCRATCH_BYTES;
+    const size_t need1 = layout_bytes(1);
+    if (need1 > cap)
+      return fail(LLOID_ENOMEM,
+                  "this call needs %zu bytes of device scratch with one window per chunk; the static scratch "
+                  "holds %zu (use lloid_filter, or a shorter block or fewer templates)",
+                  need1, cap);
+    int64_t lo = 1, hi = wpc;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo + 1) / 2;
+      if (layout_bytes(mid) <= cap) lo = mid;
+      else hi = mid - 1;
+    }
+    wpc = lo;
   }
-  add((size_t)trig_blocks(total_rows * W) + 2, 8);
-  add(1, 4);
-  add((size_t)std::max<int64_t>(dev_cap, 1), sizeof(lloid_trigger));
-  if (host_snr) add((size_t)n * 2 * banks[0]->n_templates, 4);
-  add(tab_bytes, 1);
-  lloid_status rs = ensure_ws(ctx, ctx->ws, bytes);
-  if (rs != LLOID_OK) return rs;
-  rs = ensure_pinned(ctx, ctx->pinned, ctx->pinned_bytes, tab_bytes);
-  if (rs != LLOID_OK) return rs;
+  const int64_t n_chunks = ceil_div(W, wpc);
+  const int64_t chunk_n = std::min<int64_t>(n, win.start(wpc) + 1);   // samples of the longest chunk
+  const size_t tab_bytes = table_bytes(n_chunks);
+  const size_t bytes = layout_bytes(wpc);
+  std::vector<char> host_tab;   // pageable staging of the tables (no_alloc)
+  void *ws_base = nullptr;
+  if (no_alloc) {
+    if (!ctx->static_scratch) return fail(LLOID_EDEVICE, "the context has no static scratch");
+    ws_base = ctx->static_scratch;
+    host_tab.resize(tab_bytes);
+  } else {
+    lloid_status rs = ensure_ws(ctx, ctx->ws, bytes);
+    if (rs != LLOID_OK) return rs;
+    rs = ensure_pinned(ctx, ctx->pinned, ctx->pinned_bytes, tab_bytes);
+    if (rs != LLOID_OK) return rs;
+    ws_base = ctx->ws.base;
+  }
+  const bool prof = ctx->profile && !no_alloc;
 
-  Carve cv{(char *)ctx->ws.base};
+  Carve cv{(char *)ws_base};
   const void *d_strain = strain;
   void *strain_tmp = host_strain ? cv.take<char>((size_t)n * dtype_size(sdt)) : nullptr;
   std::vector<float *> xl(n_levels);
@@ -811,7 +885,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     StageItems items;
   };
   std::vector<Chunk> chunks(n_chunks);
-  char *htab = (char *)ctx->pinned;
+  char *htab = no_alloc ? host_tab.data() : (char *)ctx->pinned;
   size_t off = 0;
   auto put = [&](const void *src, size_t sz) -> size_t {
     off = (size_t)round_up((int64_t)off, 64);
@@ -853,7 +927,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
 
   // ---- launches
   auto mark = [&](int stage, int end) -> hipError_t {
-    return ctx->profile ? hipEventRecord(ctx->ev[2 * stage + end], st) : hipSuccess;
+    return prof ? hipEventRecord(ctx->ev[2 * stage + end], st) : hipSuccess;
   };
   HIP_TRY(mark(LLOID_STAGE_INGEST, 0));
   HIP_TRY(hipMemcpyAsync(dtab, htab, off, hipMemcpyHostToDevice, st));
@@ -872,7 +946,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   const float phase_thr = (peaks && peaks[0].phase) ? -1.f : thr;
   // every chunk's FIR, interpolation, mixing and phase stages get events of their own
   const size_t nev = (size_t)2 * kChunkStages * n_chunks;
-  if (ctx->profile)
+  if (prof)
     while (ctx->cev.size() < nev) {
       hipEvent_t e;
       HIP_TRY(hipEventCreate(&e));
@@ -880,7 +954,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     }
   for (int64_t c = 0; c < n_chunks; ++c) {
     const lloid_status r2 = launch_stages(ctx, ct, dtab, chunks[c].to, chunks[c].items, snr != nullptr, phase_thr,
-                                          thr, ctx->profile ? &ctx->cev[(size_t)2 * kChunkStages * c] : nullptr);
+                                          thr, prof ? &ctx->cev[(size_t)2 * kChunkStages * c] : nullptr);
     if (r2 != LLOID_OK) return r2;
   }
   HIP_TRY(mark(LLOID_STAGE_TRIGGER, 0));
@@ -908,7 +982,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   if (ncopy > 0) HIP_TRY(hipMemcpyAsync(trig, dtrig, (size_t)ncopy * sizeof(lloid_trigger), hipMemcpyDefault, st));
   HIP_TRY(mark(LLOID_STAGE_D2H, 1));
   HIP_TRY(hipStreamSynchronize(st));
-  if (ctx->profile) {
+  if (prof) {
     for (int i = 0; i < LLOID_N_STAGES; ++i) {
       float ms = 0.f;
       if (i >= LLOID_STAGE_FIR && i < LLOID_STAGE_FIR + kChunkStages) {
@@ -938,6 +1012,15 @@ extern "C" lloid_status lloid_filter(lloid_bank *b, int32_t detector, const void
   ABI_GUARD_BEGIN
   if (!b) return fail(LLOID_EINVAL, "NULL bank");
   return filter_banks(&b, 1, detector, strain, sdt, n, opts, trig, trig_cap, n_trig, snr, peaks);
+  ABI_GUARD_END
+}
+
+extern "C" lloid_status lloid_filter_noalloc(lloid_bank *b, int32_t detector, const void *strain, lloid_dtype sdt,
+                                             int64_t n, const lloid_trigger_opts *opts, lloid_trigger *trig,
+                                             int64_t trig_cap, int64_t *n_trig, lloid_peaks *peaks) {
+  ABI_GUARD_BEGIN
+  if (!b) return fail(LLOID_EINVAL, "NULL bank");
+  return filter_banks(&b, 1, detector, strain, sdt, n, opts, trig, trig_cap, n_trig, nullptr, peaks, true);
   ABI_GUARD_END
 }
 

@@ -131,6 +131,7 @@ struct lloid_ctx {
   double halfband[lloid::kHalfTaps];
   int n_cu = 0;
   lloid::Workspace ws;          // grow-only device scratch of filter calls on this context
+  void *static_scratch = nullptr;  // this device's static scratch array (lloid_filter_noalloc)
   void *pinned = nullptr;       // pinned host staging for descriptor tables
   size_t pinned_bytes = 0;
   int64_t chunk_budget = int64_t(6) << 30;  // device bytes of per-chunk operands

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "liblloid.so")
 LLOID_OK, LLOID_EINVAL, LLOID_ENOMEM, LLOID_EAGAIN = 0, -1, -2, -3
 LLOID_ETRUNC, LLOID_EDEVICE, LLOID_EORDER, LLOID_EDATA = -4, -5, -6, -7
 LLOID_F64, LLOID_F32, LLOID_F16, LLOID_BF16 = 0, 1, 2, 3
+NOALLOC_SCRATCH_BYTES = 256 << 20   # LLOID_NOALLOC_SCRATCH_BYTES
 DTYPES = {"f64": LLOID_F64, "f32": LLOID_F32, "f16": LLOID_F16, "bf16": LLOID_BF16}
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EAGAIN", -4: "ETRUNC",
                 -5: "EDEVICE", -6: "EORDER", -7: "EDATA"}
@@ -119,6 +120,8 @@ def _load():
         "lloid_bank_destroy": ([vp], ctypes.c_int),
         "lloid_filter": ([vp, i32, vp, ctypes.c_int, i64, ctypes.POINTER(lloid_trigger_opts), vp, i64,
                           ctypes.POINTER(i64), vp, ctypes.POINTER(lloid_peaks)], ctypes.c_int),
+        "lloid_filter_noalloc": ([vp, i32, vp, ctypes.c_int, i64, ctypes.POINTER(lloid_trigger_opts), vp, i64,
+                                  ctypes.POINTER(i64), ctypes.POINTER(lloid_peaks)], ctypes.c_int),
         "lloid_ctx_set_tiles": ([vp, i32, i32], ctypes.c_int),
         "lloid_ctx_get_tiles": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
         "lloid_autotune": ([vp, ctypes.POINTER(vp), i32, ctypes.c_double, ctypes.c_char_p, vp, i32,
@@ -169,7 +172,7 @@ def exported_symbols():
     return ["lloid_last_error", "lloid_version", "lloid_ctx_create", "lloid_ctx_destroy",
             "lloid_ctx_profile", "lloid_ctx_stage_times",
             "lloid_bank_create", "lloid_bank_sigma2", "lloid_bank_query", "lloid_bank_destroy",
-            "lloid_filter", "lloid_filter_batch", "lloid_ctx_set_chunk_bytes",
+            "lloid_filter", "lloid_filter_noalloc", "lloid_filter_batch", "lloid_ctx_set_chunk_bytes",
             "lloid_stream_create", "lloid_stream_admit", "lloid_stream_remove", "lloid_stream_push",
             "lloid_stream_poll", "lloid_stream_flush", "lloid_stream_stats_get", "lloid_stream_stats_reset",
             "lloid_stream_destroy",
@@ -389,6 +392,37 @@ def lloid_filter(bank, detector: int, strain, window=(1, 1), threshold: float = 
     else:
         res.triggers = triggers_out
     res.snr = snr_out
+    return res
+
+
+def lloid_filter_noalloc(bank, detector: int, strain, window=(1, 1), threshold: float = 4.0,
+                         strain_scale: float = 0.0, trig_cap: int | None = None,
+                         peaks: bool = False) -> FilterResult:
+    """lloid_filter through the allocation-free entry point (static device
+    scratch of NOALLOC_SCRATCH_BYTES per GPU).  The caller's outputs are host
+    numpy arrays allocated here."""
+    strain, dt, n = _strain_arg(strain)
+    info = lloid_bank_query(bank)
+    num, den = window
+    opts = lloid_trigger_opts(int(num), int(den), float(threshold), float(strain_scale))
+    n_windows = -(-n * int(den) // (info.full_rate_hz * int(num)))
+    res = FilterResult(triggers=None, n_triggers=0)
+    pk = None
+    if peaks:
+        res.peak_snr = np.empty((info.n_templates, n_windows), dtype=np.float32)
+        res.peak_sample = np.empty((info.n_templates, n_windows), dtype=np.int64)
+        res.peak_phase = np.empty((info.n_templates, n_windows), dtype=np.float32)
+        pk = lloid_peaks(res.peak_snr.ctypes.data, res.peak_sample.ctypes.data, res.peak_phase.ctypes.data,
+                         n_windows)
+    cap = trig_cap if trig_cap is not None else info.n_templates * max(1, n_windows)
+    out = np.empty(max(cap, 1), dtype=TRIGGER_DTYPE)
+    n_trig = ctypes.c_int64()
+    st = _lib.lloid_filter_noalloc(bank, int(detector), ctypes.c_void_p(_ptr(strain)), dt, int(n),
+                                   ctypes.byref(opts), ctypes.c_void_p(out.ctypes.data), int(cap),
+                                   ctypes.byref(n_trig), ctypes.byref(pk) if pk is not None else None)
+    _check(st)
+    res.n_triggers = int(n_trig.value)
+    res.triggers = out[: res.n_triggers]
     return res
 
 
