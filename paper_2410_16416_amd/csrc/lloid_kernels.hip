@@ -672,6 +672,253 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mix_peak(const MixJob *__restr
   }
 }
 
+// 16-bit operands, direct-to-LDS form of the mixing kernel.  The operand
+// chunks go from global memory straight into LDS (16-byte buffer loads with
+// an LDS destination: no staging registers, no LDS store instructions), two
+// buffers; rows past either matrix's end read as zero.  An LDS row holds BK
+// elements in 16-byte chunks, chunk q of row r at position
+// q ^ ((r / (16 / CPR)) % CPR) (CPR chunks per row), so the 16 rows that 16
+// lanes read in one fragment load start on distinct banks.  Each output's K
+// sum runs in the same order as in k_mix_peak, so the results are
+// bit-identical.  The compiled shape: 256 x 256 tiles of eight 64 x 128
+// waves, K chunks of 64 (128 KiB of LDS, one workgroup per CU).  Measured and
+// not kept: four 128 x 128 waves (one wave per SIMD: its 256 accumulators
+// leave the epilogue spilling, 7.6 against 4.0 ms per 1024-template
+// detector-call) and two independent workgroups of 128 x 256 per CU with K
+// chunks of 32 (4.9 ms).
+template <int BK> struct DlRow {
+  static constexpr int BYTES = 2 * BK, CPR = BYTES / 16, RPI = 1024 / BYTES;   // RPI: rows per load instruction
+  static __device__ __forceinline__ int swz(int row, int q) { return q ^ ((row / (16 / CPR)) % CPR); }
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Fragments of one k-step: MT A fragments (mixing rows wm*32*MT + mt*32 +
+// lane%32) and NT B fragments (operand rows wn*32*NT + nt*32 + lane%32), 8
+// consecutive k values from 16 ks + 8 (lane/32).
+template <typename T, int BK, int MT, int NT>
+__device__ __forceinline__ void dl_frags(const char *a, const char *b, int wm, int wn, int fr, int fh, int ks,
+                                         typename Op<T>::vec (&af)[MT], typename Op<T>::vec (&bf)[NT]) {
+  typedef DlRow<BK> R;
+  const int qc = 2 * ks + fh;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int row = wm * 32 * MT + mt * 32 + fr;
+    af[mt] = *(const typename Op<T>::vec *)(a + row * R::BYTES + R::swz(row, qc) * 16);
+  }
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int row = wn * 32 * NT + nt * 32 + fr;
+    bf[nt] = *(const typename Op<T>::vec *)(b + row * R::BYTES + R::swz(row, qc) * 16);
+  }
+}
+
+template <typename T, int MT, int NT>
+__device__ __forceinline__ void dl_mfmas(const typename Op<T>::vec (&af)[MT], const typename Op<T>::vec (&bf)[NT],
+                                         f32x16 (&acc)[MT][NT]) {
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = Op<T>::mfma(af[mt], bf[nt], acc[mt][nt]);
+}
+
+// Schedule: the chunks of all column steps of the window form one sequence
+// g = 0, 1, ...  (chunk c = g % nchunks of column step g / nchunks).  Within
+// a chunk, the fragments of k-step ks + 1 are read while the MFMAs of ks
+// run; before the MFMAs of the last k-step, every wave waits for the next
+// chunk's loads and meets at the barrier, then reads the next chunk's first
+// fragments and starts the loads of the chunk after it into the buffer just
+// finished, and only then issues the last k-step's MFMAs.  With K chunks of
+// 64 and kcat an odd multiple of 32, the last chunk of a column step holds 2
+// k-steps: its upper 32 columns are loaded as out-of-range (zeros) for both
+// operands, so the 4 k-steps always run and the extra products are exact
+// zeros.  Waves: WM x WN, each 32 MT rows x 32 NT columns; WGS workgroups per
+// CU.
+template <typename T, int WM, int WN, int MT, int NT, int BK, int WGS, bool SNR>
+__global__ __launch_bounds__(64 * WM * WN, WGS) void k_mix_dl(const MixJob *__restrict__ jobs, int n_jobs) {
+  static_assert(sizeof(T) == 2, "16-bit operands only");
+  typedef typename Op<T>::vec vec;
+  typedef DlRow<BK> R;
+  constexpr int NW = WM * WN, THREADS = 64 * NW;
+  constexpr int BM = 32 * MT * WM, BN = 32 * NT * WN;
+  constexpr int KS = BK / 16;                  // k-steps per chunk
+  constexpr int JA = BM / R::RPI / NW, JB = BN / R::RPI / NW;   // load instructions per wave and chunk
+  static_assert(JA * R::RPI * NW == BM && JB * R::RPI * NW == BN, "whole load instructions per wave");
+  static_assert((R::RPI * NW) % 16 == 0, "one voffset per wave");
+  static_assert(KS == 2 || KS == 4, "chunks of 32 or 64");
+  __shared__ __attribute__((aligned(1024))) char As0[BM * R::BYTES];
+  __shared__ __attribute__((aligned(1024))) char Bs0[BN * R::BYTES];
+  __shared__ __attribute__((aligned(1024))) char As1[BM * R::BYTES];
+  __shared__ __attribute__((aligned(1024))) char Bs1[BN * R::BYTES];
+  __shared__ VN red[WN][BM / 2];
+
+  const MixJob &jb = jobs[find_job(jobs, n_jobs, blockIdx.x)];
+  const int64_t b = (int64_t)blockIdx.x - jb.item0;
+  const int n_rtiles = jb.n_rtiles;
+  int rt;
+  int64_t wl;
+  if (jb.nw >= 8) {
+    const int64_t slot = b >> 3;
+    rt = (int)(slot % n_rtiles);
+    wl = (slot / n_rtiles) * 8 + (b & 7);
+  } else {
+    rt = (int)(b % n_rtiles);
+    wl = b / n_rtiles;
+  }
+  if (wl >= jb.nw) return;
+  const int64_t w = jb.w0 + wl;
+  const T *mix = (const T *)jb.mix;
+  const int rows = jb.rows, kcat = jb.kcat, n_templates = jb.n_templates;
+  const float inv_scale = jb.inv_scale;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t r0 = (int64_t)rt * BM;
+  const int64_t ws = (w * jb.win_p) / jb.win_q;
+  int64_t we = ((w + 1) * jb.win_p) / jb.win_q;
+  if (we > jb.n_end) we = jb.n_end;
+  const T *ocat = (const T *)jb.ocat + (ws - jb.ocat_abs0) * (int64_t)kcat;
+  VN best[MT][8];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int p = 0; p < 8; ++p) best[mt][p] = VN{-1.f, 0x7fffffff};
+
+  constexpr int ESZ = 2;
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(mix + r0 * kcat, (rows - r0) * (int64_t)kcat * ESZ);
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(ocat, (we - ws) * (int64_t)kcat * ESZ);
+  const int nchunks = (kcat + BK - 1) / BK;
+  const bool half_tail = (kcat % BK) != 0;   // K chunks of 64: the last one holds 32 columns
+  const int nsteps = (int)((we - ws + BN - 1) / BN);
+  const int G = nsteps * nchunks;
+  // Load instruction j of this wave fills LDS rows RPI (NW j + wave) .. + RPI - 1
+  // of a tile, lane i the 16-byte position i % CPR of row RPI (NW j + wave) +
+  // i / CPR: logical chunk swz(row, i % CPR), the same for every j (the row
+  // step is a multiple of 16 rows), so one voffset serves every instruction
+  // and the row step goes into the scalar offset.
+  const int vrow = R::RPI * wave + lane / R::CPR;
+  const int lq = R::swz(vrow, lane % R::CPR);
+  const int voffs = vrow * kcat * ESZ + lq * 16;
+  const int voffs_tail = lq < R::CPR / 2 ? voffs : 0x7ff00000;   // upper half of a half chunk: zeros
+  const int jstep = R::RPI * NW * kcat * ESZ;
+  auto issue = [&](int g) {
+    const int c = g % nchunks, st = g / nchunks;
+    const int ka = c * BK * ESZ;
+    const int kb = st * BN * kcat * ESZ + ka;
+    const int vo = (half_tail && c == nchunks - 1) ? voffs_tail : voffs;
+    char *at = (g & 1) ? As1 : As0;
+    char *bt = (g & 1) ? Bs1 : Bs0;
+#pragma unroll
+    for (int j = 0; j < JA; ++j)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_void *)(at + (NW * j + wave) * 1024), 16, vo,
+                                               ka + j * jstep, 0, 0);
+#pragma unroll
+    for (int j = 0; j < JB; ++j)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void *)(bt + (NW * j + wave) * 1024), 16, vo,
+                                               kb + j * jstep, 0, 0);
+  };
+  const int fr = lane & 31, fh = lane >> 5;
+  vec fa0[MT], fb0[NT], fa1[MT], fb1[NT];
+  issue(0);
+  __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
+  __syncthreads();
+  dl_frags<T, BK, MT, NT>(As0, Bs0, wm, wn, fr, fh, 0, fa0, fb0);
+  if (G > 1) issue(1);
+  int g = 0;
+  for (int st = 0; st < nsteps; ++st) {
+    f32x16 acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[mt][nt][e] = 0.f;
+    for (int c = 0; c < nchunks; ++c, ++g) {
+      const char *a = (g & 1) ? As1 : As0;
+      const char *bt = (g & 1) ? Bs1 : Bs0;
+      // the phases stay in this order (the scheduler would otherwise hoist
+      // the barrier above the MFMAs and group the reads)
+      dl_frags<T, BK, MT, NT>(a, bt, wm, wn, fr, fh, 1, fa1, fb1);
+      __builtin_amdgcn_sched_barrier(0);
+      dl_mfmas<T, MT, NT>(fa0, fb0, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (KS == 4) {
+        dl_frags<T, BK, MT, NT>(a, bt, wm, wn, fr, fh, 2, fa0, fb0);
+        __builtin_amdgcn_sched_barrier(0);
+        dl_mfmas<T, MT, NT>(fa1, fb1, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        dl_frags<T, BK, MT, NT>(a, bt, wm, wn, fr, fh, 3, fa1, fb1);
+        __builtin_amdgcn_sched_barrier(0);
+        dl_mfmas<T, MT, NT>(fa0, fb0, acc);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // the next chunk's loads (this wave's part) are done and this wave's
+      // reads of the current buffer have returned; the barrier makes both
+      // hold for every wave
+      __builtin_amdgcn_s_waitcnt(0x0070);   // vmcnt(0) lgkmcnt(0)
+      __syncthreads();
+      if (g + 1 < G)
+        dl_frags<T, BK, MT, NT>((g & 1) ? As0 : As1, (g & 1) ? Bs0 : Bs1, wm, wn, fr, fh, 0, fa0, fb0);
+      if (g + 2 < G) issue(g + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      dl_mfmas<T, MT, NT>(fa1, fb1, acc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // epilogue of the column step: complex SNR of 8 templates per lane per
+    // row tile, running peaks
+    const int64_t n0 = ws + (int64_t)st * BN;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int64_t col = n0 + wn * 32 * NT + nt * 32 + fr;
+      const bool ok = col < we;
+      const int rel = (int)(col - ws);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          const float re = acc[mt][nt][2 * p], im = acc[mt][nt][2 * p + 1];
+          const float v = re * re + im * im;
+          if (ok && v > best[mt][p].v) best[mt][p] = VN{v, rel};
+          if (SNR && ok) {
+            const int64_t i = (r0 + wm * 32 * MT + mt * 32 + 8 * (p >> 1) + 4 * fh + 2 * (p & 1)) >> 1;
+            if (i < n_templates)
+              *(float2 *)(jb.snr + (i * jb.snr_ld + (col - jb.snr_abs0)) * 2) =
+                  make_float2(re * inv_scale, im * inv_scale);
+          }
+        }
+      }
+    }
+  }
+
+  // reduce the 32 columns of each half-wave, then the waves that share rows
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      VN bb = best[mt][p];
+#pragma unroll
+      for (int off = 1; off < 32; off <<= 1) {
+        const float ov = __shfl_xor(bb.v, off);
+        const int on = __shfl_xor(bb.n, off);
+        if (better(ov, on, bb.v, bb.n)) bb = VN{ov, on};
+      }
+      if (fr == 0) red[wn][wm * 16 * MT + mt * 16 + 4 * (p >> 1) + 2 * fh + (p & 1)] = bb;
+    }
+  __syncthreads();
+  for (int t = threadIdx.x; t < BM / 2; t += THREADS) {
+    VN bb = red[0][t];
+#pragma unroll
+    for (int q = 1; q < WN; ++q)
+      if (better(red[q][t].v, red[q][t].n, bb.v, bb.n)) bb = red[q][t];
+    const int64_t i = r0 / 2 + t;
+    if (i < n_templates) {
+      const int64_t o = i * jb.ld_peak + (w - jb.w_base);
+      jb.peak_snr[o] = sqrtf(fmaxf(bb.v, 0.f)) * inv_scale;
+      jb.peak_n[o] = ws + bb.n;
+    }
+  }
+}
+
 // Phase and sub-sample refinement at each reported window peak: z_i at n* - 1,
 // n*, n* + 1 recomputed as the dot products of mixing rows 2i, 2i+1 with those
 // operand rows (FP32 accumulation; the operand holds one extra sample on each
@@ -1402,10 +1649,19 @@ static hipError_t mix_t(int variant, const MixJob *jobs, int n_jobs, int64_t n_i
     case 1: return mix_v<T, 4, 2, 2, 2, 32>(jobs, n_jobs, n_items, with_snr, s);
     case 2: return mix_v<T, 2, 2, 4, 2, 32>(jobs, n_jobs, n_items, with_snr, s);
     case 3: return mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 32>(jobs, n_jobs, n_items, with_snr, s);
-    default:
-      // 16-bit operands: K chunks of 64 (149.5 KB of LDS, one workgroup per CU)
+    case 4:
+      // 16-bit operands: register-staged K chunks of 64 (149.5 KB of LDS, one workgroup per CU)
       if constexpr (sizeof(T) == 2) return mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 64>(jobs, n_jobs, n_items, with_snr, s);
       else return mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 32>(jobs, n_jobs, n_items, with_snr, s);
+    default:
+      // 16-bit operands: direct-to-LDS K chunks of 64, eight 64 x 128 waves
+      if constexpr (sizeof(T) == 2) {
+        if (with_snr) k_mix_dl<T, 4, 2, 2, 4, 64, 1, true><<<(unsigned)n_items, 512, 0, s>>>(jobs, n_jobs);
+        else k_mix_dl<T, 4, 2, 2, 4, 64, 1, false><<<(unsigned)n_items, 512, 0, s>>>(jobs, n_jobs);
+        return hipGetLastError();
+      } else {
+        return mix_v<T, kMixMT, kMixNT, kMixWM, kMixWN, 32>(jobs, n_jobs, n_items, with_snr, s);
+      }
   }
 }
 
