@@ -713,13 +713,16 @@ __device__ __forceinline__ void dl_frags(const char *a, const char *b, int wm, i
   }
 }
 
-template <typename T, int MT, int NT>
+// FIRST: the first k-step of a column step, whose accumulators start at zero
+// (the zero is the MFMA's constant operand, no register clearing)
+template <typename T, int MT, int NT, bool FIRST = false>
 __device__ __forceinline__ void dl_mfmas(const typename Op<T>::vec (&af)[MT], const typename Op<T>::vec (&bf)[NT],
                                          f32x16 (&acc)[MT][NT]) {
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = Op<T>::mfma(af[mt], bf[nt], acc[mt][nt]);
+    for (int nt = 0; nt < NT; ++nt)
+      acc[mt][nt] = Op<T>::mfma(af[mt], bf[nt], FIRST ? f32x16{} : acc[mt][nt]);
 }
 
 // Schedule: the chunks of all column steps of the window form one sequence
@@ -827,20 +830,17 @@ __global__ __launch_bounds__(64 * WM * WN, WGS) void k_mix_dl(const MixJob *__re
   int g = 0;
   for (int st = 0; st < nsteps; ++st) {
     f32x16 acc[MT][NT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[mt][nt][e] = 0.f;
-    for (int c = 0; c < nchunks; ++c, ++g) {
+    // one chunk; FIRST: the column step's first (its first k-step starts the
+    // sums); skip_hi: a half chunk (its k-steps 2 and 3 are zeros: no MFMAs)
+    auto chunk = [&](auto first_c, bool skip_hi) {
+      constexpr bool FIRST = decltype(first_c)::value;
       const char *a = (g & 1) ? As1 : As0;
       const char *bt = (g & 1) ? Bs1 : Bs0;
       // the phases stay in this order (the scheduler would otherwise hoist
       // the barrier above the MFMAs and group the reads)
       dl_frags<T, BK, MT, NT>(a, bt, wm, wn, fr, fh, 1, fa1, fb1);
       __builtin_amdgcn_sched_barrier(0);
-      dl_mfmas<T, MT, NT>(fa0, fb0, acc);
+      dl_mfmas<T, MT, NT, FIRST>(fa0, fb0, acc);
       __builtin_amdgcn_sched_barrier(0);
       if constexpr (KS == 4) {
         dl_frags<T, BK, MT, NT>(a, bt, wm, wn, fr, fh, 2, fa0, fb0);
@@ -849,7 +849,7 @@ __global__ __launch_bounds__(64 * WM * WN, WGS) void k_mix_dl(const MixJob *__re
         __builtin_amdgcn_sched_barrier(0);
         dl_frags<T, BK, MT, NT>(a, bt, wm, wn, fr, fh, 3, fa1, fb1);
         __builtin_amdgcn_sched_barrier(0);
-        dl_mfmas<T, MT, NT>(fa0, fb0, acc);
+        if (!skip_hi) dl_mfmas<T, MT, NT>(fa0, fb0, acc);
         __builtin_amdgcn_sched_barrier(0);
       }
       // the next chunk's loads (this wave's part) are done and this wave's
@@ -861,9 +861,12 @@ __global__ __launch_bounds__(64 * WM * WN, WGS) void k_mix_dl(const MixJob *__re
         dl_frags<T, BK, MT, NT>((g & 1) ? As0 : As1, (g & 1) ? Bs0 : Bs1, wm, wn, fr, fh, 0, fa0, fb0);
       if (g + 2 < G) issue(g + 2);
       __builtin_amdgcn_sched_barrier(0);
-      dl_mfmas<T, MT, NT>(fa1, fb1, acc);
+      if (KS == 2 || !skip_hi) dl_mfmas<T, MT, NT>(fa1, fb1, acc);
       __builtin_amdgcn_sched_barrier(0);
-    }
+      ++g;
+    };
+    chunk(std::true_type{}, half_tail && nchunks == 1);
+    for (int c = 1; c < nchunks; ++c) chunk(std::false_type{}, half_tail && c == nchunks - 1);
     // epilogue of the column step: complex SNR of 8 templates per lane per
     // row tile, running peaks
     const int64_t n0 = ws + (int64_t)st * BN;
