@@ -1589,6 +1589,16 @@ template <typename T>
 static hipError_t fir_t(int variant, const FirJob *jobs, int n_jobs, int64_t n_items, hipStream_t s) {
   switch (variant) {
     case 1: return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
+    case 3:
+    case 4:
+      // 16-bit operands: the Hankel fragment window with basis chunks of 128
+      // or 256 taps (a barrier per 8 or 16 k-steps instead of 4)
+      if constexpr (sizeof(T) == 2) {
+        if (variant == 3) return fir_v<T, 2, 4, kFirWaves, 4 * kBK, true>(jobs, n_jobs, n_items, s);
+        return fir_v<T, 2, 4, kFirWaves, 8 * kBK, true>(jobs, n_jobs, n_items, s);
+      } else {
+        return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
+      }
     case 2:
       // 16-bit operands: 64 x 1024 tiles with the Hankel fragment window
       if constexpr (sizeof(T) == 2) return fir_v<T, 2, 4, kFirWaves, 2 * kBK, true>(jobs, n_jobs, n_items, s);
@@ -1603,7 +1613,7 @@ static hipError_t fir_t(int variant, const FirJob *jobs, int n_jobs, int64_t n_i
 void fir_tile_shape(lloid_dtype t, int variant, int *bm, int *bn) {
   *bm = 32 * kFirMT;
   *bn = kFirWaves * 32 * kFirNT;
-  if (variant == 2 && t != LLOID_F32) *bm = 32 * 2, *bn = kFirWaves * 32 * 4;
+  if ((variant == 2 || variant == 3 || variant == 4) && t != LLOID_F32) *bm = 32 * 2, *bn = kFirWaves * 32 * 4;
 }
 
 void mix_tile_shape(lloid_dtype, int variant, int *bm, int *bn) {

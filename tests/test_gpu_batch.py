@@ -109,7 +109,7 @@ def test_tile_variants_give_identical_results(compute):
         # ragged last window (odd and even chunk counts per window)
         for window in ((1, 4), (3, 4)):
             ref = None
-            for fv in range(3):
+            for fv in range(5):
                 for mv in range(5):
                     lloid.lloid_ctx_set_tiles(c, fv, mv)
                     assert lloid.lloid_ctx_get_tiles(c) == (fv, mv)
@@ -133,7 +133,7 @@ def test_tile_variants_give_identical_results(compute):
             else:
                 assert np.array_equal(r.snr, series), mv
         with pytest.raises(lloid.LloidError) as ei:
-            lloid.lloid_ctx_set_tiles(c, 3, 0)
+            lloid.lloid_ctx_set_tiles(c, 5, 0)
         assert ei.value.status == lloid.LLOID_EINVAL
     finally:
         for h in handles:
@@ -154,7 +154,7 @@ def test_autotune_picks_the_fastest_and_caches(tmp_path):
         best, res = lloid.lloid_autotune(c, handles, 4.0, cache)
         log(f"[autotune] best {best}; " + ", ".join(f"{r['fir_variant']}/{r['mix_variant']}: {r['ms']:.2f} ms"
                                                    for r in res))
-        assert res.shape[0] == 3 * 5 and np.all(res["ms"] > 0)   # FIR x mixing shapes
+        assert res.shape[0] == 5 * 5 and np.all(res["ms"] > 0)   # FIR x mixing shapes
         k = int(np.argmin(res["ms"]))
         assert best == (int(res["fir_variant"][k]), int(res["mix_variant"][k]))
         text = open(cache).read()
