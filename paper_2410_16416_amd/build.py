@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblloid.so")
-SOURCES = ["lloid_kernels.hip", "lloid_host.cpp", "lloid_stream.cpp"]
+SOURCES = ["lloid_kernels.hip", "lloid_host.cpp", "lloid_stream.cpp", "lloid_plan.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -445,33 +445,6 @@ lloid_status lloid::ensure_pinned(lloid_ctx *ctx, void *&p, size_t &have, size_t
   return LLOID_OK;
 }
 
-lloid::UpPlan lloid::up_plan(int64_t t0, int64_t t1, int level) {
-  UpPlan p;
-  // an odd level starts with one x2 hop at its own (lowest) rate, the rest are x4
-  for (int lev = level; lev > 0;) {
-    const int r = (lev % 2) ? 2 : 4;
-    p.r.push_back(r);
-    p.lev_in.push_back(lev);
-    lev -= r == 4 ? 2 : 1;
-    p.lev_out.push_back(lev);
-  }
-  const int H = (int)p.r.size();
-  p.in.resize(H);
-  p.out.resize(H);
-  // top-down: a hop's outputs, in whole 32-sample tiles from a multiple of 32,
-  // read the 64 source samples of each tile from n0 / R - (32 - 32 / R)
-  Range want{t0, t1};
-  for (int h = H - 1; h >= 0; --h) {
-    p.out[h] = want;
-    const int64_t a = floor_div(want.lo, 32) * 32;
-    const int64_t span = round_up(want.hi - a, kUpCols);
-    const int R = p.r[h], c = 32 - 32 / R;
-    p.in[h] = {a / R - c, (a + span - 32) / R - c + 64};
-    want = p.in[h];
-  }
-  return p;
-}
-
 bool lloid::operands_fit(const lloid_bank *b, int64_t t_len) {
   if (t_len * b->kcat * (int64_t)dtype_size(b->compute) > kMaxBuffer) return false;
   for (const auto &sl : b->slices)
@@ -479,21 +452,6 @@ bool lloid::operands_fit(const lloid_bank *b, int64_t t_len) {
       for (int64_t ld : low_ld(t_len, sl.level))
         if ((int64_t)sl.lp * ld * (int64_t)low_esz(b->compute) > kMaxBuffer) return false;
   return true;
-}
-
-std::vector<int64_t> lloid::low_ld(int64_t t_len, int level) {
-  const UpPlan p = up_plan(0, 1, level);   // hop rates only
-  const int H = (int)p.r.size();
-  std::vector<int64_t> ld(H);
-  int64_t want = t_len;
-  for (int h = H - 1; h >= 0; --h) {
-    // worst case: the first output sits 31 samples past a tile start
-    const int64_t span = round_up(want + 31, kUpCols);
-    const int64_t in = (span - 32) / p.r[h] + 64;
-    ld[h] = round_up(in, 64);
-    want = in;
-  }
-  return ld;
 }
 
 void lloid::interp_fragments(const double *g, int R, int ks_elems, int vec, std::vector<double> &out) {

@@ -9,12 +9,9 @@
 #include <vector>
 
 #include "lloid.h"
+#include "lloid_plan.h"
 
 namespace lloid {
-
-// Half-band resampler: g[n], |n| <= kHalfQ, zero at even n != 0.
-constexpr int kHalfQ = 32;
-constexpr int kHalfTaps = 2 * kHalfQ + 1;
 
 // GEMM tiling shared by the FIR and the mixing kernels (wave64, 4 waves).
 constexpr int kWaves = 4;
@@ -31,11 +28,6 @@ constexpr int kFirMT = 4, kFirNT = 2, kFirWaves = 8, kFirKSup = 1024;
 constexpr int kMixMT = 2, kMixNT = 4, kMixWM = 4, kMixWN = 2;
 constexpr int kMixBM = 32 * kMixMT * kMixWM;
 constexpr int kMixBN = 32 * kMixNT * kMixWN;
-
-struct Range {
-  int64_t lo = 0, hi = 0;  // absolute indices [lo, hi)
-  int64_t size() const { return hi > lo ? hi - lo : 0; }
-};
 
 // Device-side description of one slice of a bank.
 struct SliceDev {
@@ -175,8 +167,7 @@ void mix_tile_shape(lloid_dtype t, int variant, int *bm, int *bn);
 hipError_t launch_fir_jobs(lloid_dtype t, int variant, const FirJob *jobs, int n_jobs, int64_t n_items,
                            hipStream_t s);
 hipError_t launch_up_jobs(lloid_dtype t, const UpJob *jobs, int n_jobs, int64_t n_items, hipStream_t s);
-// Work items of an interpolation job: four 32-channel x 128-sample wave tasks each.
-constexpr int kUpCols = 128;
+// Work items of an interpolation job: four 32-channel x kUpCols-sample wave tasks each.
 // Mixing and window peaks; then the phase at peaks with |z| >= phase_thr (0 for the others).
 hipError_t launch_mix_jobs(lloid_dtype t, int variant, const MixJob *jobs, int n_jobs, int64_t n_items,
                            bool with_snr, hipStream_t s);
@@ -211,9 +202,6 @@ hipError_t launch_fill_u8(void *p, size_t bytes, hipStream_t s);
 // ---- shared host helpers (lloid_host.cpp) ----
 lloid_status fail(lloid_status st, const char *fmt, ...);
 
-inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
-inline int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-inline int64_t ceil_div(int64_t a, int64_t b) { return -floor_div(-a, b); }
 
 inline size_t dtype_size(lloid_dtype t) {
   switch (t) {
@@ -239,23 +227,6 @@ inline bool is_device_ptr(const void *p) {
   return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
-// interpolation reads w[j] with |n - 2j| <= Q and decimation reads u[2k - m]
-// with |m| <= Q: the range a level needs from the one above it
-inline Range halo_up(Range r) { return {ceil_div(r.lo - kHalfQ, 2), floor_div(r.hi - 1 + kHalfQ, 2) + 1}; }
-
-inline std::vector<Range> need_ranges(int64_t t0, int64_t t1, int n_levels) {
-  std::vector<Range> need(n_levels);
-  need[0] = {t0, t1};
-  for (int k = 1; k < n_levels; ++k) need[k] = halo_up(need[k - 1]);
-  return need;
-}
-
-// Trigger windows: window w starts at floor(w p / q).
-struct Windows {
-  int64_t p = 1, q = 1;
-  int64_t start(int64_t w) const { return (w * p) / q; }
-  int64_t count(int64_t n) const { return ceil_div(n * q, p); }   // windows intersecting [0, n)
-};
 
 struct Carve {
   char *base;
@@ -292,9 +263,6 @@ struct TileShapes {
   }
 };
 
-constexpr int kMaxLevel = 7;       // lowest slice rate f0 / 128
-constexpr int kMaxAutocorrHalf = 512;
-constexpr int kMaxHops = 4;        // interpolation hops of a level-7 slice: x2, x4, x4, x4
 
 struct StageItems {
   int64_t fir = 0, mix = 0, entries = 0;
@@ -310,18 +278,6 @@ struct TabOffsets {
 
 lloid_status ensure_ws(lloid_ctx *ctx, Workspace &ws, size_t bytes);
 lloid_status ensure_pinned(lloid_ctx *ctx, void *&p, size_t &have, size_t bytes);
-// Interpolation hops of a slice at `level` for full-rate outputs [t0, t1):
-// hop h maps level lev_in[h] to lev_out[h] by r[h] on range out[h] (aligned
-// tiles), reading in[h]; the FIR must produce in[0].
-struct UpPlan {
-  std::vector<int> r, lev_in, lev_out;
-  std::vector<Range> in, out;
-};
-UpPlan up_plan(int64_t t0, int64_t t1, int level);
-// Row pitch (elements) of each channel-major low-rate buffer of a slice for
-// outputs spanning t_len samples, an upper bound over output positions:
-// [0] the FIR output, [h] the output of hop h - 1.
-std::vector<int64_t> low_ld(int64_t t_len, int level);
 // Buffer resources address 32-bit byte offsets: operand and low-rate buffers
 // of a chunk stay below kMaxBuffer bytes, level buffers below 2^30 bytes.
 constexpr int64_t kMaxBuffer = (int64_t(1) << 31) - (int64_t(1) << 24);

@@ -47,13 +47,6 @@ struct DetState {
   int64_t pushed = 0;          // full-rate samples ingested by the submitter
 };
 
-struct Slot {
-  lloid_bank *bank = nullptr;
-  int32_t id = -1;
-  int64_t bytes = 0;
-  bool active = false;
-};
-
 // One staging entry of the stride ring: a stride's samples on their way to
 // the device (host strides in pinned memory, device strides already copied
 // to device memory).
@@ -100,12 +93,11 @@ struct lloid_stream {
   lloid_dtype ct = LLOID_F16;
   Windows win;
   float thr = 4.f, sscale = 1.f;
-  int64_t budget = 0, used = 0;
   int64_t win_len = 1;
   std::vector<int64_t> hist, cap;  // per level: history kept, buffer capacity
   std::vector<DetState> det;
-  std::vector<Slot> slots;         // index = slot id
-  std::deque<int32_t> queue;       // slot ids waiting for admission
+  Admission adm;                   // slots: device-memory budget, arrival-order queue
+  std::vector<lloid_bank *> bank_of;   // per slot id (NULL once removed)
   int64_t w_next = 0;              // next window to enqueue
   int64_t n_end = -1;              // data end once flushed (-1 while streaming)
   int64_t push_max = 0;            // samples per staging entry
@@ -180,17 +172,6 @@ lloid_status check_bank(const lloid_stream *s, const lloid_bank *b) {
     if (span > s->hist[sl.level]) return fail(LLOID_EINVAL, "a slice spans more than the stream's history");
   }
   return LLOID_OK;
-}
-
-// admit queued banks in arrival order while they fit the budget (lock held)
-void admit_queued(lloid_stream *s) {
-  while (!s->queue.empty()) {
-    Slot &q = s->slots[s->queue.front()];
-    if (s->budget > 0 && s->used + q.bytes > s->budget) break;
-    s->used += q.bytes;
-    q.active = true;
-    s->queue.pop_front();
-  }
 }
 
 // Record the first failure of a worker thread (lock held); later calls return it.
@@ -275,38 +256,23 @@ lloid_status ingest(lloid_stream *s, int d, const void *src, lloid_dtype dt, int
   return decimate_new(s, ds, last);
 }
 
-// Largest window end wb (> w_next) whose outputs every active bank can compute now.
-int64_t ready_until(const lloid_stream *s) {
-  int64_t data_end = INT64_MAX;
-  for (const auto &d : s->det) data_end = std::min(data_end, d.pushed);
-  if (s->n_end >= 0) data_end = s->n_end;
-  int64_t best = s->w_next;
-  for (int64_t wb = s->w_next + 1; wb <= s->w_next + s->max_w; ++wb) {
-    const int64_t t0 = s->win.start(s->w_next);
-    int64_t t1 = s->win.start(wb);
-    if (s->n_end >= 0) {
-      if (t0 >= s->n_end) break;
-      t1 = std::min(t1, s->n_end);
-    } else if (t1 > data_end) {
-      break;
-    }
-    bool ok = true;
-    for (const auto &sl : s->slots) {
-      if (!sl.active || !ok) continue;
-      const int64_t mg = operand_margin(sl.bank);
-      for (const auto &sd : sl.bank->slices) {
-        // outputs [t0 - mg, t1 + mg): the peaks' sub-sample refinement and
-        // signal-consistency lags read up to mg samples past t1
-        const Range r = need_ranges(t0 - mg, t1 + mg, sd.level + 1)[sd.level];
-        for (const auto &d : s->det)
-          if (r.hi - sd.start_tap / sd.dec > d.avail[sd.level]) ok = false;
-      }
-    }
-    if (!ok) break;
-    best = wb;
-    if (s->n_end >= 0 && t1 >= s->n_end) break;
+// Largest window end wb (> w_next) whose outputs every active bank can compute
+// now (submitter thread: the slot table does not change while it runs).
+int64_t stream_ready_until(const lloid_stream *s) {
+  ReadyState st;
+  st.win = s->win;
+  st.w_next = s->w_next;
+  st.max_w = s->max_w;
+  st.n_end = s->n_end;
+  for (const auto &d : s->det) {
+    st.pushed.push_back(d.pushed);
+    st.avail.push_back(d.avail);
   }
-  return best;
+  for (int32_t i = 0; i < s->adm.n_slots(); ++i)
+    if (s->adm.active(i))
+      for (const auto &sd : s->bank_of[i]->slices)
+        st.slices.push_back(ReadySlice{sd.level, sd.start_tap / sd.dec, operand_margin(s->bank_of[i])});
+  return ready_until(st);
 }
 
 lloid_status ensure_pinned_bytes(void *&p, size_t &have, size_t bytes) {
@@ -347,9 +313,8 @@ lloid_status enqueue_tick(lloid_stream *s, int64_t wa, int64_t wb, Clock::time_p
   int ti = -1;
   {
     std::unique_lock<std::mutex> lk(s->mu);
-    admit_queued(s);
-    for (size_t i = 0; i < s->slots.size(); ++i)
-      if (s->slots[i].active) ids.push_back(s->slots[i].id), bank_of.push_back(s->slots[i].bank);
+    for (int32_t i = 0; i < s->adm.n_slots(); ++i)
+      if (s->adm.active(i)) ids.push_back(i), bank_of.push_back(s->bank_of[i]);
     s->w_next = wb;
     s->windows += nw;
     if (ids.empty()) {
@@ -570,7 +535,7 @@ lloid_status process(lloid_stream *s, const Item &it) {
     if (r != LLOID_OK) return r;
   }
   for (;;) {
-    const int64_t wb = ready_until(s);
+    const int64_t wb = stream_ready_until(s);
     if (wb <= s->w_next) break;
     const lloid_status r = enqueue_tick(s, s->w_next, wb, it.pushed_at);
     if (r != LLOID_OK) return r;
@@ -710,7 +675,7 @@ extern "C" lloid_status lloid_stream_create(lloid_ctx *ctx, int32_t full_rate_hz
   s->win_len = ceil_div(s->win.p, s->win.q);
   s->thr = t.threshold;
   s->sscale = sscale;
-  s->budget = opts->hbm_budget;
+  s->adm = Admission(opts->hbm_budget);
   s->max_w = opts->max_windows_per_tick > 0 ? opts->max_windows_per_tick : 8;
   s->use_graph = opts->use_graph != 0;
   int L = 1;
@@ -790,16 +755,12 @@ extern "C" lloid_status lloid_stream_admit(lloid_stream *s, lloid_bank *bank, in
   wait_submitted(s, lk);
   r = stored_error(s);
   if (r != LLOID_OK) return r;
-  Slot sl;
-  sl.bank = bank;
-  sl.id = (int32_t)s->slots.size();
-  sl.bytes = bank->device_bytes + scratch_bytes(s, bank);
-  if (s->budget > 0 && sl.bytes > s->budget) return fail(LLOID_ENOMEM, "the bank alone exceeds the stream's budget");
-  s->slots.push_back(sl);
-  s->queue.push_back(sl.id);
-  admit_queued(s);
-  *slot = sl.id;
-  if (!s->slots[sl.id].active) return fail(LLOID_EAGAIN, "queued until device memory frees up");
+  bool active = false;
+  const int32_t id = s->adm.add(bank->device_bytes + scratch_bytes(s, bank), &active);
+  if (id < 0) return fail(LLOID_ENOMEM, "the bank alone exceeds the stream's budget");
+  s->bank_of.push_back(bank);
+  *slot = id;
+  if (!active) return fail(LLOID_EAGAIN, "queued until device memory frees up");
   return LLOID_OK;
   ABI_GUARD_END
 }
@@ -808,15 +769,11 @@ extern "C" lloid_status lloid_stream_remove(lloid_stream *s, int32_t slot) {
   ABI_GUARD_BEGIN
   if (!s) return fail(LLOID_EINVAL, "NULL stream");
   std::unique_lock<std::mutex> lk(s->mu);
-  if (slot < 0 || slot >= (int32_t)s->slots.size() || !s->slots[slot].bank) return fail(LLOID_EINVAL, "no such slot");
+  if (!s->adm.present(slot)) return fail(LLOID_EINVAL, "no such slot");
   // the bank leaves at the stream's position after every stride pushed so far
   wait_submitted(s, lk);
-  Slot &sl = s->slots[slot];
-  if (sl.active) s->used -= sl.bytes;
-  else s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), slot), s->queue.end());
-  sl.active = false;
-  sl.bank = nullptr;
-  admit_queued(s);
+  s->adm.remove(slot);   // queued banks that now fit become active
+  s->bank_of[slot] = nullptr;
   // the caller may destroy the bank: no tick in flight may still read it
   wait_completed(s, lk);
   return stored_error(s);
@@ -959,9 +916,9 @@ extern "C" lloid_status lloid_stream_stats_get(const lloid_stream *s, lloid_stre
     out->latency_p99_ms = q(0.99);
     out->latency_max_ms = v.back();
   }
-  for (const auto &sl : s->slots)
-    if (sl.bank) (sl.active ? out->active_slots : out->queued_banks) += 1;
-  out->bytes_in_use = s->used;
+  out->active_slots = s->adm.n_active();
+  out->queued_banks = s->adm.n_queued();
+  out->bytes_in_use = s->adm.used();
   out->graph_captures = s->graph_captures;
   out->graph_replays = s->graph_replays;
   out->queued_strides = (int64_t)s->inbox.size();
