@@ -562,10 +562,12 @@ void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, 
   m.peak_si = bb.psi;
   m.peak_xi = bb.pxi;
   m.peak_z = b->acorr ? bb.pz : nullptr;
+  m.xi_key = b->acorr ? bb.pkey : nullptr;
   m.acorr = b->acorr;
   m.acorr_half = b->acorr_half;
   m.snr = snr;
   m.ocat_abs0 = e0;
+  m.ocat_end = e1;
   m.snr_abs0 = t0;
   m.n_end = n_end;
   m.w0 = wa;
@@ -607,7 +609,11 @@ void lloid::number_jobs(std::vector<FirJob> &fj, std::vector<UpJob> *uj, std::ve
     e += (int64_t)m.n_templates * m.nw;
     m.x0 = n.windows;
     n.windows += m.nw;
-    if (m.acorr) n.xi2 = true;
+    if (m.acorr) {
+      n.xi2 = true;
+      n.xi_kmax = std::max(n.xi_kmax, m.kcat);
+      n.xi_units += xi_unit_cap(m.nw, m.n_templates);
+    }
   }
   n.mix = it;
   n.entries = e;
@@ -615,7 +621,7 @@ void lloid::number_jobs(std::vector<FirJob> &fj, std::vector<UpJob> *uj, std::ve
 
 lloid_status lloid::launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dtab, const TabOffsets &to,
                                   const StageItems &n, bool with_snr, float phase_thr, float trig_thr,
-                                  hipEvent_t *ev) {
+                                  const XiWork &xw, hipEvent_t *ev) {
   hipStream_t st = ctx->stream;
   auto mark = [&](int stage, int end) -> hipError_t {
     return ev ? hipEventRecord(ev[2 * (stage - LLOID_STAGE_FIR) + end], st) : hipSuccess;
@@ -632,7 +638,11 @@ lloid_status lloid::launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dt
   HIP_TRY(mark(LLOID_STAGE_MIX, 1));
   HIP_TRY(mark(LLOID_STAGE_PHASE, 0));
   HIP_TRY(launch_peak_phase(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.entries, phase_thr, st));
-  if (n.xi2) HIP_TRY(launch_xi2(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.windows, trig_thr, st));
+  if (n.xi2) {
+    if (xw.cap < n.xi_units) return fail(LLOID_EINVAL, "signal-consistency unit list too small");
+    HIP_TRY(launch_xi2(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.windows, n.xi_kmax, trig_thr, xw, ctx->n_cu,
+                       st));
+  }
   HIP_TRY(mark(LLOID_STAGE_PHASE, 1));
   return LLOID_OK;
 }
@@ -734,6 +744,13 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
                              64 * (3 + kMaxHops)) +
            nb * sizeof(TrigJob) + 256;
   };
+  // signal-consistency units of the banks with lags over a chunk of wpc_ windows
+  auto xi_cap = [&](int64_t wpc_) -> int64_t {
+    int64_t c = 0;
+    for (int i = 0; i < nb; ++i)
+      if (banks[i]->acorr) c += xi_unit_cap(wpc_, banks[i]->n_templates);
+    return c;
+  };
   auto layout_bytes = [&](int64_t wpc_) -> size_t {
     const int64_t chunk_n_ = std::min<int64_t>(n, win.start(wpc_) + 1);
     size_t bytes = 0;
@@ -749,6 +766,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
       add(tab, 4);
       add(tab, 4);
       add(tab, 8);
+      if (banks[i]->acorr) add(tab, 8);
       const int64_t ops = chunk_n_ + 2 * operand_margin(banks[i]);
       add((size_t)ops * banks[i]->kcat, esz);
       for (const auto &sl : banks[i]->slices)
@@ -757,6 +775,8 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     }
     add((size_t)trig_blocks(total_rows * W) + 2, 8);
     add(1, 4);
+    add((size_t)xi_cap(wpc_), sizeof(XiUnit));
+    add(2, 4);
     add((size_t)std::max<int64_t>(dev_cap, 1), sizeof(lloid_trigger));
     if (host_snr) add((size_t)n * 2 * banks[0]->n_templates, 4);
     add(table_bytes(ceil_div(W, wpc_)), 1);
@@ -817,6 +837,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     bw[i].psi = cv.take<float>(tab);
     bw[i].pxi = cv.take<float>(tab);
     bw[i].pz = cv.take<float2>(tab);
+    if (banks[i]->acorr) bw[i].pkey = cv.take<int64_t>(tab);
     bw[i].ld_peak = W;
     bw[i].w_base = 0;
     const int64_t ops = chunk_n + 2 * operand_margin(banks[i]);
@@ -833,6 +854,10 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   int64_t *counts = cv.take<int64_t>((size_t)n_blk + 2);
   int64_t *total = counts + n_blk;
   int *bad = cv.take<int>(1);
+  XiWork xw;
+  xw.cap = xi_cap(wpc);
+  xw.units = cv.take<XiUnit>((size_t)xw.cap);
+  xw.counters = cv.take<int32_t>(2);
   lloid_trigger *dtrig = cv.take<lloid_trigger>((size_t)std::max<int64_t>(dev_cap, 1));
   float *dsnr = snr ? (host_snr ? cv.take<float>((size_t)n * 2 * banks[0]->n_templates) : snr) : nullptr;
   char *dtab = cv.take<char>(tab_bytes);
@@ -912,7 +937,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     }
   for (int64_t c = 0; c < n_chunks; ++c) {
     const lloid_status r2 = launch_stages(ctx, ct, dtab, chunks[c].to, chunks[c].items, snr != nullptr, phase_thr,
-                                          thr, prof ? &ctx->cev[(size_t)2 * kChunkStages * c] : nullptr);
+                                          thr, xw, prof ? &ctx->cev[(size_t)2 * kChunkStages * c] : nullptr);
     if (r2 != LLOID_OK) return r2;
   }
   HIP_TRY(mark(LLOID_STAGE_TRIGGER, 0));

@@ -89,9 +89,26 @@ struct MixJob {
   const float *acorr;         // [n_templates][2 acorr_half + 1] (re, im) autocorrelation, or NULL
   float *snr;            // optional [F][snr_ld][2], column n - snr_abs0
   int64_t ocat_abs0, n_end, w0, nw, win_p, win_q, ld_peak, w_base, snr_ld, snr_abs0, item0, e0;
-  int64_t x0;                 // first (job, window) item of this job in the signal-consistency launch
+  int64_t x0;                 // first (job, window) item of this job in the signal-consistency launches
+  int64_t ocat_end;           // absolute sample past the operand's last row
+  int64_t *xi_key;            // listing slab [ld_peak][n_templates] of trigger keys (banks with lags)
   float inv_scale;
   int rows, kcat, n_templates, n_rtiles, acorr_half;
+};
+
+// One unit of the signal-consistency tiles: triggers first .. first + n - 1
+// (n <= 64) of the listing of (job, window) item `item`.
+struct XiUnit {
+  int64_t item;
+  int32_t first, n;
+};
+
+// Device scratch of the signal-consistency launches: the unit list and two
+// counters (units listed, units taken).
+struct XiWork {
+  XiUnit *units = nullptr;
+  int64_t cap = 0;
+  int32_t *counters = nullptr;
 };
 
 // Trigger compaction over the peak table of one bank, windows [w_base, w_base + nw):
@@ -178,7 +195,10 @@ hipError_t launch_peak_phase(lloid_dtype t, const MixJob *jobs, int n_jobs, int6
                              hipStream_t s);
 // Signal-consistency value at the peaks with |z| >= thr of the jobs that carry
 // autocorrelations; one workgroup per (job, window).
-hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_windows, float thr, hipStream_t s);
+// n_windows: (job, window) items; kmax: largest kcat of a job with lags;
+// xw.cap >= sum over those jobs of nw * ceil(n_templates / 64)
+hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_windows, int kmax, float thr,
+                      const XiWork &xw, int n_cu, hipStream_t s);
 // Trigger compaction: counts, offsets and records (job-major, template, window);
 // counts holds trig_blocks(n_elems) slots.
 hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems, float thr, int64_t *counts,
@@ -251,6 +271,7 @@ struct BankBufs {
                                          // interpolation hop's output except the last
   float *psnr = nullptr, *pphase = nullptr, *pdt = nullptr, *psi = nullptr, *pxi = nullptr;
   float2 *pz = nullptr;            // z at each peak, for the signal-consistency value
+  int64_t *pkey = nullptr;         // trigger listing slab [ld_peak][F] (banks with lags)
   int64_t *pn = nullptr;
   int64_t ld_peak = 0, w_base = 0; // peak tables [F][ld_peak], column w - w_base
 };
@@ -268,6 +289,8 @@ struct StageItems {
   int64_t fir = 0, mix = 0, entries = 0;
   int64_t windows = 0;             // (job, window) pairs: workgroups of the signal-consistency launch
   bool xi2 = false;                // some mixing job carries autocorrelations
+  int xi_kmax = 0;                 // largest kcat of such a job
+  int64_t xi_units = 0;            // signal-consistency units those jobs can list at most
   int64_t up[kMaxHops] = {};       // items of each interpolation hop
 };
 
@@ -300,7 +323,10 @@ void number_jobs(std::vector<FirJob> &fj, std::vector<UpJob> *uj, std::vector<Mi
 // NULL, or 8 events bracketing those four stages.
 constexpr int kChunkStages = 4;    // LLOID_STAGE_FIR .. LLOID_STAGE_PHASE
 lloid_status launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dtab, const TabOffsets &to,
-                           const StageItems &n, bool with_snr, float phase_thr, float trig_thr, hipEvent_t *ev);
+                           const StageItems &n, bool with_snr, float phase_thr, float trig_thr, const XiWork &xw,
+                           hipEvent_t *ev);
+// Signal-consistency units that nw windows of a bank of F templates can list at most.
+inline int64_t xi_unit_cap(int64_t nw, int F) { return nw * ceil_div(F, 64); }
 
 // Samples of the mixing operand beyond each end of a chunk's outputs: one for
 // the sub-sample refinement, K for the signal-consistency lags.

@@ -1007,19 +1007,105 @@ __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ j
 // Signal-consistency value at each trigger peak (Sec. II.A computes phase and
 // xi^2 for every trigger):
 //   xi2 = sum_k |z[n* + k] - z[n*] R[k]|^2 / sum_k (2 - 2 |R[k]|^2)
-// over the lags k = -K..K with 0 <= n* + k < n_end.  One workgroup per (job,
-// window) lists the window's triggers in LDS and sorts them by peak sample;
-// each wave takes groups of 16 consecutive triggers and recomputes their z
-// (32 mixing rows: cos and sin of 16 templates) over the samples their lags
-// reach, 32 samples at a time, as MFMA tiles Z = M_rows * Ocat^T (a chunk's
-// operand holds K extra samples on each side).  The tile's epilogue adds
-// each lane's lags to its eight triggers' sums; z[n*] comes from the phase
-// kernel.  Sorting keeps a group's lags close together: the samples a group
-// covers are about its spread of peaks plus 2K.
+// over the lags k = -K..K with 0 <= n* + k < n_end.  z is recomputed at the
+// lags as MFMA tiles Z = M_rows * Ocat^T over groups of 16 triggers (32
+// mixing rows: cos and sin of 16 templates) and 32 samples; the tile's
+// epilogue adds each lane's lags to its eight triggers' sums, and z[n*] comes
+// from the phase kernel.  Triggers are listed per window and sorted by peak
+// sample, so that a group's lags lie close together: the samples a group
+// covers are about its spread of peaks plus 2K (a chunk's operand holds K
+// extra samples on each side).
+//
+// Two forms.  16-bit operands with kcat <= 512 run two launches:
+// k_xi2_list (one workgroup per (job, window)) stores the sorted keys and
+// appends one unit per 64 of them to a list, and k_xi2_tiles (persistent
+// workgroups taking units from that list) keeps each wave's A fragments in
+// registers for the whole unit and stages every operand tile once in LDS for
+// its four waves, with coalesced direct-to-LDS loads.  Otherwise k_xi2 does
+// both in one workgroup per (job, window), reading fragments straight from
+// memory.
 
 constexpr int kXiThreads = 256;
 constexpr int kXiList = 1024;   // triggers listed per pass over a window's templates
 constexpr int kXiGroup = 16;    // triggers per MFMA row tile
+
+// (job, window) item `item` of the signal-consistency launches: the last job
+// with x0 <= item.
+__device__ __forceinline__ int find_xi_job(const MixJob *__restrict__ jobs, int n_jobs, int64_t item) {
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].x0 <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One listing pass of window w (start ws) over templates [i0, F): the keys
+// (n* - ws) << 32 | i of at most kXiList triggers in l_key, sorted by peak
+// sample (template order among equal samples).  Returns how many; *i_next is
+// the first template left for the next pass (F when none).  Every thread of
+// the workgroup calls it.
+__device__ int xi_list_pass(const MixJob &jb, int64_t w, int64_t ws, float thr, int i0, int64_t *l_key,
+                            int *l_count, int *i_next_out) {
+  const int F = jb.n_templates, lane = threadIdx.x & 63;
+  if (threadIdx.x == 0) *l_count = 0;
+  __syncthreads();
+  int i_next = F;
+  for (int ib = i0; ib < F; ib += kXiThreads) {
+    const int i = ib + (int)threadIdx.x;
+    const int64_t o = (int64_t)i * jb.ld_peak + (w - jb.w_base);
+    const bool f = i < F && jb.peak_snr[o] >= thr;
+    const uint64_t m = __ballot(f);
+    int base = 0;
+    if (lane == 0 && m) base = atomicAdd(l_count, (int)__popcll(m));
+    base = __shfl(base, 0);
+    if (f) {
+      const int at = base + (int)__popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull));
+      if (at < kXiList) l_key[at] = ((jb.peak_n[o] - ws) << 32) | (int64_t)i;
+    }
+    __syncthreads();
+    const int cnt = *l_count;
+    __syncthreads();
+    if (cnt > kXiList) {   // full: this block's triggers wait for the next pass
+      i_next = ib;
+      break;
+    }
+  }
+  int n_list = min(*l_count, kXiList);
+  if (i_next < F) {
+    // keep the triggers of templates below i_next (every one of them fits)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int k = 0;
+      for (int t = 0; t < n_list; ++t)
+        if ((int)(l_key[t] & 0xffffffff) < i_next) l_key[k++] = l_key[t];
+      *l_count = k;
+    }
+    __syncthreads();
+    n_list = *l_count;
+  }
+  // bitonic sort of the keys by peak sample (padding sorts last)
+  int np2 = 1;
+  while (np2 < n_list) np2 <<= 1;
+  for (int t = n_list + (int)threadIdx.x; t < np2; t += kXiThreads) l_key[t] = INT64_MAX;
+  __syncthreads();
+  for (int size = 2; size <= np2; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < np2 / 2; t += kXiThreads) {
+        const int a = 2 * stride * (t / stride) + (t % stride), b2 = a + stride;
+        const bool up = (a & size) == 0;
+        const int64_t x = l_key[a], y = l_key[b2];
+        if ((x > y) == up) {
+          l_key[a] = y;
+          l_key[b2] = x;
+        }
+      }
+      __syncthreads();
+    }
+  *i_next_out = i_next;
+  return n_list;
+}
 
 template <typename T>
 __global__ __launch_bounds__(kXiThreads) void k_xi2(const MixJob *__restrict__ jobs, int n_jobs, float thr) {
@@ -1027,15 +1113,9 @@ __global__ __launch_bounds__(kXiThreads) void k_xi2(const MixJob *__restrict__ j
   __shared__ int64_t l_key[kXiList];   // (n* - window start) << 32 | template
   __shared__ int l_count;
 
-  // job and window of this workgroup: the last job with x0 <= blockIdx.x
+  // job and window of this workgroup
   const int64_t item = blockIdx.x;
-  int lo = 0, hi = n_jobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].x0 <= item) lo = mid;
-    else hi = mid - 1;
-  }
-  const MixJob &jb = jobs[lo];
+  const MixJob &jb = jobs[find_xi_job(jobs, n_jobs, item)];
   const int64_t wl = item - jb.x0;
   if (!jb.acorr || wl >= jb.nw) return;   // uniform over the workgroup
   const int64_t w = jb.w0 + wl;
@@ -1049,61 +1129,8 @@ __global__ __launch_bounds__(kXiThreads) void k_xi2(const MixJob *__restrict__ j
   const int nks = kcat / O::KS;
 
   for (int i0 = 0; i0 < F;) {
-    // ---- list the triggers among templates [i0, ...), at most kXiList
-    if (threadIdx.x == 0) l_count = 0;
-    __syncthreads();
-    int i_next = F;
-    for (int ib = i0; ib < F; ib += kXiThreads) {
-      const int i = ib + (int)threadIdx.x;
-      const int64_t o = (int64_t)i * jb.ld_peak + (w - jb.w_base);
-      const bool f = i < F && jb.peak_snr[o] >= thr;
-      const uint64_t m = __ballot(f);
-      int base = 0;
-      if (lane == 0 && m) base = atomicAdd(&l_count, (int)__popcll(m));
-      base = __shfl(base, 0);
-      if (f) {
-        const int at = base + (int)__popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull));
-        if (at < kXiList) l_key[at] = ((jb.peak_n[o] - ws) << 32) | (int64_t)i;
-      }
-      __syncthreads();
-      const int cnt = l_count;
-      __syncthreads();
-      if (cnt > kXiList) {   // full: this block's triggers wait for the next pass
-        i_next = ib;
-        break;
-      }
-    }
-    int n_list = min(l_count, kXiList);
-    if (i_next < F) {
-      // keep the triggers of templates below i_next (every one of them fits)
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        int k = 0;
-        for (int t = 0; t < n_list; ++t)
-          if ((int)(l_key[t] & 0xffffffff) < i_next) l_key[k++] = l_key[t];
-        l_count = k;
-      }
-      __syncthreads();
-      n_list = l_count;
-    }
-    // ---- bitonic sort of the keys by peak sample (padding sorts last)
-    int np2 = 1;
-    while (np2 < n_list) np2 <<= 1;
-    for (int t = n_list + (int)threadIdx.x; t < np2; t += kXiThreads) l_key[t] = INT64_MAX;
-    __syncthreads();
-    for (int size = 2; size <= np2; size <<= 1)
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        for (int t = threadIdx.x; t < np2 / 2; t += kXiThreads) {
-          const int a = 2 * stride * (t / stride) + (t % stride), b2 = a + stride;
-          const bool up = (a & size) == 0;
-          const int64_t x = l_key[a], y = l_key[b2];
-          if ((x > y) == up) {
-            l_key[a] = y;
-            l_key[b2] = x;
-          }
-        }
-        __syncthreads();
-      }
+    int i_next;
+    const int n_list = xi_list_pass(jb, w, ws, thr, i0, l_key, &l_count, &i_next);
 
     // ---- groups of kXiGroup triggers, one wave each
     const int n_groups = (n_list + kXiGroup - 1) / kXiGroup;
@@ -1199,6 +1226,246 @@ __global__ __launch_bounds__(kXiThreads) void k_xi2(const MixJob *__restrict__ j
     }
     __syncthreads();
     i0 = i_next;
+  }
+}
+
+// Listing launch of the two-launch form: keys of window w go to the job's
+// listing slab at xi_key[(w - w_base) F + t], t = 0..count - 1 (one sorted
+// run per listing pass), and units (item, 64 j, min(64, count - 64 j)) to
+// units[counters[0]++ ...].  counters[0] starts at zero.
+__global__ __launch_bounds__(kXiThreads) void k_xi2_list(const MixJob *__restrict__ jobs, int n_jobs, float thr,
+                                                         XiUnit *__restrict__ units, int64_t cap,
+                                                         int32_t *__restrict__ counters) {
+  __shared__ int64_t l_key[kXiList];
+  __shared__ int l_count, l_u0;
+  const int64_t item = blockIdx.x;
+  const MixJob &jb = jobs[find_xi_job(jobs, n_jobs, item)];
+  const int64_t wl = item - jb.x0;
+  if (!jb.acorr || wl >= jb.nw) return;   // uniform over the workgroup
+  const int64_t w = jb.w0 + wl;
+  const int64_t ws = (w * jb.win_p) / jb.win_q;
+  const int F = jb.n_templates;
+  int64_t *slab = jb.xi_key + (w - jb.w_base) * (int64_t)F;
+  int count = 0;
+  for (int i0 = 0; i0 < F;) {
+    int i_next;
+    const int n_list = xi_list_pass(jb, w, ws, thr, i0, l_key, &l_count, &i_next);
+    for (int t = threadIdx.x; t < n_list; t += kXiThreads) slab[count + t] = l_key[t];
+    count += n_list;
+    __syncthreads();   // the next pass rewrites l_key
+    i0 = i_next;
+  }
+  const int nu = (count + 63) / 64;
+  if (nu == 0) return;
+  if (threadIdx.x == 0) l_u0 = atomicAdd(&counters[0], nu);
+  __syncthreads();
+  for (int j = threadIdx.x; j < nu; j += kXiThreads) {
+    const int64_t u = (int64_t)l_u0 + j;
+    if (u < cap) units[u] = XiUnit{item, 64 * j, min(64, count - 64 * j)};
+  }
+}
+
+// Staged operand tile: 32 rows (samples) of kcat 16-bit values, row pitch P =
+// kcat / 8 + 1 16-byte chunks (odd, so 16 consecutive rows start on distinct
+// banks), filled by whole 64-chunk loads: at most 33 of them for kcat = 512.
+constexpr int kXiTileChunks = 33 * 64;
+
+// Tile launch of the two-launch form.  Workgroups take units from
+// counters[1] until the list of counters[0] units is done.  Wave g of a unit
+// owns its triggers 16 g .. 16 g + 15: the A fragments of every k-step stay in
+// registers (NKS >= kcat / 16 k-steps; the ones past kcat are zeros) and its
+// lag range [ga0, ga1) decides which tiles it multiplies.  The workgroup walks
+// the union [ba0, ba1) of its waves' ranges in 32-sample tiles; each tile is
+// loaded once into LDS (double-buffered, the next tile's loads in flight
+// while the current one is multiplied).
+template <typename T, int NKS>
+__global__ __launch_bounds__(kXiThreads, 2) void k_xi2_tiles(const MixJob *__restrict__ jobs, int n_jobs,
+                                                             const XiUnit *__restrict__ units, int64_t cap,
+                                                             int32_t *__restrict__ counters) {
+  static_assert(sizeof(T) == 2, "16-bit operands only");
+  static_assert(NKS % 4 == 0 && NKS <= 32, "k-steps in blocks of 4, kcat <= 512");
+  typedef typename Op<T>::vec vec;
+  __shared__ __attribute__((aligned(1024))) char Bt[2][kXiTileChunks * 16];
+  __shared__ int64_t s_key[64];
+  __shared__ float2 s_z[64];
+  __shared__ int s_lo[64], s_ab[64];   // lag window start (relative to ws), autocorrelation row
+  __shared__ int s_u;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int fr = lane & 31, fh = lane >> 5;
+  // chunks past a row's kcat values that no load of a tile writes are read
+  // (against zero A fragments) by the padding k-steps: keep them finite
+  for (int c = threadIdx.x; c < 2 * kXiTileChunks; c += kXiThreads) ((uint4 *)&Bt[0][0])[c] = uint4{0, 0, 0, 0};
+  const int64_t n_units = min((int64_t)counters[0], cap);
+  for (;;) {
+    if (threadIdx.x == 0) s_u = atomicAdd(&counters[1], 1);
+    __syncthreads();
+    const int u = __builtin_amdgcn_readfirstlane(s_u);   // the same in every lane: keep it scalar
+    if (u >= n_units) break;                              // uniform over the workgroup
+    const XiUnit un = units[u];
+    const MixJob &jb = jobs[find_xi_job(jobs, n_jobs, un.item)];
+    const int64_t w = jb.w0 + (un.item - jb.x0);
+    const int64_t ws = (w * jb.win_p) / jb.win_q;
+    const int64_t pcol = w - jb.w_base;
+    const int K = jb.acorr_half, kcat = jb.kcat, nks = kcat / 16, nt_u = un.n;
+    if (threadIdx.x < 64) {
+      int64_t key = -1;
+      float2 z = make_float2(0.f, 0.f);
+      int lo = INT_MIN / 2, ab = 0;   // a missing trigger reaches no lag
+      if (lane < nt_u) {
+        key = jb.xi_key[pcol * jb.n_templates + un.first + lane];
+        z = jb.peak_z[(key & 0xffffffff) * jb.ld_peak + pcol];
+        lo = (int)(key >> 32) - K;
+        ab = (int)(key & 0xffffffff) * (2 * K + 1);
+      }
+      s_key[lane] = key;
+      s_z[lane] = z;
+      s_lo[lane] = lo;
+      s_ab[lane] = ab;
+    }
+    __syncthreads();
+
+    // peak samples (relative to ws): range of this wave's group, then of the unit
+    const int nr_l = (int)(s_key[lane] >> 32);
+    int mn = lane < nt_u ? nr_l : INT_MAX, mx = lane < nt_u ? nr_l : INT_MIN;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      mn = min(mn, __shfl_xor(mn, off));
+      mx = max(mx, __shfl_xor(mx, off));
+    }
+    const int gmn = __builtin_amdgcn_readfirstlane(__shfl(mn, 16 * wave));
+    const int gmx = __builtin_amdgcn_readfirstlane(__shfl(mx, 16 * wave));
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1) {
+      mn = min(mn, __shfl_xor(mn, off));
+      mx = max(mx, __shfl_xor(mx, off));
+    }
+    mn = __builtin_amdgcn_readfirstlane(mn);
+    mx = __builtin_amdgcn_readfirstlane(mx);
+    const int64_t ba0 = max<int64_t>(0, ws + mn - K), ba1 = min<int64_t>(jb.n_end, ws + mx + K + 1);
+    const bool has = 16 * wave < nt_u;
+    const int64_t ga0 = has ? max<int64_t>(0, ws + gmn - K) : INT64_MAX;
+    const int64_t ga1 = has ? min<int64_t>(jb.n_end, ws + gmx + K + 1) : INT64_MIN;
+
+    // A fragments: lane row fr is cos (even) or sin (odd) of trigger 16 g + fr / 2
+    // (a missing trigger repeats the unit's first; its rows are never used)
+    vec af[NKS];
+    {
+      const int tr = 16 * wave + (fr >> 1);
+      const int64_t i = s_key[tr < nt_u ? tr : 0] & 0xffffffff;
+      const T *arow = (const T *)jb.mix + (2 * i + (lane & 1)) * (int64_t)kcat + fh * 8;
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        const vec v = *(const vec *)(arow + min(ks, nks - 1) * 16);
+        af[ks] = ks < nks ? v : vec{};
+      }
+    }
+    float num[8], den[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) num[p] = den[p] = 0.f;
+
+    // tile loads: this wave's load i fills chunks (4 i + wave) 64 + lane of
+    // the tile, chunk c = row c / P, position c % P (the pad position reads
+    // the row's first chunk, rows past 31 read row 31).  The resource ends at
+    // the unit's last sample: rows past it load zeros.
+    const int cpr = kcat / 8, P = cpr + 1, nblk = (32 * P + 63) / 64;
+    const int rowbytes = kcat * 2;
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(jb.ocat, (ba1 - jb.ocat_abs0) * (int64_t)rowbytes);
+    const int dr = 256 / P, dq = 256 - dr * P;
+    const int base0 = (int)(ba0 - jb.ocat_abs0) * rowbytes;
+    auto issue = [&](int j) {
+      // the chunk positions are recomputed per tile (a few ALU operations per
+      // load) rather than held in registers across the loop
+      int c0 = wave * 64 + lane;
+      asm volatile("" : "+v"(c0));
+      int r = c0 / P, q = c0 - r * P;
+      const int tb = base0 + 32 * j * rowbytes;
+      char *buf = Bt[j & 1];
+#pragma unroll
+      for (int i = 0; i < (kXiTileChunks + 255) / 256; ++i) {
+        const int blk = 4 * i + wave;
+        if (blk < nblk) {
+          const int vo = tb + min(r, 31) * rowbytes + (q < cpr ? q : 0) * 16;
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void *)(buf + blk * 1024), 16, vo, 0, 0, 0);
+        }
+        q += dq;
+        r += dr;
+        if (q >= P) {
+          q -= P;
+          ++r;
+        }
+      }
+    };
+    const int ntl = (int)((ba1 - ba0 + 31) / 32);
+    const float2 *acorr = (const float2 *)jb.acorr;
+    const float sc = jb.inv_scale;
+    const int nrel0 = (int)(ba0 - ws) + fr, nrel_end = (int)(ba1 - ws);
+    issue(0);
+    for (int j = 0; j < ntl; ++j) {
+      __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's loads of tile j
+      __syncthreads();                      // every wave's; tile j - 1's buffer is free
+      if (j + 1 < ntl) issue(j + 1);
+      const int64_t s0 = ba0 + 32 * (int64_t)j;
+      if (s0 < ga1 && s0 + 32 > ga0) {   // uniform over the wave
+        const char *bb = Bt[j & 1] + (fr * P + fh) * 16;
+        f32x16 acc, acc2;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] = acc2[e] = 0.f;
+#pragma unroll
+        for (int kb = 0; kb < NKS; kb += 4) {
+          vec bf[4];
+#pragma unroll
+          for (int u2 = 0; u2 < 4; ++u2) bf[u2] = *(const vec *)(bb + (kb + u2) * 32);
+          __builtin_amdgcn_sched_barrier(0);   // the block's reads ahead of its MFMAs
+#pragma unroll
+          for (int u2 = 0; u2 < 4; u2 += 2) {
+            acc = Op<T>::mfma(af[kb + u2], bf[u2], acc);
+            acc2 = Op<T>::mfma(af[kb + u2 + 1], bf[u2 + 1], acc2);
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] += acc2[e];
+        const int nrel = nrel0 + 32 * j;   // this lane's sample, relative to ws
+        // the lane's eight triggers (accumulator rows 8 (e/4) + 4 fh + e%4):
+        // all eight autocorrelation reads in flight at once (a lag outside
+        // the window reads entry 0 and adds nothing)
+        float2 r[8];
+        bool in[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          const int t = 16 * wave + 4 * (p >> 1) + 2 * fh + (p & 1);
+          const int d = nrel - s_lo[t];
+          in[p] = nrel < nrel_end && (unsigned)d <= (unsigned)(2 * K);
+          r[p] = acorr[in[p] ? s_ab[t] + d : 0];
+        }
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          const float2 z = s_z[16 * wave + 4 * (p >> 1) + 2 * fh + (p & 1)];
+          const float dre = acc[2 * p] * sc - (z.x * r[p].x - z.y * r[p].y);
+          const float dim = acc[2 * p + 1] * sc - (z.x * r[p].y + z.y * r[p].x);
+          if (in[p]) {
+            num[p] += dre * dre + dim * dim;
+            den[p] += 2.f - 2.f * (r[p].x * r[p].x + r[p].y * r[p].y);
+          }
+        }
+      }
+    }
+    // sum each trigger's terms over the 32 lanes (samples) of its half-wave
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+      for (int off = 1; off < 32; off <<= 1) {
+        num[p] += __shfl_xor(num[p], off);
+        den[p] += __shfl_xor(den[p], off);
+      }
+    if (fr == 0) {
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const int t = 16 * wave + 4 * (p >> 1) + 2 * fh + (p & 1);
+        if (t < nt_u)
+          jb.peak_xi[(s_key[t] & 0xffffffff) * jb.ld_peak + pcol] = den[p] > 0.f ? num[p] / den[p] : 0.f;
+      }
+    }
+    __syncthreads();   // the unit's keys and tiles are free for the next unit
   }
 }
 
@@ -1712,9 +1979,27 @@ hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems,
   return hipGetLastError();
 }
 
-hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_windows, float thr, hipStream_t s) {
+hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_windows, int kmax, float thr,
+                      const XiWork &xw, int n_cu, hipStream_t s) {
   if (n_windows <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)n_windows;   // one workgroup per (job, window)
+  const int nks = kmax / 16;
+  if (t != LLOID_F32 && nks <= 32 && xw.cap > 0) {
+    hipError_t e = launch_fill_u8(xw.counters, 2 * sizeof(int32_t), s);
+    if (e != hipSuccess) return e;
+    k_xi2_list<<<blocks, kXiThreads, 0, s>>>(jobs, n_jobs, thr, xw.units, xw.cap, xw.counters);
+    // persistent: two workgroups per CU take units until the list is done
+    const unsigned tb = (unsigned)std::min<int64_t>(xw.cap, 2 * (int64_t)std::max(n_cu, 1));
+    const bool k16 = nks <= 16;
+    if (t == LLOID_F16) {
+      if (k16) k_xi2_tiles<_Float16, 16><<<tb, kXiThreads, 0, s>>>(jobs, n_jobs, xw.units, xw.cap, xw.counters);
+      else k_xi2_tiles<_Float16, 32><<<tb, kXiThreads, 0, s>>>(jobs, n_jobs, xw.units, xw.cap, xw.counters);
+    } else {
+      if (k16) k_xi2_tiles<__bf16, 16><<<tb, kXiThreads, 0, s>>>(jobs, n_jobs, xw.units, xw.cap, xw.counters);
+      else k_xi2_tiles<__bf16, 32><<<tb, kXiThreads, 0, s>>>(jobs, n_jobs, xw.units, xw.cap, xw.counters);
+    }
+    return hipGetLastError();
+  }
   switch (t) {
     case LLOID_F16: k_xi2<_Float16><<<blocks, kXiThreads, 0, s>>>(jobs, n_jobs, thr); break;
     case LLOID_BF16: k_xi2<__bf16><<<blocks, kXiThreads, 0, s>>>(jobs, n_jobs, thr); break;

@@ -332,7 +332,7 @@ lloid_status enqueue_tick(lloid_stream *s, int64_t wa, int64_t wb, Clock::time_p
   // stream), then kTickRing areas of device tables, one per ring entry
   size_t bytes = 0;
   auto add = [&](size_t cnt, size_t sz) { bytes = (size_t)round_up((int64_t)bytes, 256) + cnt * sz; };
-  int64_t rows = 0;
+  int64_t rows = 0, xi_cap = 0;
   size_t n_fir = 0, n_up = 0;
   for (const lloid_bank *b : bank_of) {
     for (int d = 0; d < s->n_det; ++d) {
@@ -346,10 +346,16 @@ lloid_status enqueue_tick(lloid_stream *s, int64_t wa, int64_t wb, Clock::time_p
       for (int k = 0; k < 5; ++k) add((size_t)b->n_templates * nw, 4);
       add((size_t)b->n_templates * nw, 8);
       add((size_t)b->n_templates * nw, 8);
+      if (b->acorr) {
+        add((size_t)b->n_templates * nw, 8);
+        xi_cap += xi_unit_cap(nw, b->n_templates);
+      }
     }
     rows += (int64_t)b->n_templates * s->n_det;
   }
   add((size_t)trig_blocks(rows * nw) + 2, 8);
+  add((size_t)xi_cap, sizeof(XiUnit));
+  add(2, 4);
   const size_t tab_bytes = n_fir * sizeof(FirJob) + n_up * sizeof(UpJob) +
                            bank_of.size() * s->n_det * (sizeof(MixJob) + sizeof(TrigJob)) + 64 * (4 + kMaxHops);
   const size_t common = (size_t)round_up((int64_t)bytes, 256);
@@ -403,6 +409,7 @@ lloid_status enqueue_tick(lloid_stream *s, int64_t wa, int64_t wb, Clock::time_p
       bb.pxi = cv.take<float>((size_t)b->n_templates * nw);
       bb.pn = cv.take<int64_t>((size_t)b->n_templates * nw);
       bb.pz = cv.take<float2>((size_t)b->n_templates * nw);
+      if (b->acorr) bb.pkey = cv.take<int64_t>((size_t)b->n_templates * nw);
       bb.ld_peak = nw;
       bb.w_base = wa;
       std::vector<LevelView> lv(s->n_levels);
@@ -418,6 +425,10 @@ lloid_status enqueue_tick(lloid_stream *s, int64_t wa, int64_t wb, Clock::time_p
   const int64_t n_blk = trig_blocks(rows * nw);
   int64_t *counts = cv.take<int64_t>((size_t)n_blk + 2);
   int64_t *total = counts + n_blk;
+  XiWork xw;
+  xw.cap = xi_cap;
+  xw.units = cv.take<XiUnit>((size_t)xi_cap);
+  xw.counters = cv.take<int32_t>(2);
   char *dtab = (char *)s->ws.base + tab_base + (size_t)ti * s->tab_area;
   StageItems items;
   number_jobs(fj, uj, mj, items);
@@ -444,7 +455,7 @@ lloid_status enqueue_tick(lloid_stream *s, int64_t wa, int64_t wb, Clock::time_p
   // pinned host memory, the count into pinned host memory
   auto work = [&]() -> lloid_status {
     HIP_TRY(hipMemcpyAsync(dtab, htab, off, hipMemcpyHostToDevice, st));
-    const lloid_status r = launch_stages(ctx, s->ct, dtab, to, items, false, s->thr, s->thr, nullptr);
+    const lloid_status r = launch_stages(ctx, s->ct, dtab, to, items, false, s->thr, s->thr, xw, nullptr);
     if (r != LLOID_OK) return r;
     HIP_TRY(launch_trigger_jobs((const TrigJob *)(dtab + trig_off), (int)tj.size(), rows * nw, s->thr, counts, total,
                                 cap, tk.htrig, st));
@@ -460,6 +471,8 @@ lloid_status enqueue_tick(lloid_stream *s, int64_t wa, int64_t wb, Clock::time_p
                                 (int64_t)(uintptr_t)tk.htrig, items.fir, items.mix, items.entries, (int64_t)to.fir,
                                 (int64_t)to.mix, to.n_fir, to.n_mix};
     key.push_back(items.xi2 ? 1 : 0);
+    key.push_back((int64_t)(uintptr_t)xw.units);
+    key.push_back(xw.cap);
     key.push_back(ctx->fir_variant * 16 + ctx->mix_variant);
     key.push_back(items.windows);
     for (int h = 0; h < kMaxHops; ++h) {

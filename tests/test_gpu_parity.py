@@ -306,10 +306,13 @@ def test_xi2_matches_oracle(compute):
     log(f"  {t.shape[0]} triggers, {n_cmp} compared, max |d xi2| {worst:.2e}")
 
 
-def test_xi2_more_triggers_than_one_list_pass():
+@pytest.mark.parametrize("compute", ["f16", "f32"])
+def test_xi2_more_triggers_than_one_list_pass(compute):
     """A window with more triggers than the kernel lists at once (threshold 0:
     every one of 1500 templates triggers in every window) is handled in
-    several passes over the templates; every value still matches the oracle."""
+    several passes over the templates (16-bit: the listing stores the passes'
+    sorted runs one after the other and the tile launch takes units of 64 that
+    can straddle two runs); every value still matches the oracle."""
     from paper_2410_16416_amd import lloid
     from workloads import SliceSpec, bank_autocorrelation
     rng = np.random.default_rng(71)
@@ -319,7 +322,8 @@ def test_xi2_more_triggers_than_one_list_pass():
     bank.autocorr = r
     x = rng.standard_normal(3 * 1024 + 77)
     n = x.shape[0]
-    h = lloid.bank_from_svd(ctx(), bank, "f32")
+    log(f"[xi2 passes] compute={compute}")
+    h = lloid.bank_from_svd(ctx(), bank, compute)
     try:
         t = lloid.lloid_filter(h, 0, x, window=(1, 1), threshold=0.0).triggers
     finally:
@@ -338,25 +342,33 @@ def test_xi2_more_triggers_than_one_list_pass():
         ok = (s_ + lag >= 0) & (s_ + lag < n)
         d = z[i, (s_ + lag)[ok]] - z[i, s_] * r[i, ok]
         den = np.sum(2.0 - 2.0 * np.abs(r[i, ok]) ** 2)
-        eps = EPS_ABS["f32"]     # the bound of test_xi2_matches_oracle
+        eps = EPS_ABS[compute]   # the bound of test_xi2_matches_oracle
         tol = (4 * eps * np.sum(np.abs(d)) + 4 * eps ** 2 * ok.sum()) / den + 1e-5 * want
         assert abs(float(rec["xi2"]) - want) <= tol, (i, w, float(rec["xi2"]), want, tol)
         worst = max(worst, abs(float(rec["xi2"]) - want))
         n_cmp += 1
-    log(f"[xi2 passes] {t.shape[0]} triggers, {n_cmp} compared, max |d xi2| {worst:.2e}")
+    log(f"  {t.shape[0]} triggers, {n_cmp} compared, max |d xi2| {worst:.2e}")
     assert n_cmp > 0.95 * t.shape[0]
 
 
-@pytest.mark.parametrize("compute", ["f16", "f32"])
-def test_xi2_long_concatenated_basis(compute):
-    """A bank whose concatenated basis takes 18 (FP16) or 144 (FP32) k-steps:
-    the signal-consistency kernel then runs its k-steps in blocks of 10 with a
-    partial last block; every trigger's value matches the oracle (threshold 0:
-    every template triggers in every window)."""
+LONG_BASES = {288: [(1024, 0, 160, 128), (256, 160, 96, 96), (64, 544, 80, 64)],
+              544: [(1024, 0, 288, 256), (256, 288, 200, 192), (64, 1088, 100, 96)]}
+
+
+@pytest.mark.parametrize("compute,kcat", [("f16", 288), ("f32", 288), ("f16", 544), ("bf16", 544)])
+def test_xi2_long_concatenated_basis(compute, kcat):
+    """Banks with long concatenated bases (threshold 0: every template
+    triggers in every window), every trigger's value against the oracle.
+    kcat 288: 18 16-bit k-steps run in the tile launch's 32-step form (k-steps
+    18..31 multiply zeros); FP32 takes 144 k-steps in the one-launch kernel's
+    blocks of 10 with a partial last block.  kcat 544: 34 16-bit k-steps, more
+    than the tile launch holds in registers, so 16-bit operands take the
+    one-launch kernel too."""
     from paper_2410_16416_amd import lloid
     from workloads import SliceSpec, bank_autocorrelation
     rng = np.random.default_rng(73)
-    specs = [SliceSpec(1024, 0, 160, 128), SliceSpec(256, 160, 96, 96), SliceSpec(64, 544, 80, 64)]
+    log(f"[xi2 long K] compute={compute} kcat={kcat}")
+    specs = [SliceSpec(*sp) for sp in LONG_BASES[kcat]]
     bank = configs.random_basis_bank(200, specs, 1024, rng)
     half = 24
     r = bank_autocorrelation(bank, half)
@@ -365,7 +377,7 @@ def test_xi2_long_concatenated_basis(compute):
     n = x.shape[0]
     h = lloid.bank_from_svd(ctx(), bank, compute)
     try:
-        assert lloid.lloid_bank_query(h).concat_k == 288
+        assert lloid.lloid_bank_query(h).concat_k == kcat
         t = lloid.lloid_filter(h, 0, x, window=(1, 1), threshold=0.0).triggers
     finally:
         lloid.lloid_bank_destroy(h)
@@ -388,7 +400,7 @@ def test_xi2_long_concatenated_basis(compute):
         assert abs(float(rec["xi2"]) - want) <= tol, (i, w, float(rec["xi2"]), want, tol)
         worst = max(worst, abs(float(rec["xi2"]) - want))
         n_cmp += 1
-    log(f"[xi2 long K] {compute}: {t.shape[0]} triggers, {n_cmp} compared, max |d xi2| {worst:.2e}")
+    log(f"  {t.shape[0]} triggers, {n_cmp} compared, max |d xi2| {worst:.2e}")
     assert n_cmp > 0.9 * t.shape[0]
 
 
