@@ -1267,8 +1267,9 @@ __global__ __launch_bounds__(kXiThreads) void k_xi2_list(const MixJob *__restric
 
 // Staged operand tile: 32 rows (samples) of kcat 16-bit values, row pitch P =
 // kcat / 8 + 1 16-byte chunks (odd, so 16 consecutive rows start on distinct
-// banks), filled by whole 64-chunk loads: at most 33 of them for kcat = 512.
-constexpr int kXiTileChunks = 33 * 64;
+// banks): at most 33 loads of 64 chunks for kcat = 512.
+constexpr int kXiTileBlocks = 33;
+constexpr int kXiLoads = 9;   // loads per wave and tile: 4 waves x 9 >= kXiTileBlocks
 
 // Tile launch of the two-launch form.  Workgroups take units from
 // counters[1] until the list of counters[0] units is done.  Wave g of a unit
@@ -1276,16 +1277,22 @@ constexpr int kXiTileChunks = 33 * 64;
 // registers (NKS >= kcat / 16 k-steps; the ones past kcat are zeros) and its
 // lag range [ga0, ga1) decides which tiles it multiplies.  The workgroup walks
 // the union [ba0, ba1) of its waves' ranges in 32-sample tiles; each tile is
-// loaded once into LDS (double-buffered, the next tile's loads in flight
-// while the current one is multiplied).
+// loaded once into LDS, double-buffered.  Every wave issues exactly kXiLoads
+// loads per tile (the ones past the tile land in a scratch block) and always
+// issues the next tile (past the range: zeros), and the tile's
+// autocorrelation reads go out before those loads: loads complete in issue
+// order, so the epilogue then waits for its own reads only, not for the
+// next tile.
 template <typename T, int NKS>
 __global__ __launch_bounds__(kXiThreads, 2) void k_xi2_tiles(const MixJob *__restrict__ jobs, int n_jobs,
                                                              const XiUnit *__restrict__ units, int64_t cap,
                                                              int32_t *__restrict__ counters) {
   static_assert(sizeof(T) == 2, "16-bit operands only");
   static_assert(NKS % 4 == 0 && NKS <= 32, "k-steps in blocks of 4, kcat <= 512");
+  static_assert(4 * kXiLoads >= kXiTileBlocks, "whole tiles");
   typedef typename Op<T>::vec vec;
-  __shared__ __attribute__((aligned(1024))) char Bt[2][kXiTileChunks * 16];
+  __shared__ __attribute__((aligned(1024))) char Bt[2][kXiTileBlocks * 1024];
+  __shared__ __attribute__((aligned(1024))) char Bx[1024];   // landing block of the loads past a tile
   __shared__ int64_t s_key[64];
   __shared__ float2 s_z[64];
   __shared__ int s_lo[64], s_ab[64];   // lag window start (relative to ws), autocorrelation row
@@ -1293,9 +1300,6 @@ __global__ __launch_bounds__(kXiThreads, 2) void k_xi2_tiles(const MixJob *__res
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int fr = lane & 31, fh = lane >> 5;
-  // chunks past a row's kcat values that no load of a tile writes are read
-  // (against zero A fragments) by the padding k-steps: keep them finite
-  for (int c = threadIdx.x; c < 2 * kXiTileChunks; c += kXiThreads) ((uint4 *)&Bt[0][0])[c] = uint4{0, 0, 0, 0};
   const int64_t n_units = min((int64_t)counters[0], cap);
   for (;;) {
     if (threadIdx.x == 0) s_u = atomicAdd(&counters[1], 1);
@@ -1364,10 +1368,11 @@ __global__ __launch_bounds__(kXiThreads, 2) void k_xi2_tiles(const MixJob *__res
 #pragma unroll
     for (int p = 0; p < 8; ++p) num[p] = den[p] = 0.f;
 
-    // tile loads: this wave's load i fills chunks (4 i + wave) 64 + lane of
-    // the tile, chunk c = row c / P, position c % P (the pad position reads
-    // the row's first chunk, rows past 31 read row 31).  The resource ends at
-    // the unit's last sample: rows past it load zeros.
+    // tile loads: this wave's load i fills block 4 i + wave of the tile, lane
+    // chunk c = 64 (4 i + wave) + lane = row c / P, position c % P (the pad
+    // position reads the row's first chunk, rows past 31 read row 31).  The
+    // resource ends at the unit's last sample: rows past it load zeros, and
+    // so do the blocks past the tile's nblk (into Bx past kXiTileBlocks).
     const int cpr = kcat / 8, P = cpr + 1, nblk = (32 * P + 63) / 64;
     const int rowbytes = kcat * 2;
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(jb.ocat, (ba1 - jb.ocat_abs0) * (int64_t)rowbytes);
@@ -1382,12 +1387,11 @@ __global__ __launch_bounds__(kXiThreads, 2) void k_xi2_tiles(const MixJob *__res
       const int tb = base0 + 32 * j * rowbytes;
       char *buf = Bt[j & 1];
 #pragma unroll
-      for (int i = 0; i < (kXiTileChunks + 255) / 256; ++i) {
+      for (int i = 0; i < kXiLoads; ++i) {
         const int blk = 4 * i + wave;
-        if (blk < nblk) {
-          const int vo = tb + min(r, 31) * rowbytes + (q < cpr ? q : 0) * 16;
-          __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void *)(buf + blk * 1024), 16, vo, 0, 0, 0);
-        }
+        const int vo = blk < nblk ? tb + min(r, 31) * rowbytes + (q < cpr ? q : 0) * 16 : 0x7ffffff0;
+        char *dst = blk < kXiTileBlocks ? buf + blk * 1024 : Bx;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void *)dst, 16, vo, 0, 0, 0);
         q += dq;
         r += dr;
         if (q >= P) {
@@ -1397,20 +1401,35 @@ __global__ __launch_bounds__(kXiThreads, 2) void k_xi2_tiles(const MixJob *__res
       }
     };
     const int ntl = (int)((ba1 - ba0 + 31) / 32);
-    const float2 *acorr = (const float2 *)jb.acorr;
+    // a global (not generic) pointer: its reads count on the vector-memory
+    // counter only, so the epilogue's wait leaves the next tile's loads in flight
+    typedef float fv2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(1))) const fv2 gfv2;
+    gfv2 *acorr = (gfv2 *)jb.acorr;
     const float sc = jb.inv_scale;
     const int nrel0 = (int)(ba0 - ws) + fr, nrel_end = (int)(ba1 - ws);
     issue(0);
     for (int j = 0; j < ntl; ++j) {
       __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's loads of tile j
       __syncthreads();                      // every wave's; tile j - 1's buffer is free
-      if (j + 1 < ntl) issue(j + 1);
+      // the lane's eight triggers (accumulator rows 8 (e/4) + 4 fh + e%4):
+      // autocorrelation at this lane's lag of each (a lag outside the window
+      // reads entry 0 and adds nothing)
+      const int nrel = nrel0 + 32 * j;   // this lane's sample, relative to ws
+      fv2 r[8];
+      bool in[8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const int t = 16 * wave + 4 * (p >> 1) + 2 * fh + (p & 1);
+        const int d = nrel - s_lo[t];
+        in[p] = nrel < nrel_end && (unsigned)d <= (unsigned)(2 * K);
+        r[p] = acorr[in[p] ? s_ab[t] + d : 0];
+      }
+      issue(j + 1);   // past the range: zeros into the free buffer
       const int64_t s0 = ba0 + 32 * (int64_t)j;
       if (s0 < ga1 && s0 + 32 > ga0) {   // uniform over the wave
         const char *bb = Bt[j & 1] + (fr * P + fh) * 16;
-        f32x16 acc, acc2;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[e] = acc2[e] = 0.f;
+        f32x16 acc;
 #pragma unroll
         for (int kb = 0; kb < NKS; kb += 4) {
           vec bf[4];
@@ -1418,25 +1437,7 @@ __global__ __launch_bounds__(kXiThreads, 2) void k_xi2_tiles(const MixJob *__res
           for (int u2 = 0; u2 < 4; ++u2) bf[u2] = *(const vec *)(bb + (kb + u2) * 32);
           __builtin_amdgcn_sched_barrier(0);   // the block's reads ahead of its MFMAs
 #pragma unroll
-          for (int u2 = 0; u2 < 4; u2 += 2) {
-            acc = Op<T>::mfma(af[kb + u2], bf[u2], acc);
-            acc2 = Op<T>::mfma(af[kb + u2 + 1], bf[u2 + 1], acc2);
-          }
-        }
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[e] += acc2[e];
-        const int nrel = nrel0 + 32 * j;   // this lane's sample, relative to ws
-        // the lane's eight triggers (accumulator rows 8 (e/4) + 4 fh + e%4):
-        // all eight autocorrelation reads in flight at once (a lag outside
-        // the window reads entry 0 and adds nothing)
-        float2 r[8];
-        bool in[8];
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-          const int t = 16 * wave + 4 * (p >> 1) + 2 * fh + (p & 1);
-          const int d = nrel - s_lo[t];
-          in[p] = nrel < nrel_end && (unsigned)d <= (unsigned)(2 * K);
-          r[p] = acorr[in[p] ? s_ab[t] + d : 0];
+          for (int u2 = 0; u2 < 4; ++u2) acc = Op<T>::mfma(af[kb + u2], bf[u2], kb + u2 == 0 ? f32x16{} : acc);
         }
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
@@ -1465,7 +1466,10 @@ __global__ __launch_bounds__(kXiThreads, 2) void k_xi2_tiles(const MixJob *__res
           jb.peak_xi[(s_key[t] & 0xffffffff) * jb.ld_peak + pcol] = den[p] > 0.f ? num[p] / den[p] : 0.f;
       }
     }
-    __syncthreads();   // the unit's keys and tiles are free for the next unit
+    // the zeros issued past the range have landed and every wave is done
+    // with the unit's keys and tiles before the next unit reuses them
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    __syncthreads();
   }
 }
 
