@@ -925,83 +925,134 @@ __global__ __launch_bounds__(64 * WM * WN, WGS) void k_mix_dl(const MixJob *__re
 // Phase and sub-sample refinement at each reported window peak: z_i at n* - 1,
 // n*, n* + 1 recomputed as the dot products of mixing rows 2i, 2i+1 with those
 // operand rows (FP32 accumulation; the operand holds one extra sample on each
-// side of a chunk), one thread per (template, window) entry reading 16-byte
-// vectors; a team of 8 lanes shares an entry (strided over K, then reduced
-// with lane shuffles).  The refinement is the vertex of the parabola through
-// the three |z| values (offset clipped to half a sample; none when the triple
-// is not concave).  Peaks below `thr` get zeros (not reported), so only the
-// entries that become triggers do the work.
+// side of a chunk).  The refinement is the vertex of the parabola through the
+// three |z| values (offset clipped to half a sample; none when the triple is
+// not concave).  Peaks below `thr` get zeros (not reported).
+// One thread per (template, window) entry tests the threshold and writes the
+// zeros; then the whole wave takes its entries above it two at a time: lane k
+// reads 16-byte vector k of each of the 5 rows of both (all 10 reads in
+// flight at once) and the 12 partial sums are reduced over the wave.
 template <typename T> struct Vec16 {
   T v[16 / sizeof(T)];
 };
 
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ jobs, int n_jobs, int64_t entries,
                                                     float thr) {
-  constexpr int TEAM = 8;
-  const int64_t e = (int64_t)blockIdx.x * (256 / TEAM) + threadIdx.x / TEAM;
-  const int sub = threadIdx.x % TEAM;
-  if (e >= entries) return;   // uniform within a team
-  // job owning entry e: last job with e0 <= e
-  int lo = 0, hi = n_jobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].e0 <= e) lo = mid;
-    else hi = mid - 1;
-  }
-  const MixJob &jb = jobs[lo];
-  const int64_t le = e - jb.e0;
-  const int64_t i = le / jb.nw, wl = le - i * jb.nw;
-  const int64_t o = i * jb.ld_peak + (jb.w0 + wl - jb.w_base);
-  if (!(jb.peak_snr[o] >= thr)) {
-    if (sub == 0) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int job = 0;
+  int64_t o = 0, row = 0;   // peak-table offset and template of this lane's entry
+  bool hit = false;
+  if (e < entries) {
+    // job owning entry e: last job with e0 <= e
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].e0 <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    job = lo;
+    const MixJob &jb = jobs[lo];
+    const int64_t le = e - jb.e0;
+    row = le / jb.nw;
+    o = row * jb.ld_peak + (jb.w0 + le - row * jb.nw - jb.w_base);
+    hit = jb.peak_snr[o] >= thr;
+    if (!hit) {
       jb.peak_phase[o] = 0.f;
       jb.peak_dt[o] = 0.f;
       jb.peak_si[o] = 0.f;
     }
-    return;
   }
   constexpr int EPV = 16 / (int)sizeof(T);
-  const int kcat = jb.kcat;   // a multiple of 32: rows are whole 16-byte vectors
-  const uint4 *o0 = (const uint4 *)((const T *)jb.ocat + (jb.peak_n[o] - 1 - jb.ocat_abs0) * (int64_t)kcat);
-  const uint4 *mc = (const uint4 *)((const T *)jb.mix + (2 * i) * (int64_t)kcat);
-  const uint4 *ms = mc + kcat / EPV;
-  float re[3] = {0.f, 0.f, 0.f}, im[3] = {0.f, 0.f, 0.f};
-  for (int k = sub; k < kcat / EPV; k += TEAM) {
-    const Vec16<T> c = __builtin_bit_cast(Vec16<T>, mc[k]);
-    const Vec16<T> d = __builtin_bit_cast(Vec16<T>, ms[k]);
+  uint64_t m = __ballot(hit);
+  while (m) {
+    // up to two entries of the wave; the second repeats the first when there is none
+    const int s0 = __builtin_ctzll(m);
+    m &= m - 1;
+    const int s1 = m ? __builtin_ctzll(m) : s0;
+    if (m) m &= m - 1;
+    const int src[2] = {s0, s1};
+    float acc[2][6];
+    int jx[2];
+    int64_t ox[2];
+    const uint4 *mc[2], *ms[2], *o0[2];
+    int nv[2];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const Vec16<T> a = __builtin_bit_cast(Vec16<T>, o0[q * (kcat / EPV) + k]);
+    for (int t = 0; t < 2; ++t) {
+      jx[t] = __builtin_amdgcn_readlane(job, src[t]);
+      const MixJob &jb = jobs[jx[t]];
+      const int64_t r = ((int64_t)__builtin_amdgcn_readlane((int)(row >> 32), src[t]) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)row, src[t]);
+      ox[t] = ((int64_t)__builtin_amdgcn_readlane((int)(o >> 32), src[t]) << 32) |
+              (uint32_t)__builtin_amdgcn_readlane((int)o, src[t]);
+      const int kcat = jb.kcat;   // a multiple of 32: rows are whole 16-byte vectors
+      nv[t] = kcat / EPV;
+      o0[t] = (const uint4 *)((const T *)jb.ocat + (jb.peak_n[ox[t]] - 1 - jb.ocat_abs0) * (int64_t)kcat);
+      mc[t] = (const uint4 *)((const T *)jb.mix + (2 * r) * (int64_t)kcat);
+      ms[t] = mc[t] + nv[t];
 #pragma unroll
-      for (int j = 0; j < EPV; ++j) {
-        const float ov = Op<T>::tof(a.v[j]);
-        re[q] += Op<T>::tof(c.v[j]) * ov;
-        im[q] += Op<T>::tof(d.v[j]) * ov;
+      for (int q = 0; q < 6; ++q) acc[t][q] = 0.f;
+    }
+    for (int k0 = 0; k0 < max(nv[0], nv[1]); k0 += 64) {
+      const int k = k0 + lane;
+      Vec16<T> c[2], d[2], a[2][3];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const bool ok = k < nv[t];
+        const int kk = ok ? k : 0;
+        c[t] = __builtin_bit_cast(Vec16<T>, mc[t][kk]);
+        d[t] = __builtin_bit_cast(Vec16<T>, ms[t][kk]);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) a[t][q] = __builtin_bit_cast(Vec16<T>, o0[t][q * nv[t] + kk]);
+        if (!ok) c[t] = d[t] = Vec16<T>{};
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int j = 0; j < EPV; ++j) {
+            // explicit FMAs: the same arithmetic in both slots (the compiler
+            // would otherwise pair some products into dot-product
+            // instructions that round differently)
+            const float ov = Op<T>::tof(a[t][q].v[j]);
+            acc[t][q] = __builtin_fmaf(Op<T>::tof(c[t].v[j]), ov, acc[t][q]);
+            acc[t][3 + q] = __builtin_fmaf(Op<T>::tof(d[t].v[j]), ov, acc[t][3 + q]);
+          }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) acc[t][q] = wave_sum(acc[t][q]);
+    if (lane == 0) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        if (t == 1 && s1 == s0) break;
+        const MixJob &jb = jobs[jx[t]];
+        const float *re = acc[t], *im = acc[t] + 3;
+        float amp[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) amp[q] = sqrtf(re[q] * re[q] + im[q] * im[q]) * jb.inv_scale;
+        const float curv = amp[0] - 2.f * amp[1] + amp[2];
+        float dt = 0.f, v = amp[1];
+        if (curv < 0.f) {
+          dt = fminf(0.5f, fmaxf(-0.5f, (amp[0] - amp[2]) / (2.f * curv)));
+          v = amp[1] - 0.25f * (amp[0] - amp[2]) * dt;
+        }
+        jb.peak_phase[ox[t]] = atan2f(im[1], re[1]);
+        jb.peak_dt[ox[t]] = dt;
+        jb.peak_si[ox[t]] = v;
+        if (jb.peak_z) jb.peak_z[ox[t]] = make_float2(re[1] * jb.inv_scale, im[1] * jb.inv_scale);
       }
     }
   }
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-#pragma unroll
-    for (int off = 1; off < TEAM; off <<= 1) {
-      re[q] += __shfl_xor(re[q], off);
-      im[q] += __shfl_xor(im[q], off);
-    }
-  if (sub != 0) return;
-  float amp[3];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) amp[q] = sqrtf(re[q] * re[q] + im[q] * im[q]) * jb.inv_scale;
-  const float curv = amp[0] - 2.f * amp[1] + amp[2];
-  float dt = 0.f, v = amp[1];
-  if (curv < 0.f) {
-    dt = fminf(0.5f, fmaxf(-0.5f, (amp[0] - amp[2]) / (2.f * curv)));
-    v = amp[1] - 0.25f * (amp[0] - amp[2]) * dt;
-  }
-  jb.peak_phase[o] = atan2f(im[1], re[1]);
-  jb.peak_dt[o] = dt;
-  jb.peak_si[o] = v;
-  if (jb.peak_z) jb.peak_z[o] = make_float2(re[1] * jb.inv_scale, im[1] * jb.inv_scale);
 }
 
 // Signal-consistency value at each trigger peak (Sec. II.A computes phase and
@@ -1963,7 +2014,7 @@ hipError_t launch_mix_jobs(lloid_dtype t, int variant, const MixJob *jobs, int n
 hipError_t launch_peak_phase(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_entries, float phase_thr,
                              hipStream_t s) {
   if (n_entries <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((n_entries + 31) / 32);   // 32 entries of 8 lanes per workgroup
+  const unsigned blocks = (unsigned)((n_entries + 255) / 256);   // one entry per thread
   switch (t) {
     case LLOID_F16: k_peak_phase<_Float16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, phase_thr); break;
     case LLOID_BF16: k_peak_phase<__bf16><<<blocks, 256, 0, s>>>(jobs, n_jobs, n_entries, phase_thr); break;
