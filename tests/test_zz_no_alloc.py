@@ -67,3 +67,32 @@ def test_noalloc_refuses_what_does_not_fit():
         _same(got, want, "mini after ENOMEM")
     finally:
         lloid.lloid_bank_destroy(b)
+
+
+@pytest.mark.parametrize("compute", ["f16", "f32"])
+def test_noalloc_signal_consistency_in_chunks(compute):
+    """With autocorrelations (signal consistency on), the allocation-free call
+    carves the trigger listing slabs and the unit list out of the static
+    scratch too: forced small chunks (the unit list reused chunk after chunk)
+    give the triggers of lloid_filter bit for bit, xi2 included, on two calls
+    in a row."""
+    from paper_2410_16416_amd import lloid
+    from workloads import bank_autocorrelation
+    bank = configs.mini_multirate_bank()
+    bank.autocorr = bank_autocorrelation(bank, 20)
+    x = configs.mini_multirate(seconds=12, n_injections=2, bank=bank).strains[0]
+    b = lloid.bank_from_svd(ctx(), bank, compute)
+    try:
+        lloid.lloid_ctx_set_chunk_bytes(ctx(), 400000)
+        for n, label in ((x.shape[0], "12 s"), (5 * 1024 - 333, "5 s, ragged")):
+            log(f"[noalloc xi2] {compute} {label}")
+            want = lloid.lloid_filter(b, 0, x[:n], window=(1, 4), threshold=3.0)
+            got = lloid.lloid_filter_noalloc(b, 0, x[:n], window=(1, 4), threshold=3.0)
+            assert got.n_triggers == want.n_triggers, label
+            for f in got.triggers.dtype.names:
+                np.testing.assert_array_equal(got.triggers[f], want.triggers[f], err_msg=f"{label}: {f}")
+            assert got.n_triggers > 10 and np.all(got.triggers["xi2"] > 0)
+            log(f"  {got.n_triggers} triggers identical")
+    finally:
+        lloid.lloid_ctx_set_chunk_bytes(ctx(), 6 << 30)
+        lloid.lloid_bank_destroy(b)
