@@ -351,6 +351,68 @@ def test_xi2_more_triggers_than_one_list_pass(compute):
     assert n_cmp > 0.95 * t.shape[0]
 
 
+@functools.lru_cache(maxsize=None)
+def c1_autocorr(half: int):
+    from workloads import bank_autocorrelation
+    return bank_autocorrelation(c1_full_inputs().bank, half)
+
+
+@pytest.mark.parametrize("compute", ["f16", "bf16"])
+def test_c1_full_size_xi2_sampled(compute):
+    """The benchmark's signal-consistency configuration at full size: the
+    1024-template bank with 351 lags (K = 175; 480 concatenated columns, so
+    the tile launch's 32-step form), detector 0 x 1024 s in one call.  Sampled
+    triggers (up to 12 from each of the injection windows, the first, the
+    last and random windows) against the oracle's xi2 from the oracle's z of
+    the trigger's template around its peak, outside near ties, with the bound
+    of test_xi2_matches_oracle."""
+    from paper_2410_16416_amd import lloid
+    half = 175
+    log(f"[c1-full xi2] compute={compute}")
+    wl = c1_full_inputs()
+    bank, x = wl.bank, wl.strains[0]
+    n = x.shape[0]
+    r = c1_autocorr(half)
+    bank.autocorr = r
+    try:
+        b = lloid.bank_from_svd(ctx(), bank, compute)
+    finally:
+        bank.autocorr = None
+    try:
+        t = lloid.lloid_filter(b, 0, x, window=(1, 1)).triggers
+    finally:
+        lloid.lloid_bank_destroy(b)
+    assert t.shape[0] > 10000 and np.all(t["xi2"] >= 0)
+    rng = np.random.default_rng(13)
+    inj_w = sorted({inj.t0 // 2048 for inj in wl.injections})
+    wins = sorted(set(inj_w[:3]) | {0, 1023} | set(rng.integers(1, 1023, 3).tolist()))
+    eps = EPS_ABS[compute]
+    lag = np.arange(-half, half + 1)
+    n_cmp, n_pick, worst = 0, 0, 0.0
+    for w in wins:
+        sel = np.flatnonzero(t["window"] == w)
+        for k in rng.choice(sel, size=min(12, sel.shape[0]), replace=False):
+            rec = t[k]
+            i, s_ = int(rec["template_id"]), int(rec["sample"])
+            n_pick += 1
+            lo = max(0, min(w * 2048, s_ - half))
+            hi = min(n, max((w + 1) * 2048, s_ + half + 1))
+            z = oracle.lloid_snr(wl.bank, x, lo, hi, templates=np.array([i]))[0]
+            a = np.abs(z[w * 2048 - lo:min((w + 1) * 2048, n) - lo])
+            if a.argmax() + w * 2048 != s_:
+                continue   # near tie: the GPU's peak is another sample
+            want = oracle.xi2(z, lo, n, s_, r[i])
+            ok = (s_ + lag >= 0) & (s_ + lag < n)
+            d = z[(s_ + lag)[ok] - lo] - z[s_ - lo] * r[i, ok]
+            den = np.sum(2.0 - 2.0 * np.abs(r[i, ok]) ** 2)
+            tol = (4 * eps * np.sum(np.abs(d)) + 4 * eps ** 2 * ok.sum()) / den + 1e-5 * want
+            assert abs(float(rec["xi2"]) - want) <= tol, (i, w, s_, float(rec["xi2"]), want, tol)
+            worst = max(worst, abs(float(rec["xi2"]) - want))
+            n_cmp += 1
+    log(f"  {t.shape[0]} triggers; windows {wins}: {n_cmp} of {n_pick} sampled compared, max |d xi2| {worst:.2e}")
+    assert n_cmp > 0.8 * n_pick and n_cmp >= 40
+
+
 LONG_BASES = {288: [(1024, 0, 160, 128), (256, 160, 96, 96), (64, 544, 80, 64)],
               544: [(1024, 0, 288, 256), (256, 288, 200, 192), (64, 1088, 100, 96)]}
 
