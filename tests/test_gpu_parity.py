@@ -358,14 +358,16 @@ def c1_autocorr(half: int):
 
 
 @pytest.mark.parametrize("compute", ["f16", "bf16"])
-def test_c1_full_size_xi2_sampled(compute):
+def test_c1_full_size_trigger_fields_sampled(compute):
     """The benchmark's signal-consistency configuration at full size: the
     1024-template bank with 351 lags (K = 175; 480 concatenated columns, so
     the tile launch's 32-step form), detector 0 x 1024 s in one call.  Sampled
     triggers (up to 12 from each of the injection windows, the first, the
-    last and random windows) against the oracle's xi2 from the oracle's z of
-    the trigger's template around its peak, outside near ties, with the bound
-    of test_xi2_matches_oracle."""
+    last and random windows) against the oracle's z of the trigger's template
+    around its peak, outside near ties: xi2 with the bound of
+    test_xi2_matches_oracle; the sub-sample refinement with the bounds of
+    test_subsample_peaks_match_oracle; the phase within 2 eps / |z*| (the
+    angle a complex error of eps can turn)."""
     from paper_2410_16416_amd import lloid
     half = 175
     log(f"[c1-full xi2] compute={compute}")
@@ -388,7 +390,7 @@ def test_c1_full_size_xi2_sampled(compute):
     wins = sorted(set(inj_w[:3]) | {0, 1023} | set(rng.integers(1, 1023, 3).tolist()))
     eps = EPS_ABS[compute]
     lag = np.arange(-half, half + 1)
-    n_cmp, n_pick, worst = 0, 0, 0.0
+    n_cmp, n_pick, worst, worst_phi = 0, 0, 0.0, 0.0
     for w in wins:
         sel = np.flatnonzero(t["window"] == w)
         for k in rng.choice(sel, size=min(12, sel.shape[0]), replace=False):
@@ -408,8 +410,18 @@ def test_c1_full_size_xi2_sampled(compute):
             tol = (4 * eps * np.sum(np.abs(d)) + 4 * eps ** 2 * ok.sum()) / den + 1e-5 * want
             assert abs(float(rec["xi2"]) - want) <= tol, (i, w, s_, float(rec["xi2"]), want, tol)
             worst = max(worst, abs(float(rec["xi2"]) - want))
+            # sub-sample refinement and phase from the same oracle z
+            am, a0, ap = (float(abs(z[s_ + k - lo])) for k in (-1, 0, 1))
+            dt_o, v_o = oracle.subsample_peak(np.array([am]), np.array([a0]), np.array([ap]))
+            assert abs(float(rec["snr_interp"]) - float(v_o[0])) <= 2 * eps, (i, w, s_)
+            curv = am - 2.0 * a0 + ap
+            assert abs(float(rec["dt"]) - float(dt_o[0])) <= min(1.0, 4 * eps / max(abs(curv), 1e-12)) + 1e-6
+            dphi = np.angle(np.exp(1j * (float(rec["phase"]) - np.angle(z[s_ - lo]))))
+            assert abs(dphi) <= 2 * eps / a0 + 1e-5, (i, w, s_, float(rec["phase"]), np.angle(z[s_ - lo]))
+            worst_phi = max(worst_phi, abs(dphi))
             n_cmp += 1
-    log(f"  {t.shape[0]} triggers; windows {wins}: {n_cmp} of {n_pick} sampled compared, max |d xi2| {worst:.2e}")
+    log(f"  {t.shape[0]} triggers; windows {wins}: {n_cmp} of {n_pick} sampled compared, max |d xi2| {worst:.2e}, "
+        f"max |d phase| {worst_phi:.2e}")
     assert n_cmp > 0.8 * n_pick and n_cmp >= 40
 
 
