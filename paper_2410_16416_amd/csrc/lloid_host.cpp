@@ -732,7 +732,10 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   const bool host_snr = snr && !is_device_ptr(snr);
   int64_t total_rows = 0;
   for (int i = 0; i < nb; ++i) total_rows += banks[i]->n_templates;
-  const int64_t dev_cap = std::min<int64_t>(trig_cap, total_rows * W);
+  // a trigger buffer in device memory or pinned host memory takes the records
+  // straight from the compaction kernel; otherwise they go through scratch
+  lloid_trigger *direct_trig = trig_cap > 0 ? (lloid_trigger *)device_address(trig) : nullptr;
+  const int64_t dev_cap = direct_trig ? trig_cap : std::min<int64_t>(trig_cap, total_rows * W);
   size_t n_fir = 0, n_up = 0;
   for (int i = 0; i < nb; ++i)
     for (const auto &sl : banks[i]->slices) {
@@ -777,7 +780,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     add(1, 4);
     add((size_t)xi_cap(wpc_), sizeof(XiUnit));
     add(2, 4);
-    add((size_t)std::max<int64_t>(dev_cap, 1), sizeof(lloid_trigger));
+    if (!direct_trig) add((size_t)std::max<int64_t>(dev_cap, 1), sizeof(lloid_trigger));
     if (host_snr) add((size_t)n * 2 * banks[0]->n_templates, 4);
     add(table_bytes(ceil_div(W, wpc_)), 1);
     return bytes;
@@ -858,7 +861,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   xw.cap = xi_cap(wpc);
   xw.units = cv.take<XiUnit>((size_t)xw.cap);
   xw.counters = cv.take<int32_t>(2);
-  lloid_trigger *dtrig = cv.take<lloid_trigger>((size_t)std::max<int64_t>(dev_cap, 1));
+  lloid_trigger *dtrig = direct_trig ? direct_trig : cv.take<lloid_trigger>((size_t)std::max<int64_t>(dev_cap, 1));
   float *dsnr = snr ? (host_snr ? cv.take<float>((size_t)n * 2 * banks[0]->n_templates) : snr) : nullptr;
   char *dtab = cv.take<char>(tab_bytes);
 
@@ -961,10 +964,10 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   if (host_snr)
     HIP_TRY(hipMemcpyAsync(snr, dsnr, (size_t)banks[0]->n_templates * n * 2 * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  const int64_t ncopy = std::min(h_total, dev_cap);
+  const int64_t ncopy = direct_trig ? 0 : std::min(h_total, dev_cap);
   if (ncopy > 0) HIP_TRY(hipMemcpyAsync(trig, dtrig, (size_t)ncopy * sizeof(lloid_trigger), hipMemcpyDefault, st));
   HIP_TRY(mark(LLOID_STAGE_D2H, 1));
-  HIP_TRY(hipStreamSynchronize(st));
+  if (ncopy > 0 || prof) HIP_TRY(hipStreamSynchronize(st));
   if (prof) {
     for (int i = 0; i < LLOID_N_STAGES; ++i) {
       float ms = 0.f;

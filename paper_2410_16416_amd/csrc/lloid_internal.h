@@ -247,6 +247,20 @@ inline bool is_device_ptr(const void *p) {
   return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
+// Address at which kernels can write the caller's buffer p: p itself for
+// device memory, the device alias of pinned host memory, NULL for pageable
+// host memory.
+inline void *device_address(void *p) {
+  hipPointerAttribute_t attr;
+  if (!p || hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged) return p;
+  if (attr.type == hipMemoryTypeHost && attr.devicePointer) return attr.devicePointer;
+  return nullptr;
+}
+
 
 struct Carve {
   char *base;

@@ -107,6 +107,38 @@ def test_triggers_are_thresholded_peaks_and_truncate():
         lloid.lloid_bank_destroy(b)
 
 
+def test_triggers_into_pinned_and_device_buffers():
+    """A trigger buffer in pinned host memory or in device memory takes the
+    records straight from the compaction kernel (no staging copy): the same
+    records as a pageable buffer, and a too-small pinned buffer still gets
+    ETRUNC with the first records and the required count."""
+    import torch
+    from paper_2410_16416_amd import lloid
+    wl, x, z, pa, ps, ph = mini_case()
+    b = lloid.bank_from_svd(ctx(), wl.bank, "f16")
+    isz = lloid.TRIGGER_DTYPE.itemsize
+    try:
+        want = lloid.lloid_filter(b, 0, x, window=(1, 4), threshold=3.0).triggers
+        assert want.shape[0] > 20
+        cap = want.shape[0] + 7
+        pinned = torch.zeros(cap * isz, dtype=torch.uint8, pin_memory=True)
+        r = lloid.lloid_filter(b, 0, x, window=(1, 4), threshold=3.0, triggers_out=pinned)
+        got = pinned.numpy().view(lloid.TRIGGER_DTYPE)[: r.n_triggers]
+        assert r.n_triggers == want.shape[0] and np.array_equal(got, want)
+        dev = torch.zeros(cap * isz, dtype=torch.uint8, device="cuda")
+        r = lloid.lloid_filter(b, 0, x, window=(1, 4), threshold=3.0, triggers_out=dev)
+        torch.cuda.synchronize()
+        got = dev.cpu().numpy().view(lloid.TRIGGER_DTYPE)[: r.n_triggers]
+        assert r.n_triggers == want.shape[0] and np.array_equal(got, want)
+        small = torch.zeros(5 * isz, dtype=torch.uint8, pin_memory=True)
+        with pytest.raises(lloid.LloidError) as ei:
+            lloid.lloid_filter(b, 0, x, window=(1, 4), threshold=3.0, trig_cap=5, triggers_out=small)
+        assert ei.value.status == lloid.LLOID_ETRUNC
+        assert np.array_equal(small.numpy().view(lloid.TRIGGER_DTYPE), want[:5])
+    finally:
+        lloid.lloid_bank_destroy(b)
+
+
 def test_deterministic_and_device_strain():
     import torch
     from paper_2410_16416_amd import lloid
