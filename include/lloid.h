@@ -435,11 +435,15 @@ lloid_status lloid_coincide(lloid_ctx *ctx, const lloid_trigger *a, int64_t n_a,
 
 /* ---- tile shapes and their autotuning ----
  * The FIR and mixing kernels are compiled in a few tile shapes (variants:
- * FIR 0..4, mixing 0..4; 0 is the default).  Every variant gives
+ * FIR 0 .. LLOID_FIR_VARIANTS - 1, mixing 0 .. LLOID_MIX_VARIANTS - 1; 0 is
+ * the default).  Every variant gives
  * bit-identical results (each output's sum over K runs in the same order);
  * only the speed differs with the banks' shapes.  A context starts with the
  * defaults, or the variants named by the environment variables
  * LLOID_FIR_VARIANT and LLOID_MIX_VARIANT. */
+#define LLOID_FIR_VARIANTS 6
+#define LLOID_MIX_VARIANTS 5
+
 typedef struct {
   int32_t fir_variant;
   int32_t mix_variant;

@@ -177,7 +177,7 @@ hipError_t launch_decimate(const float *u, int64_t u_lo, int64_t u_len, float *d
 // Compiled tile-shape variants of the FIR and mixing kernels (0 = default);
 // every variant gives bit-identical results (each output's K sum runs in the
 // same order), only the speed differs.  Rows x columns per workgroup:
-constexpr int kFirVariants = 5, kMixVariants = 5;
+constexpr int kFirVariants = LLOID_FIR_VARIANTS, kMixVariants = LLOID_MIX_VARIANTS;
 void fir_tile_shape(lloid_dtype t, int variant, int *bm, int *bn);
 void mix_tile_shape(lloid_dtype t, int variant, int *bm, int *bn);
 // One launch per stage over a device descriptor table (see the job structs).

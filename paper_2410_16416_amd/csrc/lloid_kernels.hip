@@ -207,7 +207,7 @@ template <typename T, int ROWS, int BK = kBK, int THREADS = kThreads> struct Chu
 // k-step parity, a window of NT fragments in registers and reads one new
 // fragment from LDS per k-step instead of NT.
 template <typename T, int MT, int NT, int NW, int BK, bool HR = false>
-__global__ __launch_bounds__(64 * NW) void k_fir(const FirJob *__restrict__ jobs, int n_jobs) {
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void k_fir(const FirJob *__restrict__ jobs, int n_jobs) {
   typedef Op<T> O;
   static_assert(!HR || O::KS == 16, "the fragment window needs 16 taps per k-step");
   constexpr int THREADS = 64 * NW;
@@ -1921,6 +1921,12 @@ static hipError_t fir_t(int variant, const FirJob *jobs, int n_jobs, int64_t n_i
       } else {
         return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
       }
+    case 5:
+      // 16-bit operands: the Hankel fragment window in four-wave 64 x 512
+      // tiles, two workgroups per CU (one's strain-window fill and stores run
+      // while the other's MFMAs do), basis chunks of 128 taps
+      if constexpr (sizeof(T) == 2) return fir_v<T, 2, 4, 4, 4 * kBK, true>(jobs, n_jobs, n_items, s);
+      else return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
     case 2:
       // 16-bit operands: 64 x 1024 tiles with the Hankel fragment window
       if constexpr (sizeof(T) == 2) return fir_v<T, 2, 4, kFirWaves, 2 * kBK, true>(jobs, n_jobs, n_items, s);
@@ -1936,6 +1942,7 @@ void fir_tile_shape(lloid_dtype t, int variant, int *bm, int *bn) {
   *bm = 32 * kFirMT;
   *bn = kFirWaves * 32 * kFirNT;
   if ((variant == 2 || variant == 3 || variant == 4) && t != LLOID_F32) *bm = 32 * 2, *bn = kFirWaves * 32 * 4;
+  if (variant == 5 && t != LLOID_F32) *bm = 32 * 2, *bn = 4 * 32 * 4;
 }
 
 void mix_tile_shape(lloid_dtype, int variant, int *bm, int *bn) {

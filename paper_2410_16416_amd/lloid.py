@@ -22,6 +22,8 @@ LLOID_OK, LLOID_EINVAL, LLOID_ENOMEM, LLOID_EAGAIN = 0, -1, -2, -3
 LLOID_ETRUNC, LLOID_EDEVICE, LLOID_EORDER, LLOID_EDATA = -4, -5, -6, -7
 LLOID_F64, LLOID_F32, LLOID_F16, LLOID_BF16 = 0, 1, 2, 3
 NOALLOC_SCRATCH_BYTES = 256 << 20   # LLOID_NOALLOC_SCRATCH_BYTES
+FIR_VARIANTS = 6                    # LLOID_FIR_VARIANTS
+MIX_VARIANTS = 5                    # LLOID_MIX_VARIANTS
 DTYPES = {"f64": LLOID_F64, "f32": LLOID_F32, "f16": LLOID_F16, "bf16": LLOID_BF16}
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EAGAIN", -4: "ETRUNC",
                 -5: "EDEVICE", -6: "EORDER", -7: "EDATA"}

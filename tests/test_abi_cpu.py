@@ -37,6 +37,16 @@ def test_library_exports_every_declared_symbol():
     assert set(lloid.exported_symbols()) <= set(declared_functions())
 
 
+def test_binding_constants_match_the_header_macros():
+    """The binding's copies of the header's size and count macros."""
+    from paper_2410_16416_amd import lloid
+    text = open(HEADER).read()
+    macros = {m.group(1): m.group(2) for m in re.finditer(r"#define (LLOID_[A-Z0-9_]+) (.+)", text)}
+    assert eval(macros["LLOID_NOALLOC_SCRATCH_BYTES"].replace("ll", "")) == lloid.NOALLOC_SCRATCH_BYTES
+    assert int(macros["LLOID_FIR_VARIANTS"]) == lloid.FIR_VARIANTS
+    assert int(macros["LLOID_MIX_VARIANTS"]) == lloid.MIX_VARIANTS
+
+
 def test_struct_layouts_match_the_c_header(tmp_path):
     """Compile a C probe of the header with gcc and compare sizes and offsets
     with the ctypes mirrors the binding passes through the boundary."""

@@ -109,8 +109,8 @@ def test_tile_variants_give_identical_results(compute):
         # ragged last window (odd and even chunk counts per window)
         for window in ((1, 4), (3, 4)):
             ref = None
-            for fv in range(5):
-                for mv in range(5):
+            for fv in range(lloid.FIR_VARIANTS):
+                for mv in range(lloid.MIX_VARIANTS):
                     lloid.lloid_ctx_set_tiles(c, fv, mv)
                     assert lloid.lloid_ctx_get_tiles(c) == (fv, mv)
                     r = lloid.lloid_filter_batch(handles, 0, x, window=window, threshold=3.0, peaks=True)
@@ -124,7 +124,7 @@ def test_tile_variants_give_identical_results(compute):
                         assert np.array_equal(r.peak_sample[k], ref.peak_sample[k]), (window, fv, mv, k)
         # the complex SNR series too (the kernels' series-writing forms)
         series = None
-        for mv in range(5):
+        for mv in range(lloid.MIX_VARIANTS):
             lloid.lloid_ctx_set_tiles(c, 0, mv)
             r = lloid.lloid_filter(handles[0], 0, x, window=(3, 4), threshold=3.0,
                                    snr_out=np.zeros((banks[0].n_templates, x.size, 2), np.float32))
@@ -133,7 +133,7 @@ def test_tile_variants_give_identical_results(compute):
             else:
                 assert np.array_equal(r.snr, series), mv
         with pytest.raises(lloid.LloidError) as ei:
-            lloid.lloid_ctx_set_tiles(c, 5, 0)
+            lloid.lloid_ctx_set_tiles(c, lloid.FIR_VARIANTS, 0)
         assert ei.value.status == lloid.LLOID_EINVAL
     finally:
         for h in handles:
@@ -154,7 +154,7 @@ def test_autotune_picks_the_fastest_and_caches(tmp_path):
         best, res = lloid.lloid_autotune(c, handles, 4.0, cache)
         log(f"[autotune] best {best}; " + ", ".join(f"{r['fir_variant']}/{r['mix_variant']}: {r['ms']:.2f} ms"
                                                    for r in res))
-        assert res.shape[0] == 5 * 5 and np.all(res["ms"] > 0)   # FIR x mixing shapes
+        assert res.shape[0] == lloid.FIR_VARIANTS * lloid.MIX_VARIANTS and np.all(res["ms"] > 0)
         k = int(np.argmin(res["ms"]))
         assert best == (int(res["fir_variant"][k]), int(res["mix_variant"][k]))
         text = open(cache).read()
