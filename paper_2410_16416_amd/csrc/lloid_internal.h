@@ -20,9 +20,9 @@ constexpr int kBK = 32;          // K chunk staged in LDS (FIR; the concatenated
 constexpr int kLPad = 16;        // basis count padding inside the concatenated K
 constexpr int kRowTile = 32;     // MFMA 32x32 tile
 
-// FIR: kFirWaves waves share 32 * kFirMT basis rows and split
-// kFirWaves * 32 * kFirNT columns; the strain window of kFirKSup taps is
-// staged in LDS at a time.
+// FIR tiles of FP32 operands and of 16-bit variants 1 and 5: kFirWaves waves
+// share 32 * kFirMT basis rows and split kFirWaves * 32 * kFirNT columns; the
+// strain window of kFirKSup taps is staged in LDS at a time.
 constexpr int kFirMT = 4, kFirNT = 2, kFirWaves = 8, kFirKSup = 1024;
 // Mixing: waves arranged kMixWM x kMixWN, each 32 * kMixMT rows x 32 * kMixNT columns.
 constexpr int kMixMT = 2, kMixNT = 4, kMixWM = 4, kMixWN = 2;

@@ -1922,18 +1922,18 @@ static hipError_t fir_t(int variant, const FirJob *jobs, int n_jobs, int64_t n_i
         return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
       }
     case 5:
-      // 16-bit operands: the Hankel fragment window in four-wave 64 x 512
-      // tiles, two workgroups per CU (one's strain-window fill and stores run
-      // while the other's MFMAs do), basis chunks of 128 taps
-      if constexpr (sizeof(T) == 2) return fir_v<T, 2, 4, 4, 4 * kBK, true>(jobs, n_jobs, n_items, s);
+      // 16-bit operands: K chunks of 64 (twice the MFMAs per barrier)
+      if constexpr (sizeof(T) == 2) return fir_v<T, kFirMT, kFirNT, kFirWaves, 2 * kBK>(jobs, n_jobs, n_items, s);
       else return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
     case 2:
       // 16-bit operands: 64 x 1024 tiles with the Hankel fragment window
       if constexpr (sizeof(T) == 2) return fir_v<T, 2, 4, kFirWaves, 2 * kBK, true>(jobs, n_jobs, n_items, s);
       else return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
     default:
-      // 16-bit operands: K chunks of 64 (twice the MFMAs per barrier)
-      if constexpr (sizeof(T) == 2) return fir_v<T, kFirMT, kFirNT, kFirWaves, 2 * kBK>(jobs, n_jobs, n_items, s);
+      // 16-bit operands: the Hankel fragment window in four-wave 64 x 512
+      // tiles, two workgroups per CU (one's strain-window fill and stores run
+      // while the other's MFMAs do), basis chunks of 128 taps
+      if constexpr (sizeof(T) == 2) return fir_v<T, 2, 4, 4, 4 * kBK, true>(jobs, n_jobs, n_items, s);
       else return fir_v<T, kFirMT, kFirNT, kFirWaves, kBK>(jobs, n_jobs, n_items, s);
   }
 }
@@ -1942,7 +1942,7 @@ void fir_tile_shape(lloid_dtype t, int variant, int *bm, int *bn) {
   *bm = 32 * kFirMT;
   *bn = kFirWaves * 32 * kFirNT;
   if ((variant == 2 || variant == 3 || variant == 4) && t != LLOID_F32) *bm = 32 * 2, *bn = kFirWaves * 32 * 4;
-  if (variant == 5 && t != LLOID_F32) *bm = 32 * 2, *bn = 4 * 32 * 4;
+  if (variant == 0 && t != LLOID_F32) *bm = 32 * 2, *bn = 4 * 32 * 4;
 }
 
 void mix_tile_shape(lloid_dtype, int variant, int *bm, int *bn) {
