@@ -612,6 +612,7 @@ void lloid::number_jobs(std::vector<FirJob> &fj, std::vector<UpJob> *uj, std::ve
     if (m.acorr) {
       n.xi2 = true;
       n.xi_kmax = std::max(n.xi_kmax, m.kcat);
+      n.xi_acorr = std::max(n.xi_acorr, (int64_t)m.n_templates * (2 * m.acorr_half + 1));
       n.xi_units += xi_unit_cap(m.nw, m.n_templates);
     }
   }
@@ -640,8 +641,8 @@ lloid_status lloid::launch_stages(lloid_ctx *ctx, lloid_dtype ct, const char *dt
   HIP_TRY(launch_peak_phase(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.entries, phase_thr, st));
   if (n.xi2) {
     if (xw.cap < n.xi_units) return fail(LLOID_EINVAL, "signal-consistency unit list too small");
-    HIP_TRY(launch_xi2(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.windows, n.xi_kmax, trig_thr, xw, ctx->n_cu,
-                       st));
+    HIP_TRY(launch_xi2(ct, (const MixJob *)(dtab + to.mix), to.n_mix, n.windows, n.xi_kmax, n.xi_acorr, trig_thr, xw,
+                       ctx->n_cu, st));
   }
   HIP_TRY(mark(LLOID_STAGE_PHASE, 1));
   return LLOID_OK;

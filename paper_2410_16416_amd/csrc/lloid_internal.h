@@ -196,9 +196,10 @@ hipError_t launch_peak_phase(lloid_dtype t, const MixJob *jobs, int n_jobs, int6
 // Signal-consistency value at the peaks with |z| >= thr of the jobs that carry
 // autocorrelations; one workgroup per (job, window).
 // n_windows: (job, window) items; kmax: largest kcat of a job with lags;
+// acorr_max: largest n_templates * (2 acorr_half + 1) of those jobs;
 // xw.cap >= sum over those jobs of nw * ceil(n_templates / 64)
-hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_windows, int kmax, float thr,
-                      const XiWork &xw, int n_cu, hipStream_t s);
+hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_windows, int kmax, int64_t acorr_max,
+                      float thr, const XiWork &xw, int n_cu, hipStream_t s);
 // Trigger compaction: counts, offsets and records (job-major, template, window);
 // counts holds trig_blocks(n_elems) slots.
 hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems, float thr, int64_t *counts,
@@ -304,6 +305,7 @@ struct StageItems {
   int64_t windows = 0;             // (job, window) pairs: workgroups of the signal-consistency launch
   bool xi2 = false;                // some mixing job carries autocorrelations
   int xi_kmax = 0;                 // largest kcat of such a job
+  int64_t xi_acorr = 0;            // largest autocorrelation table of such a job (entries)
   int64_t xi_units = 0;            // signal-consistency units those jobs can list at most
   int64_t up[kMaxHops] = {};       // items of each interpolation hop
 };

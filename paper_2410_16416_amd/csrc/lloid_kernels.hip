@@ -1067,7 +1067,8 @@ __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ j
 // covers are about its spread of peaks plus 2K (a chunk's operand holds K
 // extra samples on each side).
 //
-// Two forms.  16-bit operands with kcat <= 512 run two launches:
+// Two forms.  16-bit operands with kcat <= 512 (and autocorrelation tables
+// of fewer than 2^31 entries) run two launches:
 // k_xi2_list (one workgroup per (job, window)) stores the sorted keys and
 // appends one unit per 64 of them to a list, and k_xi2_tiles (persistent
 // workgroups taking units from that list) keeps each wave's A fragments in
@@ -2041,12 +2042,13 @@ hipError_t launch_trigger_jobs(const TrigJob *jobs, int n_jobs, int64_t n_elems,
   return hipGetLastError();
 }
 
-hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_windows, int kmax, float thr,
-                      const XiWork &xw, int n_cu, hipStream_t s) {
+hipError_t launch_xi2(lloid_dtype t, const MixJob *jobs, int n_jobs, int64_t n_windows, int kmax, int64_t acorr_max,
+                      float thr, const XiWork &xw, int n_cu, hipStream_t s) {
   if (n_windows <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)n_windows;   // one workgroup per (job, window)
   const int nks = kmax / 16;
-  if (t != LLOID_F32 && nks <= 32 && xw.cap > 0) {
+  // the tile launch indexes the autocorrelation tables with 32-bit offsets
+  if (t != LLOID_F32 && nks <= 32 && acorr_max <= INT_MAX && xw.cap > 0) {
     hipError_t e = launch_fill_u8(xw.counters, 2 * sizeof(int32_t), s);
     if (e != hipSuccess) return e;
     k_xi2_list<<<blocks, kXiThreads, 0, s>>>(jobs, n_jobs, thr, xw.units, xw.cap, xw.counters);
