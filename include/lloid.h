@@ -209,10 +209,12 @@ lloid_status lloid_bank_destroy(lloid_bank *bank);
  * after sample n-1) and reduce it to triggers.
  *   strain: host or device, n samples of `strain_dtype` (F64 or F32).
  *   opts:   window and threshold; NULL means 1 s windows and threshold 4.
- *   trig:   host, capacity trig_cap; *n_trig receives the number of
- *           triggers.  If it exceeds trig_cap the first trig_cap (in
+ *   trig:   host or device, capacity trig_cap; *n_trig receives the number
+ *           of triggers.  If it exceeds trig_cap the first trig_cap (in
  *           template-major, window-minor order) are written and ETRUNC is
- *           returned with *n_trig = the required count.
+ *           returned with *n_trig = the required count.  Device memory and
+ *           pinned host memory receive the records straight from the
+ *           compaction kernel; pageable host memory through a staged copy.
  *   snr:    NULL, or host or device [n_templates][n][2] float receiving the
  *           complex SNR (Re, Im) of every template at every sample.
  *   peaks:  NULL, or dense per-(template, window) peak outputs.
