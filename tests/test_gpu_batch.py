@@ -74,6 +74,41 @@ def test_batch_chunking_is_invisible():
     assert np.array_equal(big.triggers, small.triggers)
 
 
+@pytest.mark.parametrize("compute", ["f16", "f32"])
+def test_batch_signal_consistency_of_mixed_banks(compute):
+    """A batch whose banks 0 and 2 carry autocorrelations and bank 1 does
+    not: the signal-consistency launches take the jobs of two banks (units of
+    both in one list), in forced small chunks too; every bank's triggers,
+    xi2 included, equal that bank filtered alone, and bank 1's xi2 is 0."""
+    from paper_2410_16416_amd import lloid
+    from workloads import bank_autocorrelation
+    banks = [configs.small_uneven_bank(i) for i in range(3)]
+    for k in (0, 2):
+        banks[k].autocorr = bank_autocorrelation(banks[k], 12)
+    x = np.random.default_rng(9).standard_normal(9 * 1024 + 211)
+    log(f"[batch xi2] {compute}: " + " | ".join(b.describe() for b in banks))
+    handles = [lloid.bank_from_svd(ctx(), b, compute) for b in banks]
+    try:
+        alone = [lloid.lloid_filter(h, 0, x, window=(1, 4), threshold=3.0).triggers for h in handles]
+        for budget in (6 << 30, 200_000):
+            lloid.lloid_ctx_set_chunk_bytes(ctx(), budget)
+            t = lloid.lloid_filter_batch(handles, 0, x, window=(1, 4), threshold=3.0).triggers
+            for k in range(3):
+                got = t[t["bank"] == k]
+                want = alone[k]
+                assert got.shape[0] == want.shape[0] and got.shape[0] > 5, (budget, k)
+                for f in want.dtype.names:
+                    if f != "bank":
+                        assert np.array_equal(got[f], want[f]), (budget, k, f)
+            assert np.all(t["xi2"][t["bank"] == 1] == 0) and np.all(t["xi2"][t["bank"] != 1] > 0)
+    finally:
+        lloid.lloid_ctx_set_chunk_bytes(ctx(), 6 << 30)
+        for h in handles:
+            lloid.lloid_bank_destroy(h)
+        for k in (0, 2):
+            banks[k].autocorr = None
+
+
 def test_c3_shaped_banks_alone_equal_in_batch():
     """Eight banks of the batched recipe's shapes (uneven F, 1-4 slices, up to
     64 s filters), 70 s of strain: batch == alone bit for bit."""
