@@ -295,8 +295,6 @@ extern "C" lloid_status lloid_bank_create(lloid_ctx *ctx, const lloid_bank_desc 
     sl.lp = (int)round_up(in.n_basis, kLPad);
     sl.lrows = (int)round_up(in.n_basis, kRowTile);
     sl.np = (int)round_up(in.n_taps, kBK);
-    sl.koff = koff;
-    koff += sl.lp;
     lsum += in.n_basis;
     double mb = 0.0;
     for (int64_t i = 0; i < (int64_t)in.n_basis * in.n_taps; ++i) mb = std::max(mb, std::fabs(in.basis[i]));
@@ -306,10 +304,24 @@ extern "C" lloid_status lloid_bank_create(lloid_ctx *ctx, const lloid_bank_desc 
     b->n_levels = std::max(b->n_levels, sl.level + 1);
     b->slices.push_back(sl);
   }
-  // the last slice absorbs the padding of the concatenated K, so every column
-  // of the operand is written by a FIR or an interpolation stage
+  // Column order of the concatenated K: the lower-rate slices first, then
+  // the full-rate ones, so that the interpolation stage writes one run at the
+  // start of every operand row and shares fewer 128-byte lines with the
+  // FIR's columns (partly written lines slow its stores: 1.95 -> 2.77 TB/s
+  // measured for the 1024-template bank's layout).  The slice last in that
+  // order absorbs the padding of the concatenated K, so every column of the
+  // operand is written by a FIR or an interpolation stage.
+  std::vector<int> korder;
+  for (int s = 0; s < d->n_slices; ++s)
+    if (b->slices[s].level > 0) korder.push_back(s);
+  for (int s = 0; s < d->n_slices; ++s)
+    if (b->slices[s].level == 0) korder.push_back(s);
+  for (int s : korder) {
+    b->slices[s].koff = koff;
+    koff += b->slices[s].lp;
+  }
   b->kcat = (int)round_up(koff, kBK);
-  b->slices.back().lp += b->kcat - koff;
+  b->slices[korder.back()].lp += b->kcat - koff;
   for (auto &sl : b->slices) sl.lrows = (int)round_up(sl.lp, kRowTile);
   b->mix_scale = pow2_scale(max_mix);
 
