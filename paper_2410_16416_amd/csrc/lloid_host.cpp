@@ -321,6 +321,7 @@ extern "C" lloid_status lloid_bank_create(lloid_ctx *ctx, const lloid_bank_desc 
     koff += b->slices[s].lp;
   }
   b->kcat = (int)round_up(koff, kBK);
+  b->kld = (int)round_up(b->kcat, 64);
   b->slices[korder.back()].lp += b->kcat - koff;
   for (auto &sl : b->slices) sl.lrows = (int)round_up(sl.lp, kRowTile);
   b->mix_scale = pow2_scale(max_mix);
@@ -328,7 +329,7 @@ extern "C" lloid_status lloid_bank_create(lloid_ctx *ctx, const lloid_bank_desc 
   // Pack on the host in FP64, cast on the device.
   lloid_status status = LLOID_OK;
   double *dtmp = nullptr;
-  size_t tmp_elems = (size_t)b->rows * b->kcat;
+  size_t tmp_elems = (size_t)b->rows * b->kld;
   for (auto &sl : b->slices) tmp_elems = std::max(tmp_elems, (size_t)sl.lrows * sl.np);
   tmp_elems = std::max(tmp_elems, (size_t)2 * F * lsum + lsum + F);
   if (hipMalloc(&dtmp, tmp_elems * sizeof(double)) != hipSuccess) {
@@ -358,14 +359,14 @@ extern "C" lloid_status lloid_bank_create(lloid_ctx *ctx, const lloid_bank_desc 
         hipStreamSynchronize(st) != hipSuccess)
       return cleanup(fail(LLOID_EDEVICE, "basis upload failed"));
   }
-  host.assign((size_t)b->rows * b->kcat, 0.0);
+  host.assign((size_t)b->rows * b->kld, 0.0);
   for (int s = 0; s < d->n_slices; ++s) {
     const lloid_slice &in = d->slices[s];
     const SliceDev &sl = b->slices[s];
     const double f = b->mix_scale / sl.basis_scale;
     for (int r = 0; r < 2 * F; ++r)
       for (int l = 0; l < in.n_basis; ++l)
-        host[(size_t)r * b->kcat + sl.koff + l] = in.mixing[(size_t)r * in.n_basis + l] * f;
+        host[(size_t)r * b->kld + sl.koff + l] = in.mixing[(size_t)r * in.n_basis + l] * f;
   }
   if (hipMalloc(&b->mix, host.size() * esz) != hipSuccess) return cleanup(fail(LLOID_ENOMEM, "mixing alloc"));
   b->device_bytes += (int64_t)(host.size() * esz);
@@ -457,8 +458,10 @@ lloid_status lloid::ensure_pinned(lloid_ctx *ctx, void *&p, size_t &have, size_t
   return LLOID_OK;
 }
 
-bool lloid::operands_fit(const lloid_bank *b, int64_t t_len) {
-  if (t_len * b->kcat * (int64_t)dtype_size(b->compute) > kMaxBuffer) return false;
+bool lloid::operands_fit(const lloid_bank *b, int64_t t_len, int64_t win_len) {
+  // a resource over the operand spans at most one window and its margins
+  const int64_t span = std::min(t_len, win_len + 2 * operand_margin(b));
+  if (span * b->kld * (int64_t)dtype_size(b->compute) > kMaxBuffer) return false;
   for (const auto &sl : b->slices)
     if (sl.level > 0)
       for (int64_t ld : low_ld(t_len, sl.level))
@@ -518,7 +521,7 @@ void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, 
       j.k_hi = e1;
       j.out = bb.ocat;
       j.out_lo = e0;
-      j.ldo = b->kcat;
+      j.ldo = b->kld;
       j.col0 = sl.koff;
     } else {
       // FIR at the slice rate into a channel-major buffer, then the hops up to f0
@@ -549,7 +552,7 @@ void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, 
         if (h + 1 == H) {
           q.dst = bb.ocat;
           q.dst_abs0 = e0;
-          q.ld_dst = b->kcat;
+          q.ld_dst = b->kld;
           q.col0 = sl.koff;
           q.dst_tm = 1;
         } else {
@@ -592,6 +595,7 @@ void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, 
   m.inv_scale = inv_scale;
   m.rows = b->rows;
   m.kcat = b->kcat;
+  m.kld = b->kld;
   m.n_templates = b->n_templates;
   m.n_rtiles = (int)ceil_div(b->rows, ts.mbm);
   mj.push_back(m);
@@ -720,7 +724,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   const size_t esz = dtype_size(ct);
   int64_t bytes_per_sample = 0;
   for (int i = 0; i < nb; ++i) {
-    bytes_per_sample += banks[i]->kcat * (int64_t)esz;
+    bytes_per_sample += banks[i]->kld * (int64_t)esz;
     for (const auto &sl : banks[i]->slices)
       if (sl.level > 0) {
         // low-rate buffers: one per hop input, at that hop's source rate
@@ -733,10 +737,11 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
   wpc = std::min(wpc, W);
   // every buffer a kernel addresses through a buffer resource stays under 2 GiB
   for (int i = 0; i < nb; ++i)
-    while (wpc > 1 && !operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1) + 2 * operand_margin(banks[i])))
+    while (wpc > 1 &&
+           !operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1) + 2 * operand_margin(banks[i]), win_len))
       wpc = (wpc + 1) / 2;
   for (int i = 0; i < nb; ++i)
-    if (!operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1) + 2 * operand_margin(banks[i])))
+    if (!operands_fit(banks[i], std::min<int64_t>(n, win.start(wpc) + 1) + 2 * operand_margin(banks[i]), win_len))
       return fail(LLOID_EINVAL, "one trigger window of bank %d needs buffers over 2 GiB", i);
   const TileShapes ts(ct, ctx->fir_variant, ctx->mix_variant);
 
@@ -784,7 +789,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
       add(tab, 8);
       if (banks[i]->acorr) add(tab, 8);
       const int64_t ops = chunk_n_ + 2 * operand_margin(banks[i]);
-      add((size_t)ops * banks[i]->kcat, esz);
+      add((size_t)ops * banks[i]->kld, esz);
       for (const auto &sl : banks[i]->slices)
         if (sl.level > 0)
           for (int64_t ld : low_ld(ops, sl.level)) add((size_t)sl.lp * ld, low_esz(ct));
@@ -857,7 +862,7 @@ static lloid_status filter_banks(lloid_bank *const *banks, int nb, int32_t detec
     bw[i].ld_peak = W;
     bw[i].w_base = 0;
     const int64_t ops = chunk_n + 2 * operand_margin(banks[i]);
-    bw[i].ocat = cv.take<char>((size_t)ops * banks[i]->kcat * esz);
+    bw[i].ocat = cv.take<char>((size_t)ops * banks[i]->kld * esz);
     bw[i].low.assign(banks[i]->slices.size(), {});
     for (size_t s = 0; s < banks[i]->slices.size(); ++s) {
       const auto &sl = banks[i]->slices[s];

@@ -78,8 +78,9 @@ struct UpJob {
 
 // Mixing + peaks of one bank over trigger windows [w0, w0 + nw).
 struct MixJob {
-  const void *mix;       // [rows][kcat] compute type
-  const void *ocat;      // [..][kcat] compute type, absolute sample ocat_abs0 at row 0
+  const void *mix;       // [rows][kld] compute type (columns past kcat are zeros)
+  const void *ocat;      // [..][kld] compute type, absolute sample ocat_abs0 at row 0;
+                         // columns past kcat are never read
   float *peak_snr;       // [F][ld_peak], column w - w_base
   int64_t *peak_n;
   float *peak_phase;
@@ -94,6 +95,7 @@ struct MixJob {
   int64_t *xi_key;            // listing slab [ld_peak][n_templates] of trigger keys (banks with lags)
   float inv_scale;
   int rows, kcat, n_templates, n_rtiles, acorr_half;
+  int kld;                    // row pitch of mix and ocat (kcat rounded up to 64)
 };
 
 // One unit of the signal-consistency tiles: triggers first .. first + n - 1
@@ -160,9 +162,12 @@ struct lloid_bank {
   lloid_dtype compute = LLOID_F16;
   std::vector<lloid::SliceDev> slices;
   int kcat = 0;             // concatenated K (multiple of kBK)
+  int kld = 0;              // row pitch of mix and of the operand: kcat rounded up
+                            // to 64 elements, so that operand rows start on 128-byte
+                            // lines for 16-bit types
   int rows = 0;             // 2F rounded up to the mixing row tile
   float mix_scale = 1;      // power of two applied to the mixing matrix
-  void *mix = nullptr;      // [rows][kcat] compute type
+  void *mix = nullptr;      // [rows][kld] compute type, zeros past kcat
   std::vector<double> sigma2;
   int64_t device_bytes = 0;
 };
@@ -281,7 +286,7 @@ struct LevelView {
 
 // Per (bank, detector) buffers of one chunk of windows.
 struct BankBufs {
-  void *ocat = nullptr;            // [chunk samples][kcat]
+  void *ocat = nullptr;            // [chunk samples][kld]
   std::vector<std::vector<void *>> low;  // per slice at level > 0: FIR output, then each
                                          // interpolation hop's output except the last
   float *psnr = nullptr, *pphase = nullptr, *pdt = nullptr, *psi = nullptr, *pxi = nullptr;
@@ -317,11 +322,15 @@ struct TabOffsets {
 
 lloid_status ensure_ws(lloid_ctx *ctx, Workspace &ws, size_t bytes);
 lloid_status ensure_pinned(lloid_ctx *ctx, void *&p, size_t &have, size_t bytes);
-// Buffer resources address 32-bit byte offsets: operand and low-rate buffers
-// of a chunk stay below kMaxBuffer bytes, level buffers below 2^30 bytes.
+// Buffer resources address 32-bit byte offsets: a resource over the operand
+// spans one trigger window plus its margins, and stays below kMaxBuffer bytes
+// (the operand of a chunk itself is addressed with 64-bit pointers); the
+// low-rate buffers of a chunk stay below kMaxBuffer bytes, level buffers below
+// 2^30 bytes.
 constexpr int64_t kMaxBuffer = (int64_t(1) << 31) - (int64_t(1) << 24);
 constexpr int64_t kMaxBlock = int64_t(1) << 28;   // samples of one filter call
-bool operands_fit(const lloid_bank *b, int64_t t_len);
+// t_len: operand rows of the chunk; win_len: samples of one trigger window
+bool operands_fit(const lloid_bank *b, int64_t t_len, int64_t win_len);
 // Composite interpolation filter of log2(R) cascaded half-band x2 stages
 // (h_2[t] = 2 g[t], h_2R[t] = sum_m 2 g[m] h_R[t - R m]) laid out as MFMA B
 // fragments: entry (ks, lane, j) holds h_R[lane % 32 - R kk + 32 R - 32] with

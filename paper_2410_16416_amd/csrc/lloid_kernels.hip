@@ -549,7 +549,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mix_peak(const MixJob *__restr
   if (wl >= jb.nw) return;
   const int64_t w = jb.w0 + wl;
   const T *mix = (const T *)jb.mix;
-  const int rows = jb.rows, kcat = jb.kcat, n_templates = jb.n_templates;
+  const int rows = jb.rows, kcat = jb.kcat, kld = jb.kld, n_templates = jb.n_templates;
   const float inv_scale = jb.inv_scale;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mix_peak(const MixJob *__restr
   const int64_t ws = (w * jb.win_p) / jb.win_q;
   int64_t we = ((w + 1) * jb.win_p) / jb.win_q;
   if (we > jb.n_end) we = jb.n_end;
-  const T *ocat = (const T *)jb.ocat + (ws - jb.ocat_abs0) * (int64_t)kcat;   // row of sample ws
+  const T *ocat = (const T *)jb.ocat + (ws - jb.ocat_abs0) * (int64_t)kld;   // row of sample ws
   VN best[MT][8];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -568,19 +568,20 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mix_peak(const MixJob *__restr
   // mixing rows [r0, rows) and operand rows [ws, we) of this workgroup; rows
   // past either end read as zero
   constexpr int ESZ = (int)sizeof(T);
-  const __amdgpu_buffer_rsrc_t ra = make_rsrc(mix + r0 * kcat, (rows - r0) * (int64_t)kcat * ESZ);
-  const __amdgpu_buffer_rsrc_t rb = make_rsrc(ocat, (we - ws) * (int64_t)kcat * ESZ);
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(mix + r0 * kld, (rows - r0) * (int64_t)kld * ESZ);
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(ocat, (we - ws) * (int64_t)kld * ESZ);
   // kcat is a multiple of 32; with BK = 64 the k-steps past kcat are skipped
+  // (the rows' pitch kld is a multiple of 64: the chunks stay inside a row)
   const int nchunks = (kcat + BK - 1) / BK;
   ChunkLoader<T, BM, BK, THREADS> la;
   ChunkLoader<T, BN, BK, THREADS> lb;
-  la.setup(kcat);
-  lb.setup(kcat);
+  la.setup(kld);
+  lb.setup(kld);
   la.load(ra, 0);
   lb.load(rb, 0);
   int it = 0;  // chunk counter across column steps: LDS buffer parity
   for (int64_t n0 = ws; n0 < we; n0 += BN) {
-    const int brow = (int)(n0 - ws) * kcat * ESZ;   // byte offset of this step's first operand row
+    const int brow = (int)(n0 - ws) * kld * ESZ;   // byte offset of this step's first operand row
     f32x16 acc[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mix_peak(const MixJob *__restr
         lb.load(rb, brow + (c + 1) * BK * ESZ);
       } else if (n0 + BN < we) {
         la.load(ra, 0);
-        lb.load(rb, brow + BN * kcat * ESZ);
+        lb.load(rb, brow + BN * kld * ESZ);
       }
 #pragma unroll
       for (int ks = 0; ks < BK / O::KS; ++ks) {
@@ -771,7 +772,7 @@ __global__ __launch_bounds__(64 * WM * WN, WGS) void k_mix_dl(const MixJob *__re
   if (wl >= jb.nw) return;
   const int64_t w = jb.w0 + wl;
   const T *mix = (const T *)jb.mix;
-  const int rows = jb.rows, kcat = jb.kcat, n_templates = jb.n_templates;
+  const int rows = jb.rows, kcat = jb.kcat, kld = jb.kld, n_templates = jb.n_templates;
   const float inv_scale = jb.inv_scale;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -780,7 +781,7 @@ __global__ __launch_bounds__(64 * WM * WN, WGS) void k_mix_dl(const MixJob *__re
   const int64_t ws = (w * jb.win_p) / jb.win_q;
   int64_t we = ((w + 1) * jb.win_p) / jb.win_q;
   if (we > jb.n_end) we = jb.n_end;
-  const T *ocat = (const T *)jb.ocat + (ws - jb.ocat_abs0) * (int64_t)kcat;
+  const T *ocat = (const T *)jb.ocat + (ws - jb.ocat_abs0) * (int64_t)kld;
   VN best[MT][8];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -788,8 +789,10 @@ __global__ __launch_bounds__(64 * WM * WN, WGS) void k_mix_dl(const MixJob *__re
     for (int p = 0; p < 8; ++p) best[mt][p] = VN{-1.f, 0x7fffffff};
 
   constexpr int ESZ = 2;
-  const __amdgpu_buffer_rsrc_t ra = make_rsrc(mix + r0 * kcat, (rows - r0) * (int64_t)kcat * ESZ);
-  const __amdgpu_buffer_rsrc_t rb = make_rsrc(ocat, (we - ws) * (int64_t)kcat * ESZ);
+  // rows of pitch kld (a multiple of 64 elements: every chunk row is one
+  // 128-byte line of a line-aligned row)
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(mix + r0 * kld, (rows - r0) * (int64_t)kld * ESZ);
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(ocat, (we - ws) * (int64_t)kld * ESZ);
   const int nchunks = (kcat + BK - 1) / BK;
   const bool half_tail = (kcat % BK) != 0;   // K chunks of 64: the last one holds 32 columns
   const int nsteps = (int)((we - ws + BN - 1) / BN);
@@ -801,13 +804,13 @@ __global__ __launch_bounds__(64 * WM * WN, WGS) void k_mix_dl(const MixJob *__re
   // and the row step goes into the scalar offset.
   const int vrow = R::RPI * wave + lane / R::CPR;
   const int lq = R::swz(vrow, lane % R::CPR);
-  const int voffs = vrow * kcat * ESZ + lq * 16;
+  const int voffs = vrow * kld * ESZ + lq * 16;
   const int voffs_tail = lq < R::CPR / 2 ? voffs : 0x7ff00000;   // upper half of a half chunk: zeros
-  const int jstep = R::RPI * NW * kcat * ESZ;
+  const int jstep = R::RPI * NW * kld * ESZ;
   auto issue = [&](int g) {
     const int c = g % nchunks, st = g / nchunks;
     const int ka = c * BK * ESZ;
-    const int kb = st * BN * kcat * ESZ + ka;
+    const int kb = st * BN * kld * ESZ + ka;
     const int vo = (half_tail && c == nchunks - 1) ? voffs_tail : voffs;
     char *at = (g & 1) ? As1 : As0;
     char *bt = (g & 1) ? Bs1 : Bs0;
@@ -983,7 +986,7 @@ __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ j
     int jx[2];
     int64_t ox[2];
     const uint4 *mc[2], *ms[2], *o0[2];
-    int nv[2];
+    int nv[2], pv[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       jx[t] = __builtin_amdgcn_readlane(job, src[t]);
@@ -992,11 +995,12 @@ __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ j
                         (uint32_t)__builtin_amdgcn_readlane((int)row, src[t]);
       ox[t] = ((int64_t)__builtin_amdgcn_readlane((int)(o >> 32), src[t]) << 32) |
               (uint32_t)__builtin_amdgcn_readlane((int)o, src[t]);
-      const int kcat = jb.kcat;   // a multiple of 32: rows are whole 16-byte vectors
-      nv[t] = kcat / EPV;
-      o0[t] = (const uint4 *)((const T *)jb.ocat + (jb.peak_n[ox[t]] - 1 - jb.ocat_abs0) * (int64_t)kcat);
-      mc[t] = (const uint4 *)((const T *)jb.mix + (2 * r) * (int64_t)kcat);
-      ms[t] = mc[t] + nv[t];
+      // kcat and the row pitch kld are multiples of 32: whole 16-byte vectors
+      nv[t] = jb.kcat / EPV;
+      pv[t] = jb.kld / EPV;
+      o0[t] = (const uint4 *)((const T *)jb.ocat + (jb.peak_n[ox[t]] - 1 - jb.ocat_abs0) * (int64_t)jb.kld);
+      mc[t] = (const uint4 *)((const T *)jb.mix + (2 * r) * (int64_t)jb.kld);
+      ms[t] = mc[t] + pv[t];
 #pragma unroll
       for (int q = 0; q < 6; ++q) acc[t][q] = 0.f;
     }
@@ -1010,7 +1014,7 @@ __global__ __launch_bounds__(256) void k_peak_phase(const MixJob *__restrict__ j
         c[t] = __builtin_bit_cast(Vec16<T>, mc[t][kk]);
         d[t] = __builtin_bit_cast(Vec16<T>, ms[t][kk]);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) a[t][q] = __builtin_bit_cast(Vec16<T>, o0[t][q * nv[t] + kk]);
+        for (int q = 0; q < 3; ++q) a[t][q] = __builtin_bit_cast(Vec16<T>, o0[t][q * pv[t] + kk]);
         if (!ok) c[t] = d[t] = Vec16<T>{};
       }
 #pragma unroll
@@ -1191,7 +1195,7 @@ __global__ __launch_bounds__(kXiThreads) void k_xi2(const MixJob *__restrict__ j
       // A rows: lane row rr = lane % 32 is cos (even) or sin (odd) of trigger rr / 2
       const int tr = (lane & 31) >> 1;
       const int64_t ir = l_key[t0 + (tr < nt ? tr : 0)] & 0xffffffff;
-      const T *arow = mix + (2 * ir + (lane & 1)) * (int64_t)kcat + (lane >> 5) * O::VEC;
+      const T *arow = mix + (2 * ir + (lane & 1)) * (int64_t)jb.kld + (lane >> 5) * O::VEC;
       // the eight triggers of this lane's accumulator pairs: rows 8 (e/4) + 4 (lane/32) + e%4
       int64_t ns[8], ii[8];
       float2 zs[8];
@@ -1219,7 +1223,7 @@ __global__ __launch_bounds__(kXiThreads) void k_xi2(const MixJob *__restrict__ j
         for (int64_t s0 = a0; s0 < a1; s0 += 32) {
           const int64_t n = s0 + (lane & 31);
           const int64_t nb = n < a1 ? n : a1 - 1;
-          const T *brow = ocat + (nb - jb.ocat_abs0) * (int64_t)kcat + (lane >> 5) * O::VEC;
+          const T *brow = ocat + (nb - jb.ocat_abs0) * (int64_t)jb.kld + (lane >> 5) * O::VEC;
           // two accumulators (even and odd k-steps) halve the MFMA dependency
           // chain.  Blocks of U k-steps issue all their reads before their MFMAs;
           // in the last block the k-steps past nks read k-step nks - 1 (in
@@ -1409,7 +1413,7 @@ __global__ __launch_bounds__(kXiThreads, 2) void k_xi2_tiles(const MixJob *__res
     {
       const int tr = 16 * wave + (fr >> 1);
       const int64_t i = s_key[tr < nt_u ? tr : 0] & 0xffffffff;
-      const T *arow = (const T *)jb.mix + (2 * i + (lane & 1)) * (int64_t)kcat + fh * 8;
+      const T *arow = (const T *)jb.mix + (2 * i + (lane & 1)) * (int64_t)jb.kld + fh * 8;
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) {
         const vec v = *(const vec *)(arow + min(ks, nks - 1) * 16);
@@ -1426,10 +1430,13 @@ __global__ __launch_bounds__(kXiThreads, 2) void k_xi2_tiles(const MixJob *__res
     // resource ends at the unit's last sample: rows past it load zeros, and
     // so do the blocks past the tile's nblk (into Bx past kXiTileBlocks).
     const int cpr = kcat / 8, P = cpr + 1, nblk = (32 * P + 63) / 64;
-    const int rowbytes = kcat * 2;
-    const __amdgpu_buffer_rsrc_t rb = make_rsrc(jb.ocat, (ba1 - jb.ocat_abs0) * (int64_t)rowbytes);
+    // the resource starts at the unit's first operand row (its extent is the
+    // unit's lag range, not the whole operand)
+    const int rowbytes = jb.kld * 2;   // operand row pitch
+    const __amdgpu_buffer_rsrc_t rb =
+        make_rsrc((const T *)jb.ocat + (ba0 - jb.ocat_abs0) * (int64_t)jb.kld, (ba1 - ba0) * (int64_t)rowbytes);
     const int dr = 256 / P, dq = 256 - dr * P;
-    const int base0 = (int)(ba0 - jb.ocat_abs0) * rowbytes;
+    const int base0 = 0;
     auto issue = [&](int j) {
       // the chunk positions are recomputed per tile (a few ALU operations per
       // load) rather than held in registers across the loop

@@ -151,7 +151,7 @@ int64_t margin_at(int k) { return ((2 * (int64_t)kMaxAutocorrHalf + 2) >> k) + 1
 // device bytes one active bank needs beyond its own arrays: per-tick scratch of every detector
 int64_t scratch_bytes(const lloid_stream *s, const lloid_bank *b) {
   const int64_t ts = tick_samples(s) + 2 * operand_margin(b);
-  int64_t per = (int64_t)ts * b->kcat * (int64_t)dtype_size(b->compute);
+  int64_t per = (int64_t)ts * b->kld * (int64_t)dtype_size(b->compute);
   for (const auto &sl : b->slices)
     if (sl.level > 0)
       for (int64_t ld : low_ld(ts, sl.level)) per += (int64_t)sl.lp * ld * (int64_t)low_esz(b->compute) + 256;
@@ -165,7 +165,7 @@ lloid_status check_bank(const lloid_stream *s, const lloid_bank *b) {
   if (b->f0 != s->f0) return fail(LLOID_EINVAL, "the bank's full rate differs from the stream's");
   if (b->compute != s->ct) return fail(LLOID_EINVAL, "the bank's compute type differs from the stream's");
   if (b->n_levels > s->n_levels) return fail(LLOID_EINVAL, "the bank's lowest rate is below the stream's");
-  if (!operands_fit(b, tick_samples(s) + 2 * operand_margin(b)))
+  if (!operands_fit(b, tick_samples(s) + 2 * operand_margin(b), s->win_len))
     return fail(LLOID_EINVAL, "the bank's per-tick buffers exceed 2 GiB");
   for (const auto &sl : b->slices) {
     const int64_t span = sl.start_tap / sl.dec + sl.n_taps + 4 * kHalfQ;
@@ -337,7 +337,7 @@ lloid_status enqueue_tick(lloid_stream *s, int64_t wa, int64_t wb, Clock::time_p
   for (const lloid_bank *b : bank_of) {
     for (int d = 0; d < s->n_det; ++d) {
       const int64_t ops = tlen + 2 * operand_margin(b);
-      add((size_t)ops * b->kcat, esz);
+      add((size_t)ops * b->kld, esz);
       for (const auto &sl : b->slices) {
         ++n_fir;
         if (sl.level > 0)
@@ -396,7 +396,7 @@ lloid_status enqueue_tick(lloid_stream *s, int64_t wa, int64_t wb, Clock::time_p
     for (int d = 0; d < s->n_det; ++d) {
       BankBufs bb;
       const int64_t ops = tlen + 2 * operand_margin(b);
-      bb.ocat = cv.take<char>((size_t)ops * b->kcat * esz);
+      bb.ocat = cv.take<char>((size_t)ops * b->kld * esz);
       bb.low.assign(b->slices.size(), {});
       for (size_t k = 0; k < b->slices.size(); ++k)
         if (b->slices[k].level > 0)

@@ -183,6 +183,14 @@ def test_edge_cases_short_inputs_and_errors():
         with pytest.raises(lloid.LloidError) as ei:
             lloid.lloid_filter(b, 0, x[:100], window=(1, 10), strain_scale=3.0)
         assert ei.value.status == lloid.LLOID_EINVAL
+        # one window whose operand rows exceed what a buffer resource spans
+        # (2^31 - 2^24 bytes) is refused before any device work; a block whose
+        # whole operand exceeds it in windows of ordinary length is not (the
+        # full-size 1024-template runs below are such blocks)
+        long = np.zeros((1 << 24) + (1 << 20), dtype=np.float32)
+        with pytest.raises(lloid.LloidError) as ei:
+            lloid.lloid_filter(b, 0, long, window=(20000, 1))
+        assert ei.value.status == lloid.LLOID_EINVAL
     finally:
         lloid.lloid_bank_destroy(b)
     sl = wl.bank.slices[0]
