@@ -153,15 +153,16 @@ extern "C" lloid_status lloid_ctx_create(int device, void *hip_stream, lloid_ctx
     return fail(LLOID_EDEVICE, "cannot upload resampler taps");
   }
   // composite interpolation filters as MFMA fragments: FP32 32x32x2 (KS 2,
-  // one value per lane; also used by BF16 operands, whose low-rate buffers
-  // are FP32) and FP16 32x32x16 (KS 16, eight values per lane); 2048 entries
-  // each, built in FP64 and rounded on the device
+  // one value per lane; the FP32 operand path), FP16 32x32x16 (KS 16, eight
+  // values per lane) and, for the BF16 operand path (whose low-rate buffers
+  // are FP32), the 32x32x16 layout split into BF16 hi and lo tables;
+  // kInterpFragEntries entries each, built in FP64
   {
-    constexpr size_t kEnt = 2048, kSlot = kEnt * 4;
+    constexpr size_t kEnt = kInterpFragEntries, kSlot = kEnt * 4;
     const lloid_dtype types[2] = {LLOID_F32, LLOID_F16};
     char *mem = nullptr;
     double *tmp = nullptr;
-    bool ok = hipMalloc((void **)&mem, 4 * kSlot) == hipSuccess && hipMalloc((void **)&tmp, kEnt * 8) == hipSuccess;
+    bool ok = hipMalloc((void **)&mem, 6 * kSlot) == hipSuccess && hipMalloc((void **)&tmp, kEnt * 8) == hipSuccess;
     std::vector<double> frag;
     for (int ti = 0; ti < 2 && ok; ++ti)
       for (int ri = 0; ri < 2 && ok; ++ri) {
@@ -173,6 +174,31 @@ extern "C" lloid_status lloid_ctx_create(int device, void *hip_stream, lloid_ctx
              launch_cast_f64(tmp, types[ti], c->d_hfrag[ti][ri], (int64_t)kEnt, c->stream) == hipSuccess &&
              hipStreamSynchronize(c->stream) == hipSuccess;
       }
+    // BF16 split: hi = bf16(h) (round to nearest even), lo = bf16(h - hi)
+    auto bf16_bits = [](float f) -> uint16_t {
+      uint32_t u;
+      std::memcpy(&u, &f, 4);
+      u += 0x7fffu + ((u >> 16) & 1u);
+      return (uint16_t)(u >> 16);
+    };
+    auto bf16_value = [](uint16_t h) -> float {
+      const uint32_t u = (uint32_t)h << 16;
+      float f;
+      std::memcpy(&f, &u, 4);
+      return f;
+    };
+    for (int ri = 0; ri < 2 && ok; ++ri) {
+      interp_fragments(c->halfband, ri == 0 ? 2 : 4, 16, 8, frag);
+      std::vector<uint16_t> split(2 * kEnt);
+      for (size_t q = 0; q < kEnt && q < frag.size(); ++q) {
+        const float f = (float)frag[q];
+        split[q] = bf16_bits(f);
+        split[kEnt + q] = bf16_bits(f - bf16_value(split[q]));
+      }
+      c->d_hfrag[2][ri] = mem + (4 + ri) * kSlot;
+      ok = frag.size() == kEnt &&
+           hipMemcpy(c->d_hfrag[2][ri], split.data(), split.size() * 2, hipMemcpyHostToDevice) == hipSuccess;
+    }
     if (tmp) (void)hipFree(tmp);
     if (!ok) {
       if (mem) (void)hipFree(mem);
@@ -503,7 +529,8 @@ void lloid::add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, 
   const int64_t mg = operand_margin(b);
   const int64_t e0 = t0 - mg, e1 = t1 + mg;
   const size_t lsz = low_esz(b->compute);
-  const int ti = b->compute == LLOID_F16 ? 1 : 0;   // BF16 interpolates FP32 buffers
+  // BF16 interpolates FP32 buffers with split-BF16 products
+  const int ti = b->compute == LLOID_F16 ? 1 : b->compute == LLOID_BF16 ? 2 : 0;
   for (size_t s = 0; s < b->slices.size(); ++s) {
     const SliceDev &sl = b->slices[s];
     FirJob j{};

@@ -137,8 +137,9 @@ struct lloid_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   float *d_halfband = nullptr;  // device copy of g[n] (kHalfTaps floats)
-  void *d_hfrag[2][2] = {};     // composite interpolation filters as MFMA fragments,
-                                // [F32, F16][R = 2, 4], in one allocation at d_hfrag[0][0]
+  void *d_hfrag[3][2] = {};     // composite interpolation filters as MFMA fragments,
+                                // [F32, F16, BF16 hi/lo split][R = 2, 4], in one
+                                // allocation at d_hfrag[0][0]
   double halfband[lloid::kHalfTaps];
   int n_cu = 0;
   lloid::Workspace ws;          // grow-only device scratch of filter calls on this context
@@ -336,6 +337,9 @@ bool operands_fit(const lloid_bank *b, int64_t t_len, int64_t win_len);
 // fragments: entry (ks, lane, j) holds h_R[lane % 32 - R kk + 32 R - 32] with
 // kk = ks * KS + (lane / 32) * VEC + j.
 void interp_fragments(const double *g, int R, int ks_elems, int vec, std::vector<double> &out);
+// Entries of one fragment table (64 composite taps x 32 output samples); the
+// BF16 split table holds the hi entries, then the lo entries.
+constexpr int kInterpFragEntries = 2048;
 // Append the FIR, interpolation and mixing jobs of bank b for output samples
 // [t0, t1) (windows [wa, wb), data ending at n_end) to the tables.
 void add_bank_jobs(const lloid_bank *b, const LevelView *lv, int64_t t0, int64_t t1, int64_t n_end, int64_t wa,

@@ -430,6 +430,67 @@ __device__ __forceinline__ void upsample_blocks(__amdgpu_buffer_rsrc_t rs, int64
   }
 }
 
+// FP32 sources of the BF16 operand path: every source value x and filter
+// tap h is split into a BF16 pair, x = x_hi + x_lo with x_hi = bf16(x) and
+// x_lo = bf16(x - x_hi) (16 significant bits), and a product takes three
+// BF16 MFMAs, x_hi h_hi + x_lo h_hi + x_hi h_lo (the dropped x_lo h_lo and
+// the splits' remainders are of order 2^-16 relative), with FP32 sums: the
+// 32x32x16 instruction in place of eight FP32 32x32x2 ones per k-step.
+// Blocks are 8 source samples (two 16-byte reads), laid out as for 16-bit
+// sources; hf holds the filter's hi fragments, then its lo fragments.
+struct uint4x2 {
+  __attribute__((ext_vector_type(4))) unsigned int a, b;
+};
+
+template <bool TM, int SB>
+__device__ __forceinline__ void upsample_blocks_split(__amdgpu_buffer_rsrc_t rs, int64_t base0, const bf16x8 *hhi,
+                                                      const bf16x8 *hlo, f32x16 *acc) {
+  constexpr int NKS = 4, CT = kUpCols / 32;
+  constexpr int NB = 2 * (NKS - 1) + SB * (CT - 1) + 1;
+  typedef float f32x8 __attribute__((ext_vector_type(8)));
+  f32x8 raw[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (SB % 2 == 0 && (j & 1)) continue;
+    const int off = (int)((base0 + j * 8) * (int64_t)sizeof(float));
+    const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0);
+    raw[j] = __builtin_bit_cast(f32x8, (uint4x2{v0, v1}));
+  }
+  __builtin_amdgcn_sched_barrier(0);   // keep every read ahead of the MFMAs
+  bf16x8 xhi[NB], xlo[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (SB % 2 == 0 && (j & 1)) continue;
+    __bf16 h[8], l[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      h[e] = (__bf16)raw[j][e];
+      l[e] = (__bf16)(raw[j][e] - (float)h[e]);
+    }
+    xhi[j] = __builtin_bit_cast(bf16x8, h);
+    xlo[j] = __builtin_bit_cast(bf16x8, l);
+  }
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int j = 2 * ks + SB * t;
+      if (TM) {
+        acc[t] = Op<__bf16>::mfma(hlo[ks], xhi[j], acc[t]);
+        acc[t] = Op<__bf16>::mfma(hhi[ks], xlo[j], acc[t]);
+        acc[t] = Op<__bf16>::mfma(hhi[ks], xhi[j], acc[t]);
+      } else {
+        acc[t] = Op<__bf16>::mfma(xhi[j], hlo[ks], acc[t]);
+        acc[t] = Op<__bf16>::mfma(xlo[j], hhi[ks], acc[t]);
+        acc[t] = Op<__bf16>::mfma(xhi[j], hhi[ks], acc[t]);
+      }
+    }
+  }
+}
+
 template <typename TS, typename TD, bool TM>
 __device__ __forceinline__ void upsample_task(const UpJob &jb, int lane, int r0, int64_t n0) {
   typedef Op<TS> O;
@@ -438,18 +499,33 @@ __device__ __forceinline__ void upsample_task(const UpJob &jb, int lane, int r0,
   const int R = jb.r;
   const int lgR = R == 4 ? 2 : 1;  // R is 2 or 4: shifts, not 64-bit divisions (their
                                    // branches would keep the tiles' reads apart)
-  const TS *hf = (const TS *)jb.hf;
-  typename O::vec hfr[NKS];
-#pragma unroll
-  for (int ks = 0; ks < NKS; ++ks) hfr[ks] = *(const typename O::vec *)(hf + (ks * 64 + lane) * O::VEC);
+  // FP32 sources feeding BF16 operands take the split-BF16 products
+  constexpr bool SPLIT = std::is_same<TS, float>::value && std::is_same<TD, __bf16>::value;
   const int cR = 32 - 32 / R;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(jb.src, jb.src_bytes);
   const int64_t rowoff = (int64_t)(r0 + (lane & 31)) * jb.ld_src;
   f32x16 acc[CT];
-  const int64_t base0 = rowoff + (((n0 >> lgR) - cR) - jb.src_lo) + (lane >> 5) * O::VEC;
-  constexpr int SB4 = 8 / O::VEC;   // 32 / R in VEC blocks for R = 4; twice that for R = 2
-  if (R == 4) upsample_blocks<TS, TM, SB4>(rs, base0, hfr, acc);
-  else upsample_blocks<TS, TM, 2 * SB4>(rs, base0, hfr, acc);
+  if constexpr (SPLIT) {
+    const __bf16 *hf = (const __bf16 *)jb.hf;
+    bf16x8 hhi[4], hlo[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      hhi[ks] = *(const bf16x8 *)(hf + (ks * 64 + lane) * 8);
+      hlo[ks] = *(const bf16x8 *)(hf + kInterpFragEntries + (ks * 64 + lane) * 8);
+    }
+    const int64_t base0 = rowoff + (((n0 >> lgR) - cR) - jb.src_lo) + (lane >> 5) * 8;
+    if (R == 4) upsample_blocks_split<TM, 1>(rs, base0, hhi, hlo, acc);
+    else upsample_blocks_split<TM, 2>(rs, base0, hhi, hlo, acc);
+  } else {
+    const TS *hf = (const TS *)jb.hf;
+    typename O::vec hfr[NKS];
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) hfr[ks] = *(const typename O::vec *)(hf + (ks * 64 + lane) * O::VEC);
+    const int64_t base0 = rowoff + (((n0 >> lgR) - cR) - jb.src_lo) + (lane >> 5) * O::VEC;
+    constexpr int SB4 = 8 / O::VEC;   // 32 / R in VEC blocks for R = 4; twice that for R = 2
+    if (R == 4) upsample_blocks<TS, TM, SB4>(rs, base0, hfr, acc);
+    else upsample_blocks<TS, TM, 2 * SB4>(rs, base0, hfr, acc);
+  }
   if constexpr (TM) {
     // lane holds channel r0 + lane % 32 at samples n0 + 32 t + 8 g + 4 (lane / 32) + q
     const int c = r0 + (lane & 31);
