@@ -712,8 +712,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mix_peak(const MixJob *__restr
           if (ok && v > best[mt][p].v) best[mt][p] = VN{v, rel};
           if (SNR && ok) {
             const int64_t i = (r0 + wm * 32 * MT + mt * 32 + 8 * (p >> 1) + 4 * (lane >> 5) + 2 * (p & 1)) >> 1;
-            if (i < n_templates)
-              *(float2 *)(jb.snr + (i * jb.snr_ld + (col - jb.snr_abs0)) * 2) = make_float2(re * inv_scale, im * inv_scale);
+            if (i < n_templates) {
+              // written once and not read here: a non-temporal store
+              typedef float fv2 __attribute__((ext_vector_type(2)));
+              __builtin_nontemporal_store(fv2{re * inv_scale, im * inv_scale},
+                                          (fv2 *)(jb.snr + (i * jb.snr_ld + (col - jb.snr_abs0)) * 2));
+            }
           }
         }
       }
