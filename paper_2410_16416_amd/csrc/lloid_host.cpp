@@ -174,27 +174,11 @@ extern "C" lloid_status lloid_ctx_create(int device, void *hip_stream, lloid_ctx
              launch_cast_f64(tmp, types[ti], c->d_hfrag[ti][ri], (int64_t)kEnt, c->stream) == hipSuccess &&
              hipStreamSynchronize(c->stream) == hipSuccess;
       }
-    // BF16 split: hi = bf16(h) (round to nearest even), lo = bf16(h - hi)
-    auto bf16_bits = [](float f) -> uint16_t {
-      uint32_t u;
-      std::memcpy(&u, &f, 4);
-      u += 0x7fffu + ((u >> 16) & 1u);
-      return (uint16_t)(u >> 16);
-    };
-    auto bf16_value = [](uint16_t h) -> float {
-      const uint32_t u = (uint32_t)h << 16;
-      float f;
-      std::memcpy(&f, &u, 4);
-      return f;
-    };
+    // BF16 split tables: the hi halves, then the lo halves
     for (int ri = 0; ri < 2 && ok; ++ri) {
       interp_fragments(c->halfband, ri == 0 ? 2 : 4, 16, 8, frag);
       std::vector<uint16_t> split(2 * kEnt);
-      for (size_t q = 0; q < kEnt && q < frag.size(); ++q) {
-        const float f = (float)frag[q];
-        split[q] = bf16_bits(f);
-        split[kEnt + q] = bf16_bits(f - bf16_value(split[q]));
-      }
+      for (size_t q = 0; q < kEnt && q < frag.size(); ++q) bf16_split((float)frag[q], &split[q], &split[kEnt + q]);
       c->d_hfrag[2][ri] = mem + (4 + ri) * kSlot;
       ok = frag.size() == kEnt &&
            hipMemcpy(c->d_hfrag[2][ri], split.data(), split.size() * 2, hipMemcpyHostToDevice) == hipSuccess;

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstring>
 
 namespace lloid {
 
@@ -120,6 +121,25 @@ int64_t ready_until(const ReadyState &st) {
     if (st.n_end >= 0 && t1 >= st.n_end) break;
   }
   return best;
+}
+
+static uint16_t bf16_round(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest, ties to even (finite values)
+  return (uint16_t)(u >> 16);
+}
+
+float bf16_value(uint16_t bits) {
+  const uint32_t u = (uint32_t)bits << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+void bf16_split(float x, uint16_t *hi, uint16_t *lo) {
+  *hi = bf16_round(x);
+  *lo = bf16_round(x - bf16_value(*hi));   // exact in FP32: x and hi share the exponent range
 }
 
 }  // namespace lloid

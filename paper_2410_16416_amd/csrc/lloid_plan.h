@@ -116,4 +116,11 @@ struct ReadyState {
 };
 int64_t ready_until(const ReadyState &st);
 
+// BF16 (8-bit significand) pair of a finite FP32 value, as bit patterns:
+// hi = x rounded to nearest (ties to even), lo = (x - hi) rounded likewise,
+// so that hi + lo carries 16 significant bits of x (the interpolation
+// filters of the BF16 operand path are split this way).
+void bf16_split(float x, uint16_t *hi, uint16_t *lo);
+float bf16_value(uint16_t bits);
+
 }  // namespace lloid

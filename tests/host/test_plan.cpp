@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <random>
@@ -244,7 +245,52 @@ static void test_ready_until() {
   }
 }
 
+// bf16_split against rounding written out in double arithmetic: the two
+// BF16 neighbours of x (8-bit significands) and the nearer one, ties to the
+// even significand; then the error bound of the pair
+static double bf_bf16_round(double x) {
+  if (x == 0.0) return 0.0;
+  const double ax = std::fabs(x);
+  int e;
+  std::frexp(ax, &e);                     // ax in [2^(e-1), 2^e)
+  const double ulp = std::ldexp(1.0, e - 8);
+  const double lo = std::floor(ax / ulp) * ulp, hi = lo + ulp;
+  double r;
+  if (ax - lo < hi - ax) r = lo;
+  else if (ax - lo > hi - ax) r = hi;
+  else r = (std::fmod(lo / ulp, 2.0) == 0.0) ? lo : hi;
+  return x < 0 ? -r : r;
+}
+
+static void test_bf16_split() {
+  std::mt19937_64 rng(7);
+  std::uniform_real_distribution<double> mant(1.0, 2.0);
+  std::uniform_int_distribution<int> ex(-40, 40);
+  std::vector<float> xs = {1.0f, 1.0f + 0x1p-8f, 1.0f + 3 * 0x1p-8f, -1.0f - 0x1p-8f, 0.0f, 0x1p-20f * 1.2345f,
+                           0.63661977f, -0.21220659f};
+  for (int i = 0; i < 20000; ++i) {
+    const float x = (float)(std::ldexp(mant(rng), ex(rng)) * ((i & 1) ? -1.0 : 1.0));
+    xs.push_back(x);
+  }
+  for (float x : xs) {
+    uint16_t h, l;
+    bf16_split(x, &h, &l);
+    const double hv = bf16_value(h), lv = bf16_value(l);
+    CHECK(hv == bf_bf16_round(x), "hi of %a is %a, want %a", (double)x, hv, bf_bf16_round(x));
+    CHECK(lv == bf_bf16_round((double)x - hv), "lo of %a is %a, want %a", (double)x, lv, bf_bf16_round((double)x - hv));
+    CHECK(std::fabs((double)x - hv - lv) <= std::ldexp(std::fabs((double)x), -16), "pair of %a misses by %a",
+          (double)x, (double)x - hv - lv);
+  }
+  // ties go to the even significand
+  uint16_t h, l;
+  bf16_split(1.0f + 0x1p-8f, &h, &l);
+  CHECK(bf16_value(h) == 1.0f && bf16_value(l) == 0x1p-8f, "tie below");
+  bf16_split(1.0f + 3 * 0x1p-8f, &h, &l);
+  CHECK(bf16_value(h) == 1.0f + 0x1p-6f && bf16_value(l) == -0x1p-8f, "tie above");
+}
+
 int main() {
+  test_bf16_split();
   test_arith_and_halo();
   test_windows();
   test_up_plan();

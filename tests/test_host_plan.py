@@ -1,6 +1,7 @@
 """Host-only planning logic of the runtime (range arithmetic of the
 multi-rate resampling, interpolation hops, trigger windows, device-memory
-admission of serving banks, window readiness of a stream), compiled for the
+admission of serving banks, window readiness of a stream, the BF16 hi/lo
+split of the interpolation filters of the BF16 path), compiled for the
 CPU with the address and undefined-behaviour sanitizers and checked against
 brute force, a queue model and the invariants the runtime relies on
 (tests/host/test_plan.cpp).  The admission check is the host-side contract
