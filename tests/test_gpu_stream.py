@@ -82,6 +82,30 @@ def test_stream_equals_offline(sizes, use_graph):
         lloid.lloid_bank_destroy(h)
 
 
+@pytest.mark.parametrize("compute", ["bf16", "f32"])
+def test_stream_equals_offline_other_precisions(compute):
+    """The serving tables in the other operand types (BF16: FP32 low-rate
+    buffers interpolated with split-BF16 products; FP32: the plain path) give
+    the offline triggers bit for bit, signal consistency included."""
+    from paper_2410_16416_amd import lloid
+    wl = configs.mini_multirate(seconds=12, detectors=2, n_injections=2)
+    wl.bank.autocorr = bank_autocorrelation(wl.bank, 20)
+    h = lloid.bank_from_svd(ctx(), wl.bank, compute)
+    s = lloid.lloid_stream_create(ctx(), 1024, compute, n_detectors=2, min_rate_hz=64, window=(1, 4),
+                                  max_filter_s=8.0)
+    try:
+        slot, active = lloid.lloid_stream_admit(s, h)
+        assert active
+        got = canon(run_stream(lloid, s, wl.strains, [1024]))
+        want = offline(lloid, h, wl.strains, (1, 4), slot)
+        log(f"[stream {compute}] {len(got)} triggers")
+        assert len(got) == len(want) > 0
+        assert np.array_equal(got, want)
+    finally:
+        lloid.lloid_stream_destroy(s)
+        lloid.lloid_bank_destroy(h)
+
+
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_continuous_batching_admission_and_removal(use_graph):
     """Banks join while others run, one waits for budget and enters when a
