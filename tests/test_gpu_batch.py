@@ -128,7 +128,7 @@ def test_c3_shaped_banks_alone_equal_in_batch():
             lloid.lloid_bank_destroy(h)
 
 
-@pytest.mark.parametrize("compute", ["f16", "f32"])
+@pytest.mark.parametrize("compute", ["f16", "bf16", "f32"])
 def test_tile_variants_give_identical_results(compute):
     """Every compiled tile shape of the FIR and mixing kernels (including the
     FIR's Hankel fragment window) gives the same

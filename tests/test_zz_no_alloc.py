@@ -24,7 +24,7 @@ def _same(a, b, label):
         np.testing.assert_array_equal(getattr(a, k), getattr(b, k), err_msg=f"{label}: {k}")
 
 
-@pytest.mark.parametrize("compute", ["f16", "f32"])
+@pytest.mark.parametrize("compute", ["f16", "bf16", "f32"])
 def test_noalloc_equals_filter_on_two_calls(compute):
     from paper_2410_16416_amd import lloid
     bank = configs.multirate_c1_bank()
